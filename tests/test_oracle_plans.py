@@ -1,0 +1,250 @@
+"""Pins for the oracle's integer plans (CPU only).
+
+Each plan array is checked against a linear-scan brute force of its
+definition on tiny adversarial inputs, and each plan is shown to define a
+correct decomposition by evaluating A*x through it (integer values, so any
+order is exact) in a plain Python walk.
+"""
+import numpy as np
+import pytest
+
+import gen
+import oracle
+
+
+def _rp(lens):
+    rp = np.zeros(len(lens) + 1, dtype=np.int32)
+    rp[1:] = np.cumsum(lens)
+    return rp
+
+
+def _mat(lens, seed=0, ncols=None):
+    rng = np.random.default_rng(seed)
+    rp = _rp(lens)
+    n = len(lens)
+    ncols = ncols or max(n, max(lens) if lens else 1)
+    ci = np.concatenate([np.sort(rng.choice(ncols, size=l, replace=False)) for l in lens] + [np.zeros(0)])
+    v = rng.integers(-8, 9, int(rp[-1])).astype(np.float64)
+    return gen.CSR(n, ncols, rp, ci.astype(np.int32), v)
+
+
+ADVERSARIAL = {
+    "nnz_lt_T": [1, 2, 0, 3],
+    "nnz_multiple_T": [4] * 16,                       # 64 entries, T = 16
+    "one_row_3_tiles": [1, 50, 1],                    # row spans >= 3 tiles of 16
+    "empty_at_edges": [16, 0, 0, 16, 0, 16, 0],       # empty rows at tile edges
+    "trailing_empty": [5, 7, 0, 0, 0],
+    "leading_empty": [0, 0, 9, 9],
+    "all_empty": [0, 0, 0],
+    "n1": [33],
+    "mixed": [0, 3, 17, 0, 1, 1, 0, 40, 2, 0, 0, 16, 16, 1],
+}
+
+
+def brute_nnz(rp, P):
+    n = rp.size - 1
+    nnz = int(rp[-1])
+    b = [0]
+    for p in range(1, P):
+        t = (p * nnz) // P
+        r = 0
+        while r <= n and rp[r] < t:
+            r += 1
+        b.append(r)
+    b.append(n)
+    return np.array(b)
+
+
+@pytest.mark.parametrize("case", sorted(ADVERSARIAL))
+@pytest.mark.parametrize("T", [1, 3, 16, 1000])
+def test_plan_nnz_brute(case, T):
+    rp = _rp(ADVERSARIAL[case])
+    b = oracle.plan_nnz(rp, T)
+    P = b.size - 1
+    assert P == max(1, -(-int(rp[-1]) // T))
+    assert np.array_equal(b, brute_nnz(rp, P))
+    assert b[0] == 0 and b[-1] == rp.size - 1 and np.all(np.diff(b) >= 0)
+
+
+def brute_bss(rp, T):
+    n = rp.size - 1
+    nnz = int(rp[-1])
+    P = max(1, -(-nnz // T))
+    row_lo, tile_row, carry = [], [], []
+    for t in range(P):
+        e = t * T
+        row_lo.append(next((r for r in range(n + 1) if rp[r] >= e), n))
+        cand = [r for r in range(n + 1) if rp[r] <= e]
+        tr = max(cand) if cand else 0
+        tr = min(max(tr, 0), max(n - 1, 0))
+        tile_row.append(tr)
+        carry.append(tr if (n > 0 and rp[tr] < e) else -1)
+    row_lo.append(n)
+    tile_row.append(n)
+    return np.array(row_lo), np.array(tile_row), np.array(carry)
+
+
+@pytest.mark.parametrize("case", sorted(ADVERSARIAL))
+@pytest.mark.parametrize("T", [1, 4, 16, 1000])
+def test_plan_bss_brute(case, T):
+    rp = _rp(ADVERSARIAL[case])
+    got = oracle.plan_bss(rp, T)
+    want = brute_bss(rp, T)
+    for g, w in zip(got, want):
+        assert np.array_equal(g, w)
+
+
+def _eval_bss(A, x, T):
+    """Walk the BSS decomposition exactly as the plan defines it: each tile
+    sums its entries per row; a row's first tile writes y, later tiles send
+    their leading partial as a carry; carries are added in ascending tile
+    order; empty rows are written 0 by the tile holding their start."""
+    row_lo, tile_row, carry = oracle.plan_bss(A.rowptr, T)
+    P = carry.size
+    nnz = A.nnz
+    y = np.full(A.n, np.nan)
+    cval = np.zeros(P)
+    for t in range(P):
+        e0, e1 = t * T, min((t + 1) * T, nnz)
+        # rows starting in this tile
+        for r in range(row_lo[t], row_lo[t + 1]):
+            k0, k1 = A.rowptr[r], min(A.rowptr[r + 1], e1)
+            y[r] = sum(A.val[k] * x[A.colind[k]] for k in range(k0, k1))
+        if carry[t] >= 0:
+            r = carry[t]
+            k1 = min(A.rowptr[r + 1], e1)
+            cval[t] = sum(A.val[k] * x[A.colind[k]] for k in range(e0, k1))
+    for t in range(P):
+        if carry[t] >= 0:
+            y[carry[t]] += cval[t]
+    return y
+
+
+@pytest.mark.parametrize("case", sorted(ADVERSARIAL))
+@pytest.mark.parametrize("T", [1, 5, 16])
+def test_bss_decomposition_is_exact(case, T):
+    A = _mat(ADVERSARIAL[case], seed=3)
+    x = gen.int_vec(A.ncols, 4)
+    y, _ = oracle.spmv(A, x)
+    assert np.array_equal(_eval_bss(A, x, T), y)
+
+
+def _mat_sym(n, seed, band, p_empty=0.0):
+    rng = np.random.default_rng(seed)
+    rows, vals = [], []
+    for i in range(n):
+        lo = max(0, i - band)
+        cand = np.arange(lo, i)
+        keep = cand[rng.random(cand.size) < 0.5] if cand.size else cand
+        if rng.random() < p_empty:
+            keep = keep[:0]
+        cols = np.concatenate([keep, [i]]).astype(np.int32)
+        rows.append(cols)
+    lens = [c.size for c in rows]
+    rp = _rp(lens)
+    ci = np.concatenate(rows).astype(np.int32)
+    v = rng.integers(-8, 9, ci.size).astype(np.float64)
+    return gen.CSR(n, n, rp, ci, v, sym_lower=True)
+
+
+def brute_sym(A, T, Rmax, C):
+    rp, ci = A.rowptr, A.colind
+    P0 = max(1, -(-A.nnz // T))
+    b0 = brute_nnz(rp, P0)
+    b = []
+    for p in range(P0):
+        R = b0[p + 1] - b0[p]
+        k = max(1, -(-R // Rmax))
+        b.extend(int(b0[p] + (i * R) // k) for i in range(k))
+    b.append(A.n)
+    P = len(b) - 1
+    pairs = set()
+    for p in range(P):
+        for i in range(b[p], b[p + 1]):
+            for k in range(rp[i], rp[i + 1]):
+                if ci[k] < b[p]:
+                    pairs.add((int(ci[k]) // C, p))
+    order = sorted(pairs)
+    nblk = -(-A.n // C)
+    tm_ptr = np.zeros(nblk + 1, dtype=np.int64)
+    for c, _ in order:
+        tm_ptr[c + 1] += 1
+    tm_ptr = np.cumsum(tm_ptr)
+    tm_tile = np.array([p for _, p in order])
+    slot = {pc: s for s, pc in enumerate(order)}
+    per_tile = sorted((p, c) for c, p in order)
+    tile_ptr = np.zeros(P + 1, dtype=np.int64)
+    for p, _ in per_tile:
+        tile_ptr[p + 1] += 1
+    tile_ptr = np.cumsum(tile_ptr)
+    tile_blk = np.array([c for _, c in per_tile])
+    tile_slot = np.array([slot[(c, p)] for p, c in per_tile])
+    return dict(b=np.array(b), tm_ptr=tm_ptr, tm_tile=tm_tile, tile_ptr=tile_ptr, tile_blk=tile_blk,
+                tile_slot=tile_slot)
+
+
+SYM_CASES = [(60, 1, 5, 0.0), (80, 2, 20, 0.2), (200, 3, 70, 0.1), (1, 4, 1, 0.0), (33, 5, 0, 0.0)]
+
+
+@pytest.mark.parametrize("n,seed,band,pe", SYM_CASES)
+@pytest.mark.parametrize("T,Rmax,C", [(16, 8, 4), (40, 1000, 16), (7, 3, 1), (1000, 5, 64)])
+def test_plan_sym_brute(n, seed, band, pe, T, Rmax, C):
+    A = _mat_sym(n, seed, band, pe)
+    got = oracle.plan_sym(A, T, Rmax, C)
+    want = brute_sym(A, T, Rmax, C)
+    for key in want:
+        assert np.array_equal(got[key].astype(np.int64), want[key].astype(np.int64)), key
+
+
+def _eval_sym(A, x, plan, C):
+    """Walk the symmetric decomposition: each tile forms its rows' own sums
+    plus the transposed entries landing inside the tile; entries landing
+    below the tile go to the (tile, block) partial named by the touch map;
+    the reduction adds, block by block, the partials in the map's order."""
+    b = plan["b"]
+    P = b.size - 1
+    y = np.zeros(A.n)
+    nt = plan["tm_tile"].size
+    part = np.zeros((nt, C))
+    for p in range(P):
+        slots = {int(c): int(s) for c, s in zip(plan["tile_blk"][plan["tile_ptr"][p]:plan["tile_ptr"][p + 1]],
+                                                plan["tile_slot"][plan["tile_ptr"][p]:plan["tile_ptr"][p + 1]])}
+        for i in range(b[p], b[p + 1]):
+            for k in range(A.rowptr[i], A.rowptr[i + 1]):
+                j = int(A.colind[k])
+                y[i] += A.val[k] * x[j]
+                if j != i:
+                    if j >= b[p]:
+                        y[j] += A.val[k] * x[i]
+                    else:
+                        part[slots[j // C], j % C] += A.val[k] * x[i]
+    for c in range(plan["tm_ptr"].size - 1):
+        for s in range(plan["tm_ptr"][c], plan["tm_ptr"][c + 1]):
+            for jj in range(C):
+                j = c * C + jj
+                if j < A.n:
+                    y[j] += part[s, jj]
+    return y
+
+
+@pytest.mark.parametrize("n,seed,band,pe", SYM_CASES)
+def test_sym_decomposition_is_exact(n, seed, band, pe):
+    A = _mat_sym(n, seed, band, pe)
+    x = gen.int_vec(A.n, 8)
+    y, _ = oracle.spmv(A, x)
+    for T, Rmax, C in [(16, 8, 4), (9, 4, 2)]:
+        plan = oracle.plan_sym(A, T, Rmax, C)
+        assert np.array_equal(_eval_sym(A, x, plan, C), y)
+
+
+def test_plan_sym_stencil_touch_is_sparse():
+    """On a 3D stencil only a few column blocks per tile are touched: the
+    zero-element omission skips almost the whole reduction vector."""
+    A = gen.stencil27(16, lower=True)
+    C = 64
+    plan = oracle.plan_sym(A, 2048, 512, C)
+    P = plan["b"].size - 1
+    nblk = -(-A.n // C)
+    per_tile = np.diff(plan["tile_ptr"])
+    assert per_tile.max() <= 12
+    assert plan["tm_tile"].size < 0.2 * P * nblk
