@@ -1,0 +1,626 @@
+// Batched independent systems: the block-diagonal concatenation of many
+// CSR matrices, one persistent SpMV launch over all of them, and BiCGStab
+// (van der Vorst's form, the paper's second linear solver) advancing every
+// system at once.  One iteration is five kernels; it is captured once in a
+// HIP graph and replayed.  Per-system scalars live on the device; a system
+// that converges (or breaks down) is masked from then on, and tiles whose
+// systems are all inactive skip their SpMV work.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <vector>
+
+#include "segchunk.h"
+
+namespace {
+
+using xab::Seg;
+constexpr int kNT = 256;
+constexpr int kChunkJ = 8;
+constexpr int kTileNnz = 2048;
+
+template <class YT, class AT>
+struct StoreSink {
+    YT *y;
+    __device__ void row_done(int32_t r, AT v) { y[r] = (YT)v; }
+    __device__ void empty_row(int32_t r) { y[r] = YT(0); }
+    template <class VT>
+    __device__ void entry(int32_t, int32_t, VT) {}
+};
+
+__device__ __forceinline__ int32_t lb_range(const int32_t *rowptr, int32_t lo, int32_t hi, int64_t target) {
+    while (lo < hi) {
+        int32_t mid = lo + (hi - lo) / 2;
+        if (rowptr[mid] >= target) hi = mid;
+        else lo = mid + 1;
+    }
+    return lo;
+}
+
+// Persistent nnz-split SpMV: the grid walks the tiles [b[t], b[t+1]) of the
+// global matrix; a tile whose first and last systems are inactive (and
+// which spans at most two systems) is skipped.
+template <class T>
+__global__ __launch_bounds__(kNT) void k_batch_spmv(const int32_t *__restrict__ rowptr,
+                                                    const int32_t *__restrict__ colind, const T *__restrict__ val,
+                                                    const T *__restrict__ x, T *__restrict__ y,
+                                                    const int32_t *__restrict__ b, int64_t P,
+                                                    const int32_t *__restrict__ sys_of_row,
+                                                    const int *__restrict__ active) {
+    constexpr int CH = kNT * kChunkJ;
+    __shared__ int32_t head_row[CH];
+    __shared__ Seg<double> wave_tot[kNT / xab::kWave];
+    StoreSink<T, double> sink{y};
+    for (int64_t t = blockIdx.x; t < P; t += gridDim.x) {
+        const int32_t r0 = b[t], r1 = b[t + 1];
+        if (r0 >= r1) continue;
+        if (active) {
+            int32_t s0 = sys_of_row[r0], s1 = sys_of_row[r1 - 1];
+            if (s1 - s0 <= 1 && !active[s0] && !active[s1]) continue;
+        }
+        const int64_t s = rowptr[r0], e = rowptr[r1];
+        Seg<double> seed{0, 0.0, -1};
+        int32_t rlo = r0;
+        int64_t A = s - (s % CH);
+        for (;;) {
+            const int64_t Aend = A + CH;
+            const bool last = Aend >= e;
+            const int32_t rhi = last ? r1 : lb_range(rowptr, rlo, r1, Aend);
+            __syncthreads();
+            xab::clear_heads<kNT, kChunkJ>(head_row);
+            __syncthreads();
+            xab::mark_heads<kNT>(rowptr, rlo, rhi, A, head_row, sink);
+            __syncthreads();
+            xab::ChunkResult<double> res = xab::seg_chunk<kNT, kChunkJ, T, T, double>(
+                A, s > A ? s : A, e < Aend ? e : Aend, colind, val, x, head_row, seed, wave_tot, sink);
+            seed = res.state;
+            rlo = rhi;
+            if (last) break;
+            A = Aend;
+        }
+        if (threadIdx.x == 0 && seed.f) y[seed.r] = (T)seed.v;
+    }
+}
+
+__device__ __forceinline__ double bsum(double v, double *sh) {
+    v = xab::wave_sum(v);
+    const int w = threadIdx.x / xab::kWave;
+    if (threadIdx.x % xab::kWave == 0) sh[w] = v;
+    __syncthreads();
+    double t = 0.0;
+#pragma unroll
+    for (int i = 0; i < kNT / xab::kWave; ++i) t += sh[i];
+    __syncthreads();
+    return t;
+}
+
+// Per-system solver state (device).
+struct SysState {
+    double rho_prev, alpha, omega, bnorm, res;
+    int iters, status;  // status: 0 converged, 1 running/not converged, 2 breakdown
+};
+
+// ||b||, r = b - A x0 (A x0 given in t), rhat = r, p = v = 0, scalars reset.
+template <class T>
+__global__ __launch_bounds__(kNT) void k_bi_init(const int64_t *__restrict__ row_off, const T *__restrict__ bvec,
+                                                 const T *__restrict__ ax, T *__restrict__ r, T *__restrict__ rh,
+                                                 T *__restrict__ p, T *__restrict__ v, SysState *__restrict__ st,
+                                                 int *__restrict__ active, double tol, int *__restrict__ n_active) {
+    __shared__ double sh[kNT / xab::kWave];
+    const int k = blockIdx.x;
+    const int64_t r0 = row_off[k], r1 = row_off[k + 1];
+    double bb = 0.0, rr = 0.0;
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += kNT) {
+        double bi = (double)bvec[i];
+        T ri = (T)(bi - (double)ax[i]);
+        r[i] = ri;
+        rh[i] = ri;
+        p[i] = T(0);
+        v[i] = T(0);
+        bb += bi * bi;
+        rr += (double)ri * (double)ri;
+    }
+    bb = bsum(bb, sh);
+    rr = bsum(rr, sh);
+    if (threadIdx.x == 0) {
+        SysState s;
+        s.rho_prev = 1.0;
+        s.alpha = 1.0;
+        s.omega = 1.0;
+        s.bnorm = bb > 0.0 ? sqrt(bb) : 1.0;
+        s.res = sqrt(rr) / s.bnorm;
+        s.iters = 0;
+        s.status = s.res <= tol ? 0 : 1;
+        st[k] = s;
+        active[k] = s.status == 1;
+        if (s.status == 1) atomicAdd(n_active, 1);
+    }
+}
+
+// rho = <rhat, r>, beta, p = r + beta (p - omega v), phat = M^-1 p
+template <class T>
+__global__ __launch_bounds__(kNT) void k_bi_p(const int64_t *__restrict__ row_off, const T *__restrict__ r,
+                                              const T *__restrict__ rh, T *__restrict__ p, const T *__restrict__ v,
+                                              T *__restrict__ ph, const T *__restrict__ d, SysState *__restrict__ st,
+                                              int *__restrict__ active, double *__restrict__ rho_out,
+                                              int *__restrict__ n_active) {
+    __shared__ double sh[kNT / xab::kWave];
+    __shared__ double beta_s;
+    const int k = blockIdx.x;
+    if (!active[k]) return;
+    const int64_t r0 = row_off[k], r1 = row_off[k + 1];
+    double a = 0.0;
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += kNT) a += (double)rh[i] * (double)r[i];
+    const double rho = bsum(a, sh);
+    if (threadIdx.x == 0) {
+        SysState s = st[k];
+        if (rho == 0.0) {
+            s.status = 2;
+            st[k] = s;
+            active[k] = 0;
+            atomicSub(n_active, 1);
+            beta_s = NAN;
+        } else {
+            beta_s = (rho / s.rho_prev) * (s.alpha / s.omega);
+            rho_out[k] = rho;
+        }
+    }
+    __syncthreads();
+    const double beta = beta_s;
+    if (beta != beta) return;
+    const double om = st[k].omega;
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += kNT) {
+        T pi = (T)((double)r[i] + beta * ((double)p[i] - om * (double)v[i]));
+        p[i] = pi;
+        ph[i] = d ? (T)((double)pi / (double)d[i]) : pi;
+    }
+}
+
+// alpha = rho / <rhat, v>, s = r - alpha v, ||s||; early exit when ||s||
+// meets tol (x += alpha phat); else shat = M^-1 s
+template <class T>
+__global__ __launch_bounds__(kNT) void k_bi_s(const int64_t *__restrict__ row_off, const T *__restrict__ r,
+                                              const T *__restrict__ rh, const T *__restrict__ v, T *__restrict__ s,
+                                              T *__restrict__ sh_vec, const T *__restrict__ ph, T *__restrict__ x,
+                                              const T *__restrict__ d, SysState *__restrict__ st,
+                                              int *__restrict__ active, const double *__restrict__ rho_in, double tol,
+                                              int *__restrict__ n_active) {
+    __shared__ double sh[kNT / xab::kWave];
+    __shared__ double alpha_s;
+    __shared__ int done_s;
+    const int k = blockIdx.x;
+    if (!active[k]) return;
+    const int64_t r0 = row_off[k], r1 = row_off[k + 1];
+    double a = 0.0;
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += kNT) a += (double)rh[i] * (double)v[i];
+    const double rv = bsum(a, sh);
+    if (threadIdx.x == 0) {
+        if (rv == 0.0) {
+            SysState q = st[k];
+            q.status = 2;
+            st[k] = q;
+            active[k] = 0;
+            atomicSub(n_active, 1);
+            alpha_s = NAN;
+        } else {
+            alpha_s = rho_in[k] / rv;
+        }
+    }
+    __syncthreads();
+    const double alpha = alpha_s;
+    if (alpha != alpha) return;
+    double ss = 0.0;
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += kNT) {
+        T si = (T)((double)r[i] - alpha * (double)v[i]);
+        s[i] = si;
+        ss += (double)si * (double)si;
+    }
+    ss = bsum(ss, sh);
+    if (threadIdx.x == 0) {
+        SysState q = st[k];
+        q.alpha = alpha;
+        double res = sqrt(ss) / q.bnorm;
+        done_s = res <= tol;
+        if (done_s) {
+            q.res = res;
+            q.iters += 1;
+            q.status = 0;
+            active[k] = 0;
+            atomicSub(n_active, 1);
+        }
+        st[k] = q;
+    }
+    __syncthreads();
+    if (done_s) {
+        for (int64_t i = r0 + threadIdx.x; i < r1; i += kNT) x[i] = (T)((double)x[i] + alpha * (double)ph[i]);
+        return;
+    }
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += kNT) sh_vec[i] = d ? (T)((double)s[i] / (double)d[i]) : s[i];
+}
+
+// omega = <t, s> / <t, t>, x += alpha phat + omega shat, r = s - omega t,
+// ||r|| -> convergence
+template <class T>
+__global__ __launch_bounds__(kNT) void k_bi_x(const int64_t *__restrict__ row_off, const T *__restrict__ s,
+                                              const T *__restrict__ t, const T *__restrict__ ph,
+                                              const T *__restrict__ shv, T *__restrict__ x, T *__restrict__ r,
+                                              SysState *__restrict__ st, int *__restrict__ active,
+                                              const double *__restrict__ rho_in, double tol, int64_t maxiter,
+                                              int *__restrict__ n_active) {
+    __shared__ double sh[kNT / xab::kWave];
+    __shared__ double om_s;
+    const int k = blockIdx.x;
+    if (!active[k]) return;
+    const int64_t r0 = row_off[k], r1 = row_off[k + 1];
+    double ts = 0.0, tt = 0.0;
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += kNT) {
+        double ti = (double)t[i];
+        ts += ti * (double)s[i];
+        tt += ti * ti;
+    }
+    ts = bsum(ts, sh);
+    tt = bsum(tt, sh);
+    if (threadIdx.x == 0) om_s = tt != 0.0 ? ts / tt : 0.0;
+    __syncthreads();
+    const double om = om_s;
+    const double al = st[k].alpha;
+    double rr = 0.0;
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += kNT) {
+        x[i] = (T)((double)x[i] + al * (double)ph[i] + om * (double)shv[i]);
+        T ri = (T)((double)s[i] - om * (double)t[i]);
+        r[i] = ri;
+        rr += (double)ri * (double)ri;
+    }
+    rr = bsum(rr, sh);
+    if (threadIdx.x == 0) {
+        SysState q = st[k];
+        q.iters += 1;
+        q.omega = om;
+        q.rho_prev = rho_in[k];
+        q.res = sqrt(rr) / q.bnorm;
+        bool stop = false;
+        if (q.res <= tol) {
+            q.status = 0;
+            stop = true;
+        } else if (om == 0.0) {
+            q.status = 2;
+            stop = true;
+        } else if (q.iters >= maxiter) {
+            stop = true;
+        }
+        st[k] = q;
+        if (stop) {
+            active[k] = 0;
+            atomicSub(n_active, 1);
+        }
+    }
+}
+
+// true residual per system: res[k] = ||b - A x||_k / ||b||_k (A x given)
+template <class T>
+__global__ __launch_bounds__(kNT) void k_bi_true(const int64_t *__restrict__ row_off, const T *__restrict__ bvec,
+                                                 const T *__restrict__ ax, const SysState *__restrict__ st,
+                                                 double *__restrict__ out) {
+    __shared__ double sh[kNT / xab::kWave];
+    const int k = blockIdx.x;
+    const int64_t r0 = row_off[k], r1 = row_off[k + 1];
+    double a = 0.0;
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += kNT) {
+        double e = (double)bvec[i] - (double)ax[i];
+        a += e * e;
+    }
+    a = bsum(a, sh);
+    if (threadIdx.x == 0) out[k] = sqrt(a) / st[k].bnorm;
+}
+
+// system index of every row; columns of system k inside its row range
+__global__ void k_sys_of_row(const int64_t *__restrict__ row_off, int32_t nsys, int32_t *__restrict__ sys) {
+    const int k = blockIdx.x;
+    if (k >= nsys) return;
+    for (int64_t i = row_off[k] + threadIdx.x; i < row_off[k + 1]; i += blockDim.x) sys[i] = k;
+}
+
+__global__ void k_check_blockdiag(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colind,
+                                  const int64_t *__restrict__ row_off, const int32_t *__restrict__ sys, int64_t n,
+                                  int *__restrict__ flag) {
+    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    int k = sys[r];
+    int64_t lo = row_off[k], hi = row_off[k + 1];
+    for (int64_t q = rowptr[r]; q < rowptr[r + 1]; ++q)
+        if (colind[q] < lo || colind[q] >= hi) {
+            atomicOr(flag, 1);
+            break;
+        }
+}
+
+template <class T>
+__global__ void k_diag_b(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colind,
+                         const T *__restrict__ val, int64_t n, T *__restrict__ d) {
+    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    double a = 0.0;
+    for (int64_t k = rowptr[r]; k < rowptr[r + 1]; ++k)
+        if (colind[k] == r) a += (double)val[k];
+    d[r] = a != 0.0 ? (T)a : T(1);
+}
+
+__global__ void k_zero_int(int *p) {
+    if (threadIdx.x == 0) *p = 0;
+}
+
+__global__ void k_split_nnz_b(const int32_t *rowptr, int64_t n, int64_t nnz, int64_t P, int32_t *b) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p > P) return;
+    if (p == 0) { b[0] = 0; return; }
+    if (p == P) { b[P] = (int32_t)n; return; }
+    int64_t target = (p * nnz) / P;
+    int64_t lo = 0, hi = n + 1;
+    while (lo < hi) {
+        int64_t mid = (lo + hi) / 2;
+        if (rowptr[mid] >= target) hi = mid;
+        else lo = mid + 1;
+    }
+    b[p] = (int32_t)lo;
+}
+
+unsigned grid_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+int persistent_grid() {
+    static int g = 0;
+    if (!g) {
+        int dev = 0, cu = 256;
+        (void)hipGetDevice(&dev);
+        if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cu = 256;
+        g = cu * 8;
+    }
+    return g;
+}
+
+template <class T>
+int batch_spmv_t(xab_ctx *ctx, const xab_batch *B, const T *x, T *y, const int *active, hipStream_t st) {
+    hipLaunchKernelGGL((k_batch_spmv<T>), dim3((unsigned)std::min<int64_t>(B->P, persistent_grid())), dim3(kNT), 0, st,
+                       B->rowptr, B->colind, (const T *)B->val, x, y, B->b, B->P, B->d_sys_of_row, active);
+    XAB_LAUNCH_CHECK(ctx, "k_batch_spmv");
+    return XAB_OK;
+}
+
+template <class T>
+int bicgstab_t(xab_ctx *ctx, const xab_batch *B, const T *bvec, T *x, const xab_krylov_opts *o, xab_krylov_info *hinfo,
+               xab_krylov_info *all) {
+    const int64_t n = B->n;
+    const int ns = B->nsys;
+    auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+    const size_t vb = al(sizeof(T) * (size_t)n);
+    size_t off_st = 10 * vb;
+    size_t off_rho = off_st + al(sizeof(SysState) * ns);
+    size_t off_act = off_rho + al(sizeof(double) * ns);
+    size_t off_cnt = off_act + al(sizeof(int) * ns);
+    size_t off_res = off_cnt + 256;
+    size_t total = off_res + al(sizeof(double) * ns);
+    char *w = (char *)xab_dalloc(ctx, total);
+    if (!w) return xab_fail(ctx, XAB_E_NOMEM, "BiCGStab workspace");
+    T *r = (T *)w, *rh = (T *)(w + vb), *p = (T *)(w + 2 * vb), *v = (T *)(w + 3 * vb), *ph = (T *)(w + 4 * vb);
+    T *s = (T *)(w + 5 * vb), *shv = (T *)(w + 6 * vb), *t = (T *)(w + 7 * vb), *d = (T *)(w + 8 * vb);
+    T *ax = (T *)(w + 9 * vb);
+    SysState *stt = (SysState *)(w + off_st);
+    double *rho = (double *)(w + off_rho);
+    int *active = (int *)(w + off_act);
+    int *n_active = (int *)(w + off_cnt);
+    double *res = (double *)(w + off_res);
+    hipStream_t st = ctx->stream;
+    hipStream_t gs = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    auto cleanup = [&](int code) {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (gs) {
+            (void)hipStreamSynchronize(gs);
+            (void)hipStreamDestroy(gs);
+        }
+        (void)hipStreamSynchronize(st);
+        xab_dfree(ctx, w);
+        return code;
+    };
+    const bool jac = o->precond == XAB_PRECOND_JACOBI;
+    const double tol = o->tol;
+    const int64_t maxiter = o->maxiter > 0 ? o->maxiter : 10000;
+    auto t0 = std::chrono::steady_clock::now();
+    int sres;
+    if (jac) hipLaunchKernelGGL((k_diag_b<T>), dim3(grid_for(n, 256)), dim3(256), 0, st, B->rowptr, B->colind,
+                                (const T *)B->val, n, d);
+    hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, st, n_active);
+    if ((sres = batch_spmv_t<T>(ctx, B, x, ax, nullptr, st)) != XAB_OK) return cleanup(sres);
+    hipLaunchKernelGGL((k_bi_init<T>), dim3(ns), dim3(kNT), 0, st, B->d_row_off, bvec, ax, r, rh, p, v, stt, active, tol,
+                       n_active);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return cleanup(xab_hip_check(ctx, e, "BiCGStab init"));
+    const T *dd = jac ? d : nullptr;
+    // one iteration over all systems
+    auto enqueue_iter = [&](hipStream_t q) {
+        hipLaunchKernelGGL((k_bi_p<T>), dim3(ns), dim3(kNT), 0, q, B->d_row_off, r, rh, p, v, ph, dd, stt, active, rho,
+                           n_active);
+        hipLaunchKernelGGL((k_batch_spmv<T>), dim3((unsigned)std::min<int64_t>(B->P, persistent_grid())), dim3(kNT), 0, q,
+                           B->rowptr, B->colind, (const T *)B->val, ph, v, B->b, B->P, B->d_sys_of_row, active);
+        hipLaunchKernelGGL((k_bi_s<T>), dim3(ns), dim3(kNT), 0, q, B->d_row_off, r, rh, v, s, shv, ph, x, dd, stt, active,
+                           rho, tol, n_active);
+        hipLaunchKernelGGL((k_batch_spmv<T>), dim3((unsigned)std::min<int64_t>(B->P, persistent_grid())), dim3(kNT), 0, q,
+                           B->rowptr, B->colind, (const T *)B->val, shv, t, B->b, B->P, B->d_sys_of_row, active);
+        hipLaunchKernelGGL((k_bi_x<T>), dim3(ns), dim3(kNT), 0, q, B->d_row_off, s, t, ph, shv, x, r, stt, active, rho, tol,
+                           maxiter, n_active);
+    };
+    const int every = o->check_every > 0 ? o->check_every : 8;
+    hipEvent_t ev = nullptr;
+    if (o->graph) {
+        // capture on a library stream (the caller's may be the legacy default
+        // stream, which cannot be captured), ordered after the caller's work
+        e = hipStreamCreateWithFlags(&gs, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventRecord(ev, st);
+        if (e == hipSuccess) e = hipStreamWaitEvent(gs, ev, 0);
+        if (e == hipSuccess) e = hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            for (int i = 0; i < every; ++i) enqueue_iter(gs);
+            e = hipStreamEndCapture(gs, &graph);
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            if (ev) (void)hipEventDestroy(ev);
+            return cleanup(xab_hip_check(ctx, e, "BiCGStab graph"));
+        }
+    }
+    hipStream_t run = o->graph ? gs : st;
+    int64_t done_iters = 0;
+    int h_active = 1;
+    while (done_iters < maxiter) {
+        if (o->graph) e = hipGraphLaunch(exec, gs);
+        else {
+            for (int i = 0; i < every; ++i) enqueue_iter(st);
+            e = hipGetLastError();
+        }
+        if (e != hipSuccess) break;
+        done_iters += every;
+        e = hipMemcpyAsync(&h_active, n_active, sizeof(int), hipMemcpyDeviceToHost, run);
+        if (e == hipSuccess) e = hipStreamSynchronize(run);
+        if (e != hipSuccess || h_active <= 0) break;
+    }
+    if (ev) (void)hipEventDestroy(ev);
+    if (e != hipSuccess) return cleanup(xab_hip_check(ctx, e, "BiCGStab iterations"));
+    if (o->graph) {
+        e = hipStreamSynchronize(gs);
+        if (e != hipSuccess) return cleanup(xab_hip_check(ctx, e, "BiCGStab sync"));
+    }
+    // true residuals
+    if ((sres = batch_spmv_t<T>(ctx, B, x, ax, nullptr, st)) != XAB_OK) return cleanup(sres);
+    hipLaunchKernelGGL((k_bi_true<T>), dim3(ns), dim3(kNT), 0, st, B->d_row_off, bvec, ax, stt, res);
+    std::vector<SysState> hs(ns);
+    std::vector<double> hr(ns);
+    e = hipMemcpyAsync(hs.data(), stt, sizeof(SysState) * ns, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(hr.data(), res, sizeof(double) * ns, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return cleanup(xab_hip_check(ctx, e, "BiCGStab results"));
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    int agg = XAB_OK;
+    int64_t maxit = 0;
+    double worst = 0.0;
+    for (int k = 0; k < ns; ++k) {
+        int sk = hs[k].status == 0 ? XAB_OK : (hs[k].status == 2 ? XAB_BREAKDOWN : XAB_NOT_CONVERGED);
+        if (sk == XAB_BREAKDOWN) agg = XAB_BREAKDOWN;
+        else if (sk == XAB_NOT_CONVERGED && agg == XAB_OK) agg = XAB_NOT_CONVERGED;
+        maxit = std::max<int64_t>(maxit, hs[k].iters);
+        worst = std::max(worst, hr[k]);
+        if (hinfo) {
+            hinfo[k] = xab_krylov_info{};
+            hinfo[k].iters = hs[k].iters;
+            hinfo[k].true_relres = hr[k];
+            hinfo[k].seconds = secs;
+            hinfo[k].status = sk;
+        }
+    }
+    if (all) {
+        *all = xab_krylov_info{};
+        all->iters = maxit;
+        all->restarts = done_iters;
+        all->true_relres = worst;
+        all->seconds = secs;
+        all->status = agg;
+    }
+    return cleanup(agg);
+}
+
+}  // namespace
+
+extern "C" {
+
+int xab_batch_csr(xab_ctx *ctx, int32_t nsys, const int64_t *h_row_off, const int64_t *h_nnz_off,
+                  const int32_t *d_rowptr, const int32_t *d_colind, const void *d_val, xab_dtype vt, uint32_t flags,
+                  xab_batch **out) {
+    if (!ctx || !out || !h_row_off || !h_nnz_off) return XAB_E_NULL;
+    *out = nullptr;
+    if (nsys < 1) return xab_fail(ctx, XAB_E_SHAPE, "nsys = %d", nsys);
+    if (vt != XAB_F64 && vt != XAB_F32) return xab_fail(ctx, XAB_E_DTYPE, "value type");
+    if (h_row_off[0] != 0 || h_nnz_off[0] != 0) return xab_fail(ctx, XAB_E_SHAPE, "offsets must start at 0");
+    for (int k = 0; k < nsys; ++k)
+        if (h_row_off[k + 1] < h_row_off[k] || h_nnz_off[k + 1] < h_nnz_off[k])
+            return xab_fail(ctx, XAB_E_SHAPE, "offsets must be monotone");
+    const int64_t n = h_row_off[nsys], nnz = h_nnz_off[nsys];
+    if (n >= (int64_t(1) << 31) || nnz >= (int64_t(1) << 31)) return xab_fail(ctx, XAB_E_SHAPE, "batch too large");
+    xab_matrix *A = nullptr;
+    int s = xab_matrix_csr(ctx, (int32_t)n, (int32_t)n, nnz, d_rowptr, d_colind, d_val, vt, flags & XAB_TRUST_INPUT, &A);
+    if (s != XAB_OK) return s;
+    xab_batch *B = new xab_batch();
+    B->ctx = ctx;
+    B->nsys = nsys;
+    B->n = n;
+    B->nnz = nnz;
+    B->row_off.assign(h_row_off, h_row_off + nsys + 1);
+    B->nnz_off.assign(h_nnz_off, h_nnz_off + nsys + 1);
+    B->rowptr = d_rowptr;
+    B->colind = d_colind;
+    B->val = d_val;
+    B->vt = vt;
+    xab_matrix_destroy(A);
+    B->P = std::max<int64_t>(1, (nnz + kTileNnz - 1) / kTileNnz);
+    B->b = (int32_t *)xab_dalloc(ctx, sizeof(int32_t) * (B->P + 1));
+    B->d_sys_of_row = (int32_t *)xab_dalloc(ctx, sizeof(int32_t) * (n > 0 ? n : 1));
+    B->d_row_off = (int64_t *)xab_dalloc(ctx, sizeof(int64_t) * (nsys + 1));
+    if (!B->b || !B->d_sys_of_row || !B->d_row_off) {
+        xab_batch_destroy(B);
+        return xab_fail(ctx, XAB_E_NOMEM, "batch plan");
+    }
+    hipStream_t st = ctx->stream;
+    hipError_t e = hipMemcpyAsync(B->d_row_off, h_row_off, sizeof(int64_t) * (nsys + 1), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_split_nnz_b, dim3(grid_for(B->P + 1, 256)), dim3(256), 0, st, d_rowptr, n, nnz, B->P, B->b);
+        hipLaunchKernelGGL(k_sys_of_row, dim3(nsys), dim3(256), 0, st, B->d_row_off, nsys, B->d_sys_of_row);
+        if (!(flags & XAB_TRUST_INPUT) && n > 0) {
+            hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, st, ctx->d_flag);
+            hipLaunchKernelGGL(k_check_blockdiag, dim3(grid_for(n, 256)), dim3(256), 0, st, d_rowptr, d_colind,
+                               B->d_row_off, B->d_sys_of_row, n, ctx->d_flag);
+        }
+        e = hipGetLastError();
+    }
+    int hflag = 0;
+    if (e == hipSuccess && !(flags & XAB_TRUST_INPUT))
+        e = hipMemcpyAsync(&hflag, ctx->d_flag, sizeof(int), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        xab_batch_destroy(B);
+        return xab_hip_check(ctx, e, "batch setup");
+    }
+    if (hflag) {
+        xab_batch_destroy(B);
+        return xab_fail(ctx, XAB_E_STRUCT, "a system has columns outside its own rows");
+    }
+    *out = B;
+    return XAB_OK;
+}
+
+void xab_batch_destroy(xab_batch *B) {
+    if (!B) return;
+    (void)hipStreamSynchronize(B->ctx->stream);
+    xab_dfree(B->ctx, B->b);
+    xab_dfree(B->ctx, B->d_sys_of_row);
+    xab_dfree(B->ctx, B->d_row_off);
+    delete B;
+}
+
+int xab_batch_spmv(xab_ctx *ctx, const xab_batch *B, const void *d_x, void *d_y) {
+    if (!ctx || !B || !d_x || !d_y) return XAB_E_NULL;
+    if (d_x == d_y) return xab_fail(ctx, XAB_E_ALIAS, "x and y alias");
+    if (B->vt == XAB_F64) return batch_spmv_t<double>(ctx, B, (const double *)d_x, (double *)d_y, nullptr, ctx->stream);
+    return batch_spmv_t<float>(ctx, B, (const float *)d_x, (float *)d_y, nullptr, ctx->stream);
+}
+
+int xab_bicgstab(xab_ctx *ctx, const xab_batch *B, const void *d_b, void *d_x, const xab_krylov_opts *opts,
+                 xab_krylov_info *h_info, xab_krylov_info *all) {
+    if (!ctx || !B || !d_b || !d_x || !opts) return XAB_E_NULL;
+    if (d_b == d_x) return xab_fail(ctx, XAB_E_ALIAS, "b and x alias");
+    XAB_HIP(ctx, hipSetDevice(ctx->device));
+    if (B->vt == XAB_F64)
+        return bicgstab_t<double>(ctx, B, (const double *)d_b, (double *)d_x, opts, h_info, all);
+    return bicgstab_t<float>(ctx, B, (const float *)d_b, (float *)d_x, opts, h_info, all);
+}
+
+}  // extern "C"

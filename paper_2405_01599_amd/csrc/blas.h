@@ -1,0 +1,31 @@
+// Level-1 / Gram-Schmidt kernels of the Krylov drivers (host wrappers).
+#pragma once
+#include "internal.h"
+
+namespace xab {
+
+constexpr int kPartLd = 72;    // stride of one workgroup's partial sums (>= 64 vectors + norm)
+constexpr int kRedBlocks = 512; // workgroups of the reduction kernels
+
+template <class T>
+int mdot(xab_ctx *ctx, const T *V, int64_t ldv, int nv, const T *w, int64_t n, double *part, int nb,
+         const int *gate);
+template <class T>
+int update_norm(xab_ctx *ctx, const T *V, int64_t ldv, int nv, const double *h, T *w, int64_t n, double *part,
+                int nb, const int *gate);
+int reduce_parts(xab_ctx *ctx, const double *part, int nb, int ldp, int m, double *out, int add, const int *gate);
+int dgks_gate(xab_ctx *ctx, const double *wn2, const double *wpn2, double eta, int *gate);
+template <class T>
+int scale_precond(xab_ctx *ctx, const T *w, const double *nrm2, T *v, T *z, const T *d, int64_t n);
+template <class TS, class T>
+int scale_from(xab_ctx *ctx, const TS *r, double scale, T *v, T *z, const T *d, int64_t n);
+int residual(xab_ctx *ctx, const double *b, double *r, int64_t n, double *part, int nb);
+template <class T>
+int combine(xab_ctx *ctx, const T *V, int64_t ldv, int k, const double *y, double scale, const T *d, double *x,
+            int64_t n);
+template <class T>
+int copy_cast(xab_ctx *ctx, const double *s, T *d, int64_t n);
+
+__global__ void k_reduce_parts(const double *part, int nb, int ldp, int m, double *out, int add, const int *gate);
+
+}  // namespace xab

@@ -1,0 +1,325 @@
+// Level-1 kernels of the Krylov drivers.  Every reduction is two-stage and
+// fixed-order (per-workgroup partials, then one ordered sum), so results do
+// not depend on scheduling.  Basis vectors may be FP64 or FP32; inner
+// products always accumulate in FP64.
+#include "blas.h"
+
+namespace xab {
+namespace {
+
+constexpr int kNT = 256;
+
+__device__ __forceinline__ double block_sum(double v, double *sh) {
+    v = wave_sum(v);
+    const int w = threadIdx.x / kWave;
+    if (threadIdx.x % kWave == 0) sh[w] = v;
+    __syncthreads();
+    double t = 0.0;
+#pragma unroll
+    for (int i = 0; i < kNT / kWave; ++i) t += sh[i];
+    __syncthreads();
+    return t;
+}
+
+// part[b * ldp + i] = sum over this workgroup's rows of V_i[r] * w[r]
+// (i < nv), part[b * ldp + nv] = sum of w[r]^2.  Rows are dealt in
+// contiguous chunks of 256 to the workgroups.
+template <class T, int NV>
+__global__ __launch_bounds__(kNT) void k_mdot(const T *__restrict__ V, int64_t ldv, int nv, const T *__restrict__ w,
+                                              int64_t n, double *__restrict__ part, int ldp) {
+    __shared__ double sh[kNT / kWave];
+    double acc[NV + 1];
+#pragma unroll
+    for (int i = 0; i <= NV; ++i) acc[i] = 0.0;
+    for (int64_t r = (int64_t)blockIdx.x * kNT + threadIdx.x; r < n; r += (int64_t)gridDim.x * kNT) {
+        const double wr = (double)w[r];
+        acc[NV] += wr * wr;
+#pragma unroll
+        for (int i = 0; i < NV; ++i)
+            if (i < nv) acc[i] += (double)V[i * ldv + r] * wr;
+    }
+    for (int i = 0; i < nv; ++i) {
+        double t = 0.0;
+#pragma unroll
+        for (int q = 0; q < NV; ++q)
+            if (q == i) t = acc[q];
+        t = block_sum(t, sh);
+        if (threadIdx.x == 0) part[(int64_t)blockIdx.x * ldp + i] = t;
+    }
+    double t = block_sum(acc[NV], sh);
+    if (threadIdx.x == 0) part[(int64_t)blockIdx.x * ldp + nv] = t;
+}
+
+// w -= sum_i h[i] V_i (i < nv); part[b] = sum of the new w^2.  When `gate`
+// is given and *gate == 0 the kernel does nothing (the conditional second
+// Gram-Schmidt pass was not needed).
+template <class T, int NV>
+__global__ __launch_bounds__(kNT) void k_update_norm(const T *__restrict__ V, int64_t ldv, int nv,
+                                                     const double *__restrict__ h, T *__restrict__ w, int64_t n,
+                                                     double *__restrict__ part, const int *__restrict__ gate) {
+    __shared__ double sh[kNT / kWave];
+    if (gate && *gate == 0) return;
+    double hh[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) hh[i] = i < nv ? h[i] : 0.0;
+    double acc = 0.0;
+    for (int64_t r = (int64_t)blockIdx.x * kNT + threadIdx.x; r < n; r += (int64_t)gridDim.x * kNT) {
+        double a = (double)w[r];
+#pragma unroll
+        for (int i = 0; i < NV; ++i)
+            if (i < nv) a -= hh[i] * (double)V[i * ldv + r];
+        const T at = (T)a;
+        w[r] = at;
+        acc += (double)at * (double)at;
+    }
+    acc = block_sum(acc, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
+template <class T, int NV>
+__global__ __launch_bounds__(kNT) void k_mdot_gated(const T *__restrict__ V, int64_t ldv, int nv,
+                                                    const T *__restrict__ w, int64_t n, double *__restrict__ part,
+                                                    int ldp, const int *__restrict__ gate) {
+    if (*gate == 0) return;
+    // same body as k_mdot (a gated launch of the second pass)
+    __shared__ double sh[kNT / kWave];
+    double acc[NV + 1];
+#pragma unroll
+    for (int i = 0; i <= NV; ++i) acc[i] = 0.0;
+    for (int64_t r = (int64_t)blockIdx.x * kNT + threadIdx.x; r < n; r += (int64_t)gridDim.x * kNT) {
+        const double wr = (double)w[r];
+        acc[NV] += wr * wr;
+#pragma unroll
+        for (int i = 0; i < NV; ++i)
+            if (i < nv) acc[i] += (double)V[i * ldv + r] * wr;
+    }
+    for (int i = 0; i < nv; ++i) {
+        double t = 0.0;
+#pragma unroll
+        for (int q = 0; q < NV; ++q)
+            if (q == i) t = acc[q];
+        t = block_sum(t, sh);
+        if (threadIdx.x == 0) part[(int64_t)blockIdx.x * ldp + i] = t;
+    }
+    double t = block_sum(acc[NV], sh);
+    if (threadIdx.x == 0) part[(int64_t)blockIdx.x * ldp + nv] = t;
+}
+
+}  // namespace
+
+// out[i] = sum over b (ascending) of part[b * ldp + i], i < m.  Optional
+// accumulate: out[i] += ... when add != 0.  When `gate` is non-null and
+// *gate == 0 nothing happens.
+__global__ void k_reduce_parts(const double *__restrict__ part, int nb, int ldp, int m, double *__restrict__ out,
+                               int add, const int *__restrict__ gate) {
+    if (gate && *gate == 0) return;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    double a = 0.0;
+    for (int b = 0; b < nb; ++b) a += part[(int64_t)b * ldp + i];
+    out[i] = add ? out[i] + a : a;
+}
+
+// DGKS test: *gate = ||w'|| < eta ||w|| given squared norms (one thread).
+__global__ void k_dgks_gate(const double *__restrict__ wnorm2, const double *__restrict__ wpnorm2, double eta,
+                            int *__restrict__ gate) {
+    if (threadIdx.x == 0) *gate = (sqrt(*wpnorm2) < eta * sqrt(*wnorm2)) ? 1 : 0;
+}
+
+// v = w / sqrt(*nrm2) (stored as T), z = v / d (Jacobi) or v
+template <class T>
+__global__ void k_scale_precond(const T *__restrict__ w, const double *__restrict__ nrm2, T *__restrict__ v,
+                                T *__restrict__ z, const T *__restrict__ d, int64_t n) {
+    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    double s = sqrt(*nrm2);
+    double inv = s > 0.0 ? 1.0 / s : 0.0;
+    T vr = (T)((double)w[r] * inv);
+    v[r] = vr;
+    if (z) z[r] = d ? (T)((double)vr / (double)d[r]) : vr;
+}
+
+// v = r * scale (scale given on the host), z = v / d or v
+template <class TS, class T>
+__global__ void k_scale_from(const TS *__restrict__ r, double scale, T *__restrict__ v, T *__restrict__ z,
+                             const T *__restrict__ d, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    T vr = (T)((double)r[i] * scale);
+    v[i] = vr;
+    if (z) z[i] = d ? (T)((double)vr / (double)d[i]) : vr;
+}
+
+// r = b - r (in place over the product), part[b] = sum r^2
+__global__ __launch_bounds__(kNT) void k_residual(const double *__restrict__ b, double *__restrict__ r, int64_t n,
+                                                  double *__restrict__ part) {
+    __shared__ double sh[kNT / kWave];
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kNT) {
+        double v = b[i] - r[i];
+        r[i] = v;
+        acc += v * v;
+    }
+    acc = block_sum(acc, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
+// x += scale * M^-1 sum_i y[i] V_i   (FP64 x, T basis, diag in FP64 or null)
+template <class T>
+__global__ void k_combine(const T *__restrict__ V, int64_t ldv, int k, const double *__restrict__ y, double scale,
+                          const T *__restrict__ d, double *__restrict__ x, int64_t n) {
+    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    double a = 0.0;
+    for (int i = 0; i < k; ++i) a += y[i] * (double)V[i * ldv + r];
+    a *= scale;
+    if (d) a /= (double)d[r];
+    x[r] += a;
+}
+
+// diagonal of A (sum of the entries with col == row); 1 where it is 0
+template <class VT>
+__global__ void k_diag(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colind,
+                       const VT *__restrict__ val, int32_t n, VT *__restrict__ d) {
+    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    VT a = VT(0);
+    for (int64_t k = rowptr[r]; k < rowptr[r + 1]; ++k)
+        if (colind[k] == r) a += val[k];
+    d[r] = a != VT(0) ? a : VT(1);
+}
+
+template <class T>
+__global__ void k_copy_cast(const double *__restrict__ s, T *__restrict__ d, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) d[i] = (T)s[i];
+}
+
+// ------------------------------------------------------------------ host wrappers
+template <class T>
+int mdot(xab_ctx *ctx, const T *V, int64_t ldv, int nv, const T *w, int64_t n, double *part, int nb,
+         const int *gate) {
+    dim3 g(nb), b(kNT);
+    const int ldp = kPartLd;
+#define XAB_MDOT_CASE(NVC)                                                                                       \
+    if (nv <= NVC) {                                                                                             \
+        if (gate) hipLaunchKernelGGL((k_mdot_gated<T, NVC>), g, b, 0, ctx->stream, V, ldv, nv, w, n, part, ldp, gate); \
+        else hipLaunchKernelGGL((k_mdot<T, NVC>), g, b, 0, ctx->stream, V, ldv, nv, w, n, part, ldp);            \
+        XAB_LAUNCH_CHECK(ctx, "k_mdot");                                                                         \
+        return XAB_OK;                                                                                           \
+    }
+    XAB_MDOT_CASE(8)
+    XAB_MDOT_CASE(16)
+    XAB_MDOT_CASE(32)
+    XAB_MDOT_CASE(64)
+#undef XAB_MDOT_CASE
+    return xab_fail(ctx, XAB_E_UNSUPPORTED, "more than 64 basis vectors");
+}
+
+template <class T>
+int update_norm(xab_ctx *ctx, const T *V, int64_t ldv, int nv, const double *h, T *w, int64_t n, double *part,
+                int nb, const int *gate) {
+    dim3 g(nb), b(kNT);
+#define XAB_UPD_CASE(NVC)                                                                                \
+    if (nv <= NVC) {                                                                                     \
+        hipLaunchKernelGGL((k_update_norm<T, NVC>), g, b, 0, ctx->stream, V, ldv, nv, h, w, n, part, gate); \
+        XAB_LAUNCH_CHECK(ctx, "k_update_norm");                                                          \
+        return XAB_OK;                                                                                   \
+    }
+    XAB_UPD_CASE(8)
+    XAB_UPD_CASE(16)
+    XAB_UPD_CASE(32)
+    XAB_UPD_CASE(64)
+#undef XAB_UPD_CASE
+    return xab_fail(ctx, XAB_E_UNSUPPORTED, "more than 64 basis vectors");
+}
+
+template int mdot<double>(xab_ctx *, const double *, int64_t, int, const double *, int64_t, double *, int, const int *);
+template int mdot<float>(xab_ctx *, const float *, int64_t, int, const float *, int64_t, double *, int, const int *);
+template int update_norm<double>(xab_ctx *, const double *, int64_t, int, const double *, double *, int64_t, double *,
+                                 int, const int *);
+template int update_norm<float>(xab_ctx *, const float *, int64_t, int, const double *, float *, int64_t, double *,
+                                int, const int *);
+
+int reduce_parts(xab_ctx *ctx, const double *part, int nb, int ldp, int m, double *out, int add, const int *gate) {
+    hipLaunchKernelGGL(k_reduce_parts, dim3((m + 63) / 64), dim3(64), 0, ctx->stream, part, nb, ldp, m, out, add, gate);
+    XAB_LAUNCH_CHECK(ctx, "k_reduce_parts");
+    return XAB_OK;
+}
+
+int dgks_gate(xab_ctx *ctx, const double *wn2, const double *wpn2, double eta, int *gate) {
+    hipLaunchKernelGGL(k_dgks_gate, dim3(1), dim3(64), 0, ctx->stream, wn2, wpn2, eta, gate);
+    XAB_LAUNCH_CHECK(ctx, "k_dgks_gate");
+    return XAB_OK;
+}
+
+template <class T>
+int scale_precond(xab_ctx *ctx, const T *w, const double *nrm2, T *v, T *z, const T *d, int64_t n) {
+    hipLaunchKernelGGL((k_scale_precond<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, ctx->stream, w, nrm2, v,
+                       z, d, n);
+    XAB_LAUNCH_CHECK(ctx, "k_scale_precond");
+    return XAB_OK;
+}
+template int scale_precond<double>(xab_ctx *, const double *, const double *, double *, double *, const double *,
+                                   int64_t);
+template int scale_precond<float>(xab_ctx *, const float *, const double *, float *, float *, const float *, int64_t);
+
+template <class TS, class T>
+int scale_from(xab_ctx *ctx, const TS *r, double scale, T *v, T *z, const T *d, int64_t n) {
+    hipLaunchKernelGGL((k_scale_from<TS, T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, ctx->stream, r, scale, v,
+                       z, d, n);
+    XAB_LAUNCH_CHECK(ctx, "k_scale_from");
+    return XAB_OK;
+}
+template int scale_from<double, double>(xab_ctx *, const double *, double, double *, double *, const double *, int64_t);
+template int scale_from<double, float>(xab_ctx *, const double *, double, float *, float *, const float *, int64_t);
+
+int residual(xab_ctx *ctx, const double *b, double *r, int64_t n, double *part, int nb) {
+    hipLaunchKernelGGL(k_residual, dim3(nb), dim3(kNT), 0, ctx->stream, b, r, n, part);
+    XAB_LAUNCH_CHECK(ctx, "k_residual");
+    return XAB_OK;
+}
+
+template <class T>
+int combine(xab_ctx *ctx, const T *V, int64_t ldv, int k, const double *y, double scale, const T *d, double *x,
+            int64_t n) {
+    hipLaunchKernelGGL((k_combine<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, ctx->stream, V, ldv, k, y, scale,
+                       d, x, n);
+    XAB_LAUNCH_CHECK(ctx, "k_combine");
+    return XAB_OK;
+}
+template int combine<double>(xab_ctx *, const double *, int64_t, int, const double *, double, const double *, double *,
+                             int64_t);
+template int combine<float>(xab_ctx *, const float *, int64_t, int, const double *, double, const float *, double *,
+                            int64_t);
+
+template <class T>
+int copy_cast(xab_ctx *ctx, const double *s, T *d, int64_t n) {
+    hipLaunchKernelGGL((k_copy_cast<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, ctx->stream, s, d, n);
+    XAB_LAUNCH_CHECK(ctx, "k_copy_cast");
+    return XAB_OK;
+}
+template int copy_cast<float>(xab_ctx *, const double *, float *, int64_t);
+
+}  // namespace xab
+
+// Jacobi diagonal of A in every precision A holds (library-owned, cached)
+int xab_matrix_diag(xab_ctx *ctx, xab_matrix *A) {
+    unsigned g = (unsigned)((A->n + 255) / 256);
+    if (A->n == 0) return XAB_OK;
+    if (A->has64 && !A->diag64) {
+        A->diag64 = (double *)xab_dalloc(ctx, sizeof(double) * A->n);
+        if (!A->diag64) return xab_fail(ctx, XAB_E_NOMEM, "diagonal");
+        hipLaunchKernelGGL((xab::k_diag<double>), dim3(g), dim3(256), 0, ctx->stream, A->rowptr, A->colind, A->val64,
+                           A->n, A->diag64);
+        XAB_LAUNCH_CHECK(ctx, "k_diag");
+    }
+    if (A->has32 && !A->diag32) {
+        A->diag32 = (float *)xab_dalloc(ctx, sizeof(float) * A->n);
+        if (!A->diag32) return xab_fail(ctx, XAB_E_NOMEM, "diagonal");
+        hipLaunchKernelGGL((xab::k_diag<float>), dim3(g), dim3(256), 0, ctx->stream, A->rowptr, A->colind, A->val32,
+                           A->n, A->diag32);
+        XAB_LAUNCH_CHECK(ctx, "k_diag");
+    }
+    return XAB_OK;
+}

@@ -1,0 +1,192 @@
+// Internal definitions of the xab library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/xab.h"
+
+// ------------------------------------------------------------------ context
+struct xab_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    void *(*alloc_fn)(size_t, void *) = nullptr;
+    void (*free_fn)(void *, void *) = nullptr;
+    void *user = nullptr;
+    int policy = XAB_TIME;
+    char err[512] = {0};
+    // device scratch owned by the context (grown on demand)
+    void *scratch = nullptr;
+    size_t scratch_bytes = 0;
+    int *d_flag = nullptr;          // validation error flags
+    // cost model (host copy; uploaded on use)
+    std::vector<float> mlp;         // XAB_MLP_NPARAMS
+    std::vector<float> fmean, fstd; // 12 each
+    bool mlp_set = false;
+    float *d_mlp = nullptr;         // device copy of mlp + mean + std
+};
+
+struct xab_matrix {
+    xab_ctx *ctx = nullptr;
+    int32_t n = 0, ncols = 0;
+    int64_t nnz = 0;
+    const int32_t *rowptr = nullptr;
+    const int32_t *colind = nullptr;
+    const double *val64 = nullptr;
+    const float *val32 = nullptr;
+    bool has64 = false, has32 = false; // value copies attached (pointers may be null when nnz = 0)
+    uint32_t flags = 0;
+    bool sym() const { return (flags & XAB_SYM_LOWER) != 0; }
+    // cached statistics (computed on first feature request)
+    bool have_stats = false;
+    int64_t stats[9] = {0};
+    double *diag64 = nullptr; // Jacobi diagonal (lazy, library-owned)
+    float *diag32 = nullptr;
+};
+
+struct xab_plan {
+    xab_ctx *ctx = nullptr;
+    const xab_matrix *A = nullptr;
+    xab_variant variant = XAB_NNZ;
+    xab_params params{};
+    int64_t P = 0;             // tiles / parts / workgroups
+    // NNZ: b[P+1]; SYM_S3: b[P+1] tile row boundaries
+    int32_t *b = nullptr;
+    // BSS
+    int32_t *row_lo = nullptr, *tile_row = nullptr, *carry_row = nullptr;
+    void *carry_val = nullptr, *tail_val = nullptr; // acc-type workspaces [P]
+    int32_t *tail_row = nullptr;
+    // SYM_S3 touch map
+    int64_t nblk = 0, ntouch = 0;
+    int32_t *tm_ptr = nullptr, *tm_tile = nullptr, *tile_ptr = nullptr, *tile_blk = nullptr, *tile_slot = nullptr;
+    int32_t *tile_minblk = nullptr;
+    void *partial = nullptr;   // ntouch * col_block acc-type values
+    size_t partial_elem = 0;   // bytes per element allocated (4 or 8)
+};
+
+struct xab_batch {
+    xab_ctx *ctx = nullptr;
+    int32_t nsys = 0;
+    int64_t n = 0, nnz = 0;
+    std::vector<int64_t> row_off, nnz_off;
+    const int32_t *rowptr = nullptr, *colind = nullptr;
+    const void *val = nullptr;
+    xab_dtype vt = XAB_F64;
+    // persistent SpMV split: P parts of whole rows, balanced by nnz
+    int64_t P = 0;
+    int32_t *b = nullptr;
+    int32_t *d_sys_of_row = nullptr; // system index of every row
+    int64_t *d_row_off = nullptr;    // [nsys+1]
+};
+
+// ------------------------------------------------------------------ helpers
+int xab_fail(xab_ctx *ctx, int code, const char *fmt, ...);
+void *xab_dalloc(xab_ctx *ctx, size_t bytes);
+void xab_dfree(xab_ctx *ctx, void *p);
+int xab_hip_check(xab_ctx *ctx, hipError_t e, const char *what);
+// scratch: at least `bytes` of context-owned device memory (reused across calls)
+void *xab_scratch(xab_ctx *ctx, size_t bytes);
+
+#define XAB_HIP(ctx, call)                                   \
+    do {                                                     \
+        hipError_t _e = (call);                              \
+        if (_e != hipSuccess) return xab_hip_check(ctx, _e, #call); \
+    } while (0)
+
+#define XAB_LAUNCH_CHECK(ctx, what)                                        \
+    do {                                                                   \
+        hipError_t _e = hipGetLastError();                                 \
+        if (_e != hipSuccess) return xab_hip_check(ctx, _e, what);         \
+    } while (0)
+
+// plan builders (plan.hip)
+int xab_build_plan(xab_ctx *ctx, const xab_matrix *A, xab_variant v, const xab_params *p, xab_plan **out);
+
+// SpMV dispatch (spmv.hip)
+int xab_spmv_dispatch(xab_ctx *ctx, const xab_plan *plan, const void *x, xab_dtype xt, void *y, xab_dtype yt,
+                      xab_dtype acc);
+
+// statistics (features.hip)
+int xab_matrix_stats(xab_ctx *ctx, xab_matrix *A);
+void xab_stats_to_features(const int64_t *st, int sym, float *out);
+
+// Jacobi diagonal (blas.hip)
+int xab_matrix_diag(xab_ctx *ctx, xab_matrix *A);
+
+// ------------------------------------------------------------------ device helpers
+#ifdef __HIPCC__
+namespace xab {
+
+constexpr int kWave = 64;
+
+// Number of XCDs of the MI355X: consecutive workgroup ids are dispatched
+// round-robin over them.  xcd_remap turns a hardware block id into a
+// logical tile index such that each XCD receives a contiguous range of
+// tiles (its L2 then caches one window of x instead of the whole vector).
+constexpr int kXcds = 8;
+__device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t nblocks) {
+    int64_t q = nblocks / kXcds, r = nblocks % kXcds;
+    int64_t xcd = bid % kXcds, i = bid / kXcds;
+    return xcd * q + (xcd < r ? xcd : r) + i;
+}
+
+template <class T>
+__device__ __forceinline__ T ld_nt(const T *p) {
+    return __builtin_nontemporal_load(p);
+}
+
+template <class T>
+__device__ __forceinline__ T shfl_up(T v, int d) {
+    return __shfl_up(v, d, kWave);
+}
+template <class T>
+__device__ __forceinline__ T shfl_xor(T v, int m, int w = kWave) {
+    return __shfl_xor(v, m, w);
+}
+
+// Segmented-sum scan element: `f` = a segment (row) starts in this span,
+// `v` = sum since the last start (or of the whole span), `r` = row of that
+// last start.  combine(a, b) = the state after a followed by b.
+template <class AT>
+struct Seg {
+    int f;
+    AT v;
+    int r;
+};
+template <class AT>
+__device__ __forceinline__ Seg<AT> seg_combine(const Seg<AT> &a, const Seg<AT> &b) {
+    Seg<AT> o;
+    o.f = a.f | b.f;
+    o.v = b.f ? b.v : a.v + b.v;
+    o.r = b.f ? b.r : a.r;
+    return o;
+}
+
+// Inclusive segmented scan across the 64 lanes of a wave.
+template <class AT>
+__device__ __forceinline__ Seg<AT> wave_seg_scan(Seg<AT> s, int lane) {
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        Seg<AT> u;
+        u.f = shfl_up(s.f, d);
+        u.v = shfl_up(s.v, d);
+        u.r = shfl_up(s.r, d);
+        if (lane >= d) s = seg_combine(u, s);
+    }
+    return s;
+}
+
+template <class T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int m = kWave / 2; m > 0; m >>= 1) v += shfl_xor(v, m);
+    return v;
+}
+
+}  // namespace xab
+#endif

@@ -1,0 +1,310 @@
+// SpMV implementations built on the segmented chunk reduction:
+//   nnz-split (the paper's non-zero elements based decomposition),
+//   branchless segmented scan (with its carry fix-up),
+//   symmetric SpMV with zero-element omission in the transpose reduction.
+#include "segchunk.h"
+#include "spmv_launch.h"
+#include "sym_layout.h"
+
+namespace xab {
+namespace {
+
+constexpr int kNT = 256;      // threads per workgroup
+constexpr int kChunkJ = 8;    // entries per lane per chunk (nnz-split, symmetric)
+
+template <class YT, class AT>
+struct StoreSink {
+    YT *y;
+    __device__ void row_done(int32_t r, AT v) { y[r] = (YT)v; }
+    __device__ void empty_row(int32_t r) { y[r] = YT(0); }
+    template <class VT>
+    __device__ void entry(int32_t, int32_t, VT) {}
+};
+
+// smallest r in [lo, hi] with rowptr[r] >= target (rowptr[hi] >= target assumed)
+__device__ __forceinline__ int32_t lb_range(const int32_t *rowptr, int32_t lo, int32_t hi, int64_t target) {
+    while (lo < hi) {
+        int32_t mid = lo + (hi - lo) / 2;
+        if (rowptr[mid] >= target) hi = mid;
+        else lo = mid + 1;
+    }
+    return lo;
+}
+
+// ------------------------------------------------------------------ nnz-split
+// Workgroup p owns whole rows [b[p], b[p+1]) (about T entries).  It walks
+// them in chunks of 256*8 entries aligned to the chunk size; a row crossing
+// a chunk boundary stays open in the scan seed, so every row is written
+// exactly once, by the workgroup that owns it.
+template <class VT, class XT, class YT, class AT>
+__global__ __launch_bounds__(kNT) void k_spmv_nnz(const int32_t *__restrict__ rowptr,
+                                                  const int32_t *__restrict__ colind, const VT *__restrict__ val,
+                                                  const XT *__restrict__ x, YT *__restrict__ y,
+                                                  const int32_t *__restrict__ b, int64_t P) {
+    constexpr int CH = kNT * kChunkJ;
+    __shared__ int32_t head_row[CH];
+    __shared__ Seg<AT> wave_tot[kNT / kWave];
+    const int64_t p = xcd_remap(blockIdx.x, P);
+    const int32_t r0 = b[p], r1 = b[p + 1];
+    if (r0 >= r1) return;
+    const int64_t s = rowptr[r0], e = rowptr[r1];
+    StoreSink<YT, AT> sink{y};
+    Seg<AT> seed{0, AT(0), -1};
+    int32_t rlo = r0;
+    int64_t A = s - (s % CH);
+    for (;;) {
+        const int64_t Aend = A + CH;
+        const bool last = Aend >= e;
+        const int32_t rhi = last ? r1 : lb_range(rowptr, rlo, r1, Aend);
+        clear_heads<kNT, kChunkJ>(head_row);
+        __syncthreads();
+        mark_heads<kNT>(rowptr, rlo, rhi, A, head_row, sink);
+        __syncthreads();
+        ChunkResult<AT> res = seg_chunk<kNT, kChunkJ, VT, XT, AT>(A, s > A ? s : A, e < Aend ? e : Aend, colind,
+                                                                  val, x, head_row, seed, wave_tot, sink);
+        seed = res.state;
+        rlo = rhi;
+        if (last) break;
+        A = Aend;
+    }
+    if (threadIdx.x == 0 && seed.f) y[seed.r] = (YT)seed.v;
+}
+
+// ------------------------------------------------------------------ BSS
+// Tile t = entries [tT, min((t+1)T, nnz)), T = 256 * J.  Rows that start
+// and end in the tile are written directly.  The last row started in the
+// tile, if it runs past the tile, leaves its partial in tail_val[t]; the
+// leading partial of a row begun in an earlier tile goes to carry_val[t].
+// The fix-up kernel then writes each such row once: its start partial plus
+// the carries of the following tiles in ascending tile order.
+template <class VT, class XT, class YT, class AT, int J>
+__global__ __launch_bounds__(kNT) void k_spmv_bss(const int32_t *__restrict__ rowptr,
+                                                  const int32_t *__restrict__ colind, const VT *__restrict__ val,
+                                                  const XT *__restrict__ x, YT *__restrict__ y, int64_t nnz,
+                                                  int64_t P, const int32_t *__restrict__ row_lo,
+                                                  const int32_t *__restrict__ carry_row, AT *__restrict__ carry_val,
+                                                  AT *__restrict__ tail_val, int32_t *__restrict__ tail_row) {
+    constexpr int T = kNT * J;
+    __shared__ int32_t head_row[T];
+    __shared__ Seg<AT> wave_tot[kNT / kWave];
+    const int64_t t = xcd_remap(blockIdx.x, P);
+    const int64_t A = t * T;
+    const int64_t c1 = (A + T < nnz) ? A + T : nnz;
+    StoreSink<YT, AT> sink{y};
+    clear_heads<kNT, J>(head_row);
+    __syncthreads();
+    mark_heads<kNT>(rowptr, row_lo[t], row_lo[t + 1], A, head_row, sink);
+    __syncthreads();
+    Seg<AT> seed{0, AT(0), -1};
+    ChunkResult<AT> res = seg_chunk<kNT, J, VT, XT, AT>(A, A, c1, colind, val, x, head_row, seed, wave_tot, sink);
+    const int32_t cr = carry_row[t];
+    if (res.has_lead && cr >= 0) carry_val[t] = res.lead;
+    if (threadIdx.x == 0) {
+        int32_t tr = -1;
+        if (!res.state.f) {
+            // no row starts in this tile: all of it belongs to the carried row
+            if (cr >= 0) carry_val[t] = res.state.v;
+        } else if (rowptr[res.state.r + 1] <= c1) {
+            y[res.state.r] = (YT)res.state.v;
+        } else {
+            tr = res.state.r;
+            tail_val[t] = res.state.v;
+        }
+        tail_row[t] = tr;
+    }
+}
+
+template <class YT, class AT>
+__global__ void k_bss_fixup(YT *__restrict__ y, int64_t P, const int32_t *__restrict__ carry_row,
+                            const AT *__restrict__ carry_val, const AT *__restrict__ tail_val,
+                            const int32_t *__restrict__ tail_row) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= P) return;
+    int32_t r = tail_row[t];
+    if (r < 0) return;
+    AT acc = tail_val[t];
+    for (int64_t u = t + 1; u < P && carry_row[u] == r; ++u) acc += carry_val[u];
+    y[r] = (YT)acc;
+}
+
+// ------------------------------------------------------------------ symmetric S3
+// y = (L + L_strict^T) x from the lower triangle L.  Tile p owns rows
+// [b[p], b[p+1]) (at most kRowCap).  Its row sums and the transposed
+// entries that land on its own rows accumulate in LDS (own[]).  Transposed
+// entries landing below the tile (column j < b[p]) accumulate in LDS slots
+// of the column blocks the touch map lists for the tile (ext[]); every
+// other region of the reduction vector is known to be zero and is never
+// touched.  At the end the tile writes its rows of y and its block
+// partials; the block-reduce kernel adds, per touched block, the partials
+// of the later tiles in ascending tile order.
+template <class VT, class XT, class YT, class AT, int C>
+__global__ __launch_bounds__(kNT) void k_spmv_sym_s3(const int32_t *__restrict__ rowptr,
+                                                     const int32_t *__restrict__ colind, const VT *__restrict__ val,
+                                                     const XT *__restrict__ x, YT *__restrict__ y,
+                                                     const int32_t *__restrict__ b, int64_t P,
+                                                     const int32_t *__restrict__ tile_ptr,
+                                                     const int32_t *__restrict__ tile_blk,
+                                                     const int32_t *__restrict__ tile_slot,
+                                                     const int32_t *__restrict__ tile_minblk,
+                                                     AT *__restrict__ partial) {
+    constexpr int CH = kNT * kChunkJ;
+    constexpr int kOwnCap = sym::kRowCap;
+    constexpr int kExtCap = sym::kExtCap;
+    __shared__ int32_t head_row[CH];
+    __shared__ Seg<AT> wave_tot[kNT / kWave];
+    __shared__ AT own[kOwnCap];
+    __shared__ AT ext[kExtCap];
+    __shared__ int16_t lut[sym::kLutMax];
+    const int64_t p = xcd_remap(blockIdx.x, P);
+    const int32_t r0 = b[p], r1 = b[p + 1];
+    if (r0 >= r1) return;
+    const int64_t s = rowptr[r0], e = rowptr[r1];
+    const int32_t q0 = tile_ptr[p], q1 = tile_ptr[p + 1];
+    const int32_t nb = q1 - q0;
+    const int32_t minblk = tile_minblk[p];
+    const int tid = threadIdx.x;
+    for (int i = tid; i < r1 - r0; i += kNT) own[i] = AT(0);
+    for (int i = tid; i < nb * C; i += kNT) ext[i] = AT(0);
+    for (int i = tid; i < sym::kLutMax; i += kNT) lut[i] = 0;
+    __syncthreads();
+    for (int i = tid; i < nb; i += kNT) lut[tile_blk[q0 + i] - minblk] = (int16_t)i;
+
+    struct Sink {
+        AT *own;
+        AT *ext;
+        const int16_t *lut;
+        const XT *x;
+        int32_t r0, minblk;
+        int32_t xrow;
+        AT xr;
+        __device__ void row_done(int32_t r, AT v) { atomicAdd(&own[r - r0], v); }
+        __device__ void empty_row(int32_t) {}
+        __device__ void entry(int32_t row, int32_t j, VT v) {
+            if (j < 0 || j >= row) return;  // dead slot or diagonal
+            if (row != xrow) {
+                xrow = row;
+                xr = (AT)x[row];
+            }
+            AT tv = (AT)v * xr;
+            if (j >= r0) atomicAdd(&own[j - r0], tv);
+            else atomicAdd(&ext[(int)lut[j / C - minblk] * C + (j % C)], tv);
+        }
+    } sink{own, ext, lut, x, r0, minblk, -1, AT(0)};
+
+    Seg<AT> seed{0, AT(0), -1};
+    int32_t rlo = r0;
+    int64_t A = s - (s % CH);
+    for (;;) {
+        const int64_t Aend = A + CH;
+        const bool last = Aend >= e;
+        const int32_t rhi = last ? r1 : lb_range(rowptr, rlo, r1, Aend);
+        clear_heads<kNT, kChunkJ>(head_row);
+        __syncthreads();
+        mark_heads<kNT>(rowptr, rlo, rhi, A, head_row, sink);
+        __syncthreads();
+        ChunkResult<AT> res = seg_chunk<kNT, kChunkJ, VT, XT, AT>(A, s > A ? s : A, e < Aend ? e : Aend, colind,
+                                                                  val, x, head_row, seed, wave_tot, sink);
+        seed = res.state;
+        rlo = rhi;
+        if (last) break;
+        A = Aend;
+    }
+    if (tid == 0 && seed.f) atomicAdd(&own[seed.r - r0], seed.v);
+    __syncthreads();
+    for (int i = tid; i < r1 - r0; i += kNT) y[r0 + i] = (YT)own[i];
+    for (int i = tid; i < nb * C; i += kNT) {
+        int q = i / C;
+        partial[(int64_t)tile_slot[q0 + q] * C + (i % C)] = ext[i];
+    }
+}
+
+// Adds to each row of a touched column block the partials of the tiles
+// listed for that block, in the listed (ascending tile) order.
+template <class YT, class AT, int C>
+__global__ void k_sym_block_reduce(YT *__restrict__ y, int32_t n, const int32_t *__restrict__ tm_ptr,
+                                   const AT *__restrict__ partial) {
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    int64_t c = j / C;
+    int32_t s0 = tm_ptr[c], s1 = tm_ptr[c + 1];
+    if (s0 == s1) return;
+    AT acc = AT(0);
+    for (int32_t s = s0; s < s1; ++s) acc += partial[(int64_t)s * C + (j % C)];
+    y[j] = (YT)((AT)y[j] + acc);
+}
+
+unsigned grid_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+}  // namespace
+
+template <class VT, class XT, class YT, class AT>
+int launch_nnz(xab_ctx *ctx, const xab_plan *pl, const VT *val, const XT *x, YT *y) {
+    const xab_matrix *A = pl->A;
+    hipLaunchKernelGGL((k_spmv_nnz<VT, XT, YT, AT>), dim3((unsigned)pl->P), dim3(kNT), 0, ctx->stream, A->rowptr,
+                       A->colind, val, x, y, pl->b, pl->P);
+    XAB_LAUNCH_CHECK(ctx, "k_spmv_nnz");
+    return XAB_OK;
+}
+
+template <class VT, class XT, class YT, class AT, int J>
+static int launch_bss_j(xab_ctx *ctx, const xab_plan *pl, const VT *val, const XT *x, YT *y) {
+    const xab_matrix *A = pl->A;
+    hipLaunchKernelGGL((k_spmv_bss<VT, XT, YT, AT, J>), dim3((unsigned)pl->P), dim3(kNT), 0, ctx->stream, A->rowptr,
+                       A->colind, val, x, y, A->nnz, pl->P, pl->row_lo, pl->carry_row, (AT *)pl->carry_val,
+                       (AT *)pl->tail_val, pl->tail_row);
+    XAB_LAUNCH_CHECK(ctx, "k_spmv_bss");
+    hipLaunchKernelGGL((k_bss_fixup<YT, AT>), dim3(grid_for(pl->P, 256)), dim3(256), 0, ctx->stream, y, pl->P,
+                       pl->carry_row, (const AT *)pl->carry_val, (const AT *)pl->tail_val, pl->tail_row);
+    XAB_LAUNCH_CHECK(ctx, "k_bss_fixup");
+    return XAB_OK;
+}
+
+template <class VT, class XT, class YT, class AT>
+int launch_bss(xab_ctx *ctx, const xab_plan *pl, const VT *val, const XT *x, YT *y) {
+    switch (pl->params.j_per_lane) {
+        case 1: return launch_bss_j<VT, XT, YT, AT, 1>(ctx, pl, val, x, y);
+        case 2: return launch_bss_j<VT, XT, YT, AT, 2>(ctx, pl, val, x, y);
+        case 4: return launch_bss_j<VT, XT, YT, AT, 4>(ctx, pl, val, x, y);
+        case 8: return launch_bss_j<VT, XT, YT, AT, 8>(ctx, pl, val, x, y);
+        case 16: return launch_bss_j<VT, XT, YT, AT, 16>(ctx, pl, val, x, y);
+        case 32: return launch_bss_j<VT, XT, YT, AT, 32>(ctx, pl, val, x, y);
+        default: return xab_fail(ctx, XAB_E_UNSUPPORTED, "j_per_lane %d", pl->params.j_per_lane);
+    }
+}
+
+template <class VT, class XT, class YT, class AT, int C>
+static int launch_s3_c(xab_ctx *ctx, const xab_plan *pl, const VT *val, const XT *x, YT *y) {
+    const xab_matrix *A = pl->A;
+    hipLaunchKernelGGL((k_spmv_sym_s3<VT, XT, YT, AT, C>), dim3((unsigned)pl->P), dim3(kNT), 0, ctx->stream,
+                       A->rowptr, A->colind, val, x, y, pl->b, pl->P, pl->tile_ptr, pl->tile_blk, pl->tile_slot,
+                       pl->tile_minblk, (AT *)pl->partial);
+    XAB_LAUNCH_CHECK(ctx, "k_spmv_sym_s3");
+    if (pl->ntouch > 0) {
+        hipLaunchKernelGGL((k_sym_block_reduce<YT, AT, C>), dim3(grid_for(A->n, 256)), dim3(256), 0, ctx->stream, y,
+                           A->n, pl->tm_ptr, (const AT *)pl->partial);
+        XAB_LAUNCH_CHECK(ctx, "k_sym_block_reduce");
+    }
+    return XAB_OK;
+}
+
+template <class VT, class XT, class YT, class AT>
+int launch_sym_s3(xab_ctx *ctx, const xab_plan *pl, const VT *val, const XT *x, YT *y) {
+    switch (pl->params.col_block) {
+        case 16: return launch_s3_c<VT, XT, YT, AT, 16>(ctx, pl, val, x, y);
+        case 32: return launch_s3_c<VT, XT, YT, AT, 32>(ctx, pl, val, x, y);
+        case 64: return launch_s3_c<VT, XT, YT, AT, 64>(ctx, pl, val, x, y);
+        case 128: return launch_s3_c<VT, XT, YT, AT, 128>(ctx, pl, val, x, y);
+        case 256: return launch_s3_c<VT, XT, YT, AT, 256>(ctx, pl, val, x, y);
+        case 512: return launch_s3_c<VT, XT, YT, AT, 512>(ctx, pl, val, x, y);
+        case 1024: return launch_s3_c<VT, XT, YT, AT, 1024>(ctx, pl, val, x, y);
+        case 2048: return launch_s3_c<VT, XT, YT, AT, 2048>(ctx, pl, val, x, y);
+        case 4096: return launch_s3_c<VT, XT, YT, AT, 4096>(ctx, pl, val, x, y);
+        default: return xab_fail(ctx, XAB_E_UNSUPPORTED, "col_block %d", pl->params.col_block);
+    }
+}
+
+XAB_INSTANTIATE_LAUNCHER(launch_nnz)
+XAB_INSTANTIATE_LAUNCHER(launch_bss)
+XAB_INSTANTIATE_LAUNCHER(launch_sym_s3)
+
+}  // namespace xab

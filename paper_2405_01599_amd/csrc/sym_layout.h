@@ -1,0 +1,13 @@
+// Limits of the symmetric zero-block-omitted SpMV tile: shared by the plan
+// builder (which rejects matrices that do not fit) and the kernel (which
+// sizes its LDS with them).
+#pragma once
+
+namespace xab {
+namespace sym {
+constexpr int kRowCap = 2048;          // rows per tile (LDS accumulator of the tile's own rows)
+constexpr int kExtCap = 6144;          // LDS slots for column blocks below the tile
+constexpr int kLutMax = 2048;          // span of block ids one tile may touch
+constexpr int kLutWords = kLutMax / 32;
+}  // namespace sym
+}  // namespace xab

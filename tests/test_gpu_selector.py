@@ -1,0 +1,221 @@
+"""GPU checks of the selector: features (exact), the TIME / STABLE / LEARNED
+policies, and the cost model's forward, gradient and training kernels
+against the FP64 oracle on identical FP32 inputs."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import gen
+import oracle
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+xab = pytest.importorskip("paper_2405_01599_amd")
+
+K = xab.NCLASSES
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return xab.Context(0)
+
+
+MATS = {
+    "lap2d": lambda: gen.laplacian2d(64),
+    "powerlaw": lambda: gen.powerlaw(50_000, seed=2),
+    "trans4": lambda: gen.trans4_like(),
+    "st27_lower": lambda: gen.stencil27(20, lower=True),
+    "blockdiag": lambda: gen.blockdiag(30_000, 3),
+    "banded_lower": lambda: gen.banded(20_000, 30, 4, lower=True),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MATS))
+def test_features_exact(ctx, name):
+    A = MATS[name]()
+    M = ctx.matrix_from_csr(A)
+    f, st = ctx.features(M)
+    ost, of = oracle.features(A)
+    assert np.array_equal(st, ost)
+    assert np.array_equal(f, of.astype(np.float32))
+
+
+@pytest.mark.parametrize("name", sorted(MATS))
+def test_select_time_is_argmin(ctx, name):
+    A = MATS[name]()
+    M = ctx.matrix_from_csr(A)
+    P, info = ctx.select(M, xab.TIME)
+    valid = [k for k in range(K) if info.valid[k]]
+    assert valid, "no valid class"
+    if A.sym_lower:
+        assert all(k >= 9 for k in valid)
+    else:
+        assert valid == list(range(9))
+    t = {k: info.time_ms[k] for k in valid}
+    best = min(valid, key=lambda k: (t[k], k))
+    assert info.chosen == best
+    v, p = xab.class_params(info.chosen)
+    assert P.variant == v
+    # the chosen plan computes the product
+    x = gen.uniform_vec(A.n, 1)
+    y = ctx.spmv(P, torch.from_numpy(x).cuda()).cpu().numpy()
+    yo, s = oracle.spmv(A, x)
+    assert np.all(np.abs(y - yo) <= 1e-12 * s)
+
+
+def test_select_stable(ctx):
+    M = ctx.matrix_from_csr(gen.powerlaw(10_000, seed=2))
+    P, info = ctx.select(M, xab.STABLE)
+    assert info.chosen == 3 and P.variant == xab.NNZ
+    S = ctx.matrix_from_csr(gen.stencil27(12, lower=True))
+    P, info = ctx.select(S, xab.STABLE)
+    assert info.chosen == 11 and P.variant == xab.SYM_S3
+
+
+def _he_init(seed=5):
+    """He-uniform weights from the fixture generator, zero biases."""
+    F, H = 12, 64
+    shapes = [(H, F), (H,), (H, H), (H,), (K, H), (K,)]
+    out = []
+    for idx, s in enumerate(shapes):
+        size = int(np.prod(s))
+        if len(s) == 2:
+            bound = math.sqrt(6.0 / s[1])
+            out.append(gen.uniform_vec(size, seed * 16 + idx, -bound, bound))
+        else:
+            out.append(np.zeros(size))
+    return np.concatenate(out).astype(np.float32)
+
+
+def test_select_learned_follows_model(ctx):
+    p = np.zeros(xab.MLP_NPARAMS, dtype=np.float32)
+    bias = np.full(K, 5.0, dtype=np.float32)
+    bias[6] = -1.0   # predicts BSS J=8 fastest for general matrices
+    bias[10] = -2.0  # and S3 C=64 for symmetric ones
+    p[-K:] = bias
+    ctx.selector_set(p, np.zeros(12), np.ones(12))
+    M = ctx.matrix_from_csr(gen.powerlaw(10_000, seed=2))
+    P, info = ctx.select(M, xab.LEARNED)
+    assert info.chosen == 6 and P.variant == xab.BSS and P.params.j_per_lane == 8
+    S = ctx.matrix_from_csr(gen.stencil27(12, lower=True))
+    P, info = ctx.select(S, xab.LEARNED)
+    assert info.chosen == 10
+
+
+def test_mlp_forward_vs_oracle(ctx):
+    p = _he_init()
+    p[-K:] = np.linspace(-1, 1, K)
+    rng = np.random.default_rng(3)
+    feat = rng.standard_normal((100, 12)).astype(np.float32)
+    ctx.selector_set(p, np.zeros(12), np.ones(12))
+    out = ctx.selector_forward(torch.from_numpy(feat).cuda(), raw=False).cpu().numpy()
+    ref = oracle.mlp_forward(p.astype(np.float64), feat.astype(np.float64), K)
+    assert np.max(np.abs(out - ref)) <= 1e-4 * max(1.0, np.max(np.abs(ref)))
+
+
+def test_mlp_standardisation(ctx):
+    p = _he_init()
+    mean = np.linspace(1, 2, 12).astype(np.float32)
+    std = np.linspace(0.5, 3, 12).astype(np.float32)
+    ctx.selector_set(p, mean, std)
+    feat = np.random.default_rng(0).standard_normal((10, 12)).astype(np.float32) * 3 + 1
+    raw = ctx.selector_forward(torch.from_numpy(feat).cuda(), raw=True).cpu().numpy()
+    fs = ((feat - mean) / std).astype(np.float32)
+    ref = oracle.mlp_forward(p.astype(np.float64), fs.astype(np.float64), K)
+    assert np.max(np.abs(raw - ref)) <= 1e-4 * max(1.0, np.max(np.abs(ref)))
+
+
+def _tensor_slices():
+    F, H = 12, 64
+    sizes = [("W1", H * F), ("b1", H), ("W2", H * H), ("b2", H), ("W3", K * H), ("b3", K)]
+    out, o = [], 0
+    for name, s in sizes:
+        out.append((name, slice(o, o + s)))
+        o += s
+    return out
+
+
+@pytest.mark.parametrize("B", [7, 32, 100])
+def test_mlp_gradients_vs_oracle(ctx, B):
+    p = _he_init()
+    p[64 * 12:64 * 12 + 64] = 0.1  # positive b1 so ReLUs are active
+    rng = np.random.default_rng(B)
+    feat = rng.standard_normal((B, 12)).astype(np.float32)
+    y = rng.standard_normal((B, K)).astype(np.float32)
+    mask = (rng.random((B, K)) < 0.8).astype(np.uint8)
+    ctx.selector_set(p, np.zeros(12), np.ones(12))
+    loss, g = ctx.selector_loss_grad(torch.from_numpy(feat).cuda(), torch.from_numpy(y).cuda(),
+                                     torch.from_numpy(mask).cuda())
+    g = g.cpu().numpy().astype(np.float64)
+    ref_loss, ref_g = oracle.mlp_loss_grad(p.astype(np.float64), feat.astype(np.float64), y.astype(np.float64),
+                                           mask, K)
+    assert abs(loss - ref_loss) <= 1e-5 * abs(ref_loss)
+    for name, sl in _tensor_slices():
+        den = np.linalg.norm(ref_g[sl])
+        if den == 0:
+            assert np.linalg.norm(g[sl]) == 0
+            continue
+        assert np.linalg.norm(g[sl] - ref_g[sl]) / den <= 1e-4, name
+
+
+def test_mlp_zero_weights_closed_form(ctx):
+    p = np.zeros(xab.MLP_NPARAMS, dtype=np.float32)
+    b3 = np.linspace(-1, 1, K).astype(np.float32)
+    p[-K:] = b3
+    ctx.selector_set(p, np.zeros(12), np.ones(12))
+    rng = np.random.default_rng(2)
+    feat = rng.standard_normal((20, 12)).astype(np.float32)
+    y = rng.standard_normal((20, K)).astype(np.float32)
+    mask = np.ones((20, K), dtype=np.uint8)
+    out = ctx.selector_forward(torch.from_numpy(feat).cuda(), raw=False).cpu().numpy()
+    assert np.array_equal(out, np.tile(b3, (20, 1)))
+    _, g = ctx.selector_loss_grad(torch.from_numpy(feat).cuda(), torch.from_numpy(y).cuda(),
+                                  torch.from_numpy(mask).cuda())
+    g = g.cpu().numpy()
+    assert np.all(g[:64 * 12] == 0)
+
+
+def _synthetic_costs(m, seed):
+    """Costs with a learnable dependence on the features (a fixed linear map
+    of the features decides which class is cheapest)."""
+    rng = np.random.default_rng(seed)
+    feat = rng.standard_normal((m, 12)).astype(np.float32) * 2 + 3
+    W = rng.standard_normal((K, 12)) * 0.4
+    cost = np.exp2(np.abs((feat - 3) @ W.T) * 0.5).astype(np.float32) * 1e-2
+    valid = np.ones((m, K), dtype=np.uint8)
+    valid[:, 9:] = 0
+    return feat, cost, valid
+
+
+def test_mlp_training_vs_oracle_and_determinism(ctx, tmp_path):
+    m, E, Bsz = 256, 20, 64
+    feat, cost, valid = _synthetic_costs(m, 1)
+    order = np.concatenate([np.random.default_rng(e).permutation(m) for e in range(E)]).astype(np.int32)
+    p0 = _he_init()
+    ctx.selector_set(p0, np.zeros(12), np.ones(12))
+    tf, tc, tv = (torch.from_numpy(a).cuda() for a in (feat, cost, valid))
+    loss, info = ctx.selector_train(tf, tc, tv, order, epochs=E, batch=Bsz, lr=1e-3)
+    p1, mu, sd = ctx.selector_get()
+    assert loss[-1] < loss[0]
+    # oracle on the same standardised inputs and targets
+    assert np.allclose(mu, feat.astype(np.float64).mean(0), rtol=1e-5, atol=1e-5)
+    fs = (feat - mu) / sd
+    best = np.where(valid, cost, np.inf).min(1, keepdims=True)
+    yt = np.where(valid, np.log2(cost / best), 0.0)
+    p_ref, loss_ref = oracle.mlp_train(p0.astype(np.float64), fs.astype(np.float64), yt, valid, order, E, Bsz, 1e-3, K)
+    assert np.allclose(loss, loss_ref, rtol=2e-3, atol=1e-6)
+    assert np.linalg.norm(p1 - p_ref) / np.linalg.norm(p_ref) <= 2e-3
+    # determinism: a second run from the same start gives the same bits
+    ctx.selector_set(p0, np.zeros(12), np.ones(12))
+    loss2, _ = ctx.selector_train(tf, tc, tv, order, epochs=E, batch=Bsz, lr=1e-3)
+    p2, _, _ = ctx.selector_get()
+    assert np.array_equal(p1, p2) and np.array_equal(loss, loss2)
+    # save / load round trip
+    path = tmp_path / "sel.bin"
+    ctx.selector_save(path)
+    ctx.selector_set(p0, np.zeros(12), np.ones(12))
+    ctx.selector_load(path)
+    p3, mu3, sd3 = ctx.selector_get()
+    assert np.array_equal(p3, p1) and np.array_equal(mu3, mu) and np.array_equal(sd3, sd)

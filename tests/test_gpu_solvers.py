@@ -1,0 +1,224 @@
+"""GPU checks of the Krylov drivers against the oracle and closed forms.
+
+There is no bitwise parity for solvers (the GPU orthogonalises with CGS +
+DGKS re-orthogonalisation, the oracle with MGS): the bar is the true
+relative residual, the forward error against the oracle's solution, and
+iteration counts close to the oracle's.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import gen
+import oracle
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+xab = pytest.importorskip("paper_2405_01599_amd")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return xab.Context(0)
+
+
+def dev(a, dt=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda().to(dt)
+
+
+def _diag(d):
+    n = d.size
+    return gen.CSR(n, n, np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), d.astype(np.float64))
+
+
+def _setup(ctx, A, k=3, f32=True):
+    M = ctx.matrix_from_csr(A, with_f32=f32)
+    return M, ctx.plan_class(M, k)
+
+
+def test_gmres_identity(ctx):
+    A = _diag(np.ones(1000))
+    M, P = _setup(ctx, A)
+    b = gen.uniform_vec(1000, 3)
+    x, info, st = ctx.gmres(P, dev(b), precond=xab.PRECOND_NONE, tol=1e-12)
+    assert st == 0 and info["iters"] == 1
+    assert np.allclose(x.cpu().numpy(), b, atol=1e-15, rtol=0)
+
+
+@pytest.mark.parametrize("q", [1, 3, 7])
+def test_gmres_diagonal_minimal_polynomial(ctx, q):
+    n = 3000
+    A = _diag(np.arange(1, q + 1, dtype=np.float64)[np.arange(n) % q])
+    M, P = _setup(ctx, A)
+    x, info, st = ctx.gmres(P, dev(np.ones(n)), precond=xab.PRECOND_NONE, tol=1e-12)
+    assert st == 0 and info["iters"] <= q
+
+
+def test_gmres_eigenvector_rhs(ctx):
+    g = 64
+    A = gen.laplacian2d(g)
+    p = np.arange(g * g) % g
+    q = np.arange(g * g) // g
+    v = np.sin(3 * math.pi * (p + 1) / (g + 1)) * np.sin(5 * math.pi * (q + 1) / (g + 1))
+    M, P = _setup(ctx, A)
+    x, info, st = ctx.gmres(P, dev(v), precond=xab.PRECOND_NONE, tol=1e-10)
+    lam = 4 - 2 * math.cos(3 * math.pi / (g + 1)) - 2 * math.cos(5 * math.pi / (g + 1))
+    assert st == 0 and info["iters"] == 1
+    assert np.allclose(x.cpu().numpy(), v / lam, atol=1e-12, rtol=0)
+
+
+@pytest.mark.parametrize("k", [0, 3, 6])
+@pytest.mark.parametrize("mode", [xab.MODE_FP64, xab.MODE_IR])
+def test_gmres_powerlaw_vs_oracle(ctx, k, mode):
+    A = gen.powerlaw(50_000, seed=2)
+    b = np.ones(A.n)
+    ref = oracle.gmres(A, b, m=30, tol=1e-10, precond=1)
+    assert ref["status"] == 0
+    M, P = _setup(ctx, A, k)
+    x, info, st = ctx.gmres(P, dev(b), m=30, tol=1e-10, mode=mode, precond=xab.PRECOND_JACOBI)
+    assert st == 0
+    xs = x.cpu().numpy()
+    # the true residual, recomputed by the oracle's own product
+    r = b - oracle.spmv(A, xs)[0]
+    assert np.linalg.norm(r) / np.linalg.norm(b) <= 1e-10
+    assert info["true_relres"] <= 1e-10
+    # forward error: both residuals <= 1e-10 and the Jacobi-scaled matrix
+    # is well conditioned (diagonal dominance 1.1)
+    assert np.linalg.norm(xs - ref["x"]) / np.linalg.norm(ref["x"]) <= 1e-8
+    if mode == xab.MODE_FP64:
+        assert abs(info["iters"] - ref["iters"]) <= max(2, 0.2 * ref["iters"])
+    else:
+        assert info["refinements"] >= 1
+
+
+@pytest.mark.parametrize("k", [9, 10, 11])
+@pytest.mark.parametrize("mode", [xab.MODE_FP64, xab.MODE_IR])
+def test_gmres_sym_stencil(ctx, k, mode):
+    if k == 9 and mode == xab.MODE_IR:
+        pytest.skip("the atomic baseline accumulates in its output type: no FP32-out/FP64-acc form")
+    A = gen.stencil27(24, lower=True)
+    b = np.ones(A.n)
+    rp, ci, v = oracle.sym_expand(A)
+    F = gen.CSR(A.n, A.n, rp, ci, v)
+    ref = oracle.gmres(F, b, m=30, tol=1e-10, precond=1)
+    M, P = _setup(ctx, A, k)
+    x, info, st = ctx.gmres(P, dev(b), m=30, tol=1e-10, mode=mode, precond=xab.PRECOND_JACOBI)
+    assert st == 0
+    xs = x.cpu().numpy()
+    r = b - oracle.spmv(F, xs)[0]
+    assert np.linalg.norm(r) / np.linalg.norm(b) <= 1e-10
+    assert np.linalg.norm(xs - ref["x"]) / np.linalg.norm(ref["x"]) <= 1e-8
+
+
+def test_gmres_status_codes(ctx):
+    A = gen.stencil27(12, lower=False)
+    M, P = _setup(ctx, A)
+    b = dev(np.ones(A.n))
+    _, info, st = ctx.gmres(P, b, maxiter=1, tol=1e-12)
+    assert st == 1 and info["iters"] == 1 and info["status"] == 1
+    _, info, st = ctx.gmres(P, b, tol=1e-14, max_time_s=1e-9, maxiter=10 ** 6)
+    assert st in (0, 3)
+    with pytest.raises(xab.XabError) as e:
+        ctx.gmres(P, b, x=b)
+    assert e.value.status == -5
+    M64 = ctx.matrix_from_csr(A, with_f32=False)
+    P64 = ctx.plan_class(M64, 3)
+    with pytest.raises(xab.XabError) as e:
+        ctx.gmres(P64, b, mode=xab.MODE_IR)
+    assert e.value.status == -3
+
+
+def test_gmres_resume_from_x(ctx):
+    """x doubles as the initial guess: a converged x needs no further step."""
+    A = gen.powerlaw(20_000, seed=2)
+    M, P = _setup(ctx, A)
+    b = dev(np.ones(A.n))
+    x, info, st = ctx.gmres(P, b, tol=1e-10)
+    assert st == 0
+    x2, info2, st2 = ctx.gmres(P, b, x=x.clone(), tol=1e-10)
+    assert st2 == 0 and info2["iters"] == 0
+
+
+# ----------------------------------------------------------------- batch
+def _batch(nsys=12, nmin=300, nmax=3000):
+    return gen.batch(nsys, seed=4, nmin=nmin, nmax=nmax)
+
+
+def test_batch_spmv_integer_exact(ctx):
+    B = _batch()
+    rng = np.random.default_rng(1)
+    B.val = rng.integers(-8, 9, B.nnz).astype(np.float64)
+    x = gen.int_vec(B.n, 3)
+    bt = ctx.batch(B)
+    y = bt.spmv(dev(x)).cpu().numpy()
+    for k in range(B.nsys):
+        S = B.system(k)
+        r0, r1 = int(B.row_off[k]), int(B.row_off[k + 1])
+        yo, _ = oracle.spmv(S, x[r0:r1])
+        assert np.array_equal(y[r0:r1], yo)
+
+
+@pytest.mark.parametrize("graph", [True, False])
+def test_bicgstab_batch_fp64(ctx, graph):
+    B = _batch()
+    bt = ctx.batch(B)
+    b = np.ones(B.n)
+    x, per, agg, st = ctx.bicgstab(bt, dev(b), tol=1e-10, graph=graph, check_every=4)
+    assert st == 0
+    xs = x.cpu().numpy()
+    for k in range(B.nsys):
+        S = B.system(k)
+        r0, r1 = int(B.row_off[k]), int(B.row_off[k + 1])
+        ref = oracle.bicgstab(S, b[r0:r1], tol=1e-10, precond=1)
+        assert ref["status"] == 0
+        rr = b[r0:r1] - oracle.spmv(S, xs[r0:r1])[0]
+        assert np.linalg.norm(rr) / np.linalg.norm(b[r0:r1]) <= 1e-10 * 1.01
+        assert per[k]["status"] == 0 and per[k]["true_relres"] <= 1e-10 * 1.01
+        assert np.linalg.norm(xs[r0:r1] - ref["x"]) / np.linalg.norm(ref["x"]) <= 1e-8
+        assert abs(per[k]["iters"] - ref["iters"]) <= max(2, 0.25 * ref["iters"])
+
+
+def test_bicgstab_graph_equals_eager(ctx):
+    B = _batch(8)
+    bt = ctx.batch(B)
+    b = dev(np.ones(B.n))
+    x1, _, _, _ = ctx.bicgstab(bt, b, tol=1e-10, graph=True, check_every=4)
+    x2, _, _, _ = ctx.bicgstab(bt, b, tol=1e-10, graph=False, check_every=4)
+    assert torch.equal(x1, x2)
+
+
+def test_bicgstab_batch_fp32(ctx):
+    B = _batch(10)
+    bt = ctx.batch(B, dtype="f32")
+    b = np.ones(B.n)
+    x, per, agg, st = ctx.bicgstab(bt, dev(b, torch.float32), tol=1e-5, graph=True)
+    assert st == 0
+    xs = x.double().cpu().numpy()
+    for k in range(B.nsys):
+        S = B.system(k)
+        r0, r1 = int(B.row_off[k]), int(B.row_off[k + 1])
+        rr = b[r0:r1] - oracle.spmv(S, xs[r0:r1])[0]
+        assert np.linalg.norm(rr) / np.linalg.norm(b[r0:r1]) <= 2e-5
+
+
+def test_bicgstab_breakdown(ctx):
+    """Rotation [[0,-1],[1,0]] as one system: <rhat, A p> = 0 at step one."""
+    rp = np.array([0, 1, 2, 3, 4], dtype=np.int32)
+    ci = np.array([1, 0, 2, 3], dtype=np.int32)
+    v = np.array([-1.0, 1.0, 2.0, 2.0])
+    B = gen.Batch(2, np.array([0, 2, 4]), np.array([0, 2, 4]), rp, ci, v, np.zeros(2), np.zeros(2))
+    bt = ctx.batch(B)
+    x, per, agg, st = ctx.bicgstab(bt, dev(np.array([0.3, -1.7, 1.0, 1.0])), tol=1e-12, precond=xab.PRECOND_NONE,
+                                   graph=False, check_every=1)
+    assert per[0]["status"] == 2 and per[1]["status"] == 0
+    assert st == 2
+
+
+def test_batch_rejects_cross_system_columns(ctx):
+    rp = np.array([0, 1, 2], dtype=np.int32)
+    ci = np.array([1, 1], dtype=np.int32)     # row 0 of system 0 points into system 1
+    B = gen.Batch(2, np.array([0, 1, 2]), np.array([0, 1, 2]), rp, ci, np.ones(2), np.zeros(2), np.zeros(2))
+    with pytest.raises(xab.XabError) as e:
+        ctx.batch(B)
+    assert e.value.status == -4

@@ -1,0 +1,284 @@
+"""GPU parity of every SpMV implementation against the CPU oracle.
+
+Through the C ABI (Python binding).  Bars:
+  * plan arrays (work splits, segmented-scan descriptors, touch map) equal
+    the oracle's bit for bit;
+  * integer-valued A and x (every partial sum exact): y equals the oracle
+    bit for bit for every variant;
+  * random FP64 values: |y - y_oracle| <= 1e-12 * sum_k |a_ik x_k| per row,
+    and y_i is exactly 0 where that sum is 0;
+  * FP32 values: the per-row error relative to the same sum, against the
+    oracle run on the FP32-rounded inputs (accumulation error) and on the
+    original FP64 inputs (total error), under the bounds stated per test;
+  * two runs give identical bits (all variants but the atomic baseline).
+"""
+import numpy as np
+import pytest
+
+import gen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+xab = pytest.importorskip("paper_2405_01599_amd")
+
+U32 = 2.0 ** -24
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return xab.Context(0)
+
+
+def dev(a, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0").to(dtype)
+
+
+def _tiny(lens, ncols=None, seed=0, intvals=True):
+    rng = np.random.default_rng(seed)
+    n = len(lens)
+    ncols = ncols or max(n, max(lens) if lens else 1)
+    rp = np.zeros(n + 1, dtype=np.int32)
+    rp[1:] = np.cumsum(lens)
+    ci = np.concatenate([np.sort(rng.choice(ncols, size=l, replace=False)) for l in lens] + [np.zeros(0)])
+    v = rng.integers(-8, 9, int(rp[-1])).astype(np.float64) if intvals else rng.standard_normal(int(rp[-1]))
+    return gen.CSR(n, ncols, rp, ci.astype(np.int32), v, name="tiny")
+
+
+def general_suite():
+    out = {
+        "tiny_mixed": _tiny([0, 3, 17, 0, 1, 1, 0, 40, 2, 0, 0, 16, 16, 1] * 7, ncols=120),
+        "empty_edges": _tiny([16, 0, 0, 16, 0, 16, 0] * 40, ncols=300),
+        "trailing_empty": _tiny([5, 7] * 50 + [0] * 37, ncols=200),
+        "all_empty": _tiny([0] * 33, ncols=33),
+        "one_long_row": _tiny([1, 3000, 1, 2], ncols=4000),
+        "n1": _tiny([77], ncols=100),
+        "lap2d": gen.laplacian2d(64),
+        "powerlaw": gen.powerlaw(60_000, seed=2),
+        "trans4": gen.trans4_like(),
+        "blockdiag": gen.blockdiag(20_000, 3),
+    }
+    return out
+
+
+GENERAL = general_suite()
+GENERAL_CLASSES = list(range(9))
+
+
+def _int_version(A, seed=5):
+    rng = np.random.default_rng(seed)
+    B = gen.CSR(A.n, A.ncols, A.rowptr, A.colind, rng.integers(-8, 9, A.nnz).astype(np.float64),
+                sym_lower=A.sym_lower, name=A.name)
+    return B
+
+
+@pytest.mark.parametrize("name", sorted(GENERAL))
+@pytest.mark.parametrize("k", GENERAL_CLASSES)
+def test_general_integer_bitexact(ctx, name, k):
+    A = _int_version(GENERAL[name])
+    x = gen.int_vec(A.ncols, 9)
+    yo, _ = oracle.spmv(A, x)
+    M = ctx.matrix_from_csr(A)
+    P = ctx.plan_class(M, k)
+    y = ctx.spmv(P, dev(x))
+    torch.cuda.synchronize()
+    assert np.array_equal(y.cpu().numpy(), yo), f"class {k} on {name}"
+
+
+@pytest.mark.parametrize("name", sorted(GENERAL))
+@pytest.mark.parametrize("k", GENERAL_CLASSES)
+def test_general_fp64_gate_and_determinism(ctx, name, k):
+    A = GENERAL[name]
+    x = gen.uniform_vec(A.ncols, 12)
+    yo, s = oracle.spmv(A, x)
+    M = ctx.matrix_from_csr(A)
+    P = ctx.plan_class(M, k)
+    xd = dev(x)
+    y1 = ctx.spmv(P, xd).cpu().numpy()
+    y2 = ctx.spmv(P, xd).cpu().numpy()
+    err = np.abs(y1 - yo)
+    assert np.all(err <= 1e-12 * s), f"max rel {np.max(err / np.maximum(s, 1e-300))}"
+    assert np.all(y1[s == 0] == 0.0)
+    assert np.array_equal(y1, y2)
+
+
+def test_nnz_plan_bitexact(ctx):
+    for name, A in GENERAL.items():
+        M = ctx.matrix_from_csr(A)
+        for T in (64, 2048, 8192):
+            P = ctx.plan(M, xab.NNZ, tile_nnz=T)
+            assert np.array_equal(P.array(0), oracle.plan_nnz(A.rowptr, T)), (name, T)
+
+
+def test_bss_plan_bitexact(ctx):
+    for name, A in GENERAL.items():
+        M = ctx.matrix_from_csr(A)
+        for J in (1, 4, 8, 16, 32):
+            P = ctx.plan(M, xab.BSS, j_per_lane=J)
+            row_lo, tile_row, carry = oracle.plan_bss(A.rowptr, 256 * J)
+            assert np.array_equal(P.array(1), row_lo), (name, J)
+            assert np.array_equal(P.array(2), tile_row), (name, J)
+            assert np.array_equal(P.array(3), carry), (name, J)
+
+
+@pytest.mark.parametrize("J", [1, 2, 4, 8, 16, 32])
+def test_bss_all_lane_widths(ctx, J):
+    A = _int_version(gen.trans4_like())
+    x = gen.int_vec(A.ncols, 2)
+    yo, _ = oracle.spmv(A, x)
+    M = ctx.matrix_from_csr(A)
+    P = ctx.plan(M, xab.BSS, j_per_lane=J)
+    assert np.array_equal(ctx.spmv(P, dev(x)).cpu().numpy(), yo)
+
+
+@pytest.mark.parametrize("S", [1, 2, 4, 8, 16, 32, 64])
+def test_row_all_lane_counts(ctx, S):
+    A = _int_version(gen.powerlaw(20_000, seed=2))
+    x = gen.int_vec(A.ncols, 2)
+    yo, _ = oracle.spmv(A, x)
+    M = ctx.matrix_from_csr(A)
+    P = ctx.plan(M, xab.ROW, lanes_per_row=S)
+    assert np.array_equal(ctx.spmv(P, dev(x)).cpu().numpy(), yo)
+
+
+# ----------------------------------------------------------------- FP32
+FP32_COMBOS = [  # (y dtype, acc) with x and values FP32
+    (torch.float32, xab.F32),
+    (torch.float32, xab.F64),
+    (torch.float64, xab.F64),
+]
+
+
+@pytest.mark.parametrize("name", ["powerlaw", "trans4", "lap2d", "one_long_row"])
+@pytest.mark.parametrize("k", [0, 1, 3, 6, 8])
+@pytest.mark.parametrize("combo", range(3))
+def test_general_fp32(ctx, name, k, combo):
+    ydt, acc = FP32_COMBOS[combo]
+    A = GENERAL[name]
+    x64 = gen.uniform_vec(A.ncols, 12)
+    x32 = x64.astype(np.float32)
+    A32 = gen.CSR(A.n, A.ncols, A.rowptr, A.colind, A.val.astype(np.float32).astype(np.float64))
+    y_rounded, s_r = oracle.spmv(A32, x32.astype(np.float64))
+    y_exact, s = oracle.spmv(A, x64)
+    M = ctx.matrix_from_csr(A, with_f32=True)
+    P = ctx.plan_class(M, k)
+    y = ctx.spmv(P, dev(x32, torch.float32), ydtype=ydt, acc=acc).double().cpu().numpy()
+    lens = np.diff(A.rowptr).astype(np.float64)
+    # accumulation error alone (rounded inputs): recursive-summation bound
+    # (len + 2) u for FP32 accumulation; FP64 accumulation only rounds the
+    # result (and BSS/row partials) once more when y is FP32
+    if acc == xab.F32:
+        bound_acc = (lens + 2) * U32
+    elif ydt == torch.float32:
+        bound_acc = np.full(A.n, 1.01 * U32)
+    else:
+        bound_acc = np.full(A.n, 1e-12)
+    ea = np.abs(y - y_rounded)
+    assert np.all(ea <= bound_acc * s_r + 0.0)
+    # total error against the FP64 inputs: value and x rounding add 2u
+    et = np.abs(y - y_exact)
+    assert np.all(et <= (bound_acc + 2.01 * U32) * s)
+
+
+# ----------------------------------------------------------------- symmetric
+def sym_suite():
+    return {
+        "lap2d_lower": gen.laplacian2d(64, lower=True),
+        "st27_16": gen.stencil27(16, lower=True),
+        "st27_24": gen.stencil27(24, lower=True),
+        "banded_lower": gen.banded(30_000, 40, 7, lower=True),
+        "tiny_sym": gen.banded(37, 3, 2, lower=True),
+    }
+
+
+SYM = sym_suite()
+SYM_CLASSES = [9, 10, 11]
+
+
+@pytest.mark.parametrize("name", sorted(SYM))
+@pytest.mark.parametrize("k", SYM_CLASSES)
+def test_sym_integer_bitexact(ctx, name, k):
+    A = _int_version(SYM[name])
+    x = gen.int_vec(A.n, 4)
+    yo, _ = oracle.spmv(A, x)
+    M = ctx.matrix_from_csr(A)
+    P = ctx.plan_class(M, k)
+    y = ctx.spmv(P, dev(x)).cpu().numpy()
+    assert np.array_equal(y, yo)
+
+
+@pytest.mark.parametrize("name", sorted(SYM))
+@pytest.mark.parametrize("k", SYM_CLASSES)
+def test_sym_fp64_gate(ctx, name, k):
+    A = SYM[name]
+    x = gen.uniform_vec(A.n, 13)
+    yo, s = oracle.spmv(A, x)
+    M = ctx.matrix_from_csr(A)
+    P = ctx.plan_class(M, k)
+    y = ctx.spmv(P, dev(x)).cpu().numpy()
+    assert np.all(np.abs(y - yo) <= 1e-12 * s)
+
+
+@pytest.mark.parametrize("name", sorted(SYM))
+def test_sym_lower_equals_full(ctx, name):
+    """Invariant: symmetric lower storage gives the full-storage product."""
+    L = SYM[name]
+    rp, ci, v = oracle.sym_expand(L)
+    F = gen.CSR(L.n, L.n, rp, ci, v)
+    x = gen.uniform_vec(L.n, 3)
+    ML, MF = ctx.matrix_from_csr(L), ctx.matrix_from_csr(F)
+    yl = ctx.spmv(ctx.plan_class(ML, 11), dev(x)).cpu().numpy()
+    yf = ctx.spmv(ctx.plan_class(MF, 3), dev(x)).cpu().numpy()
+    _, s = oracle.spmv(F, x)
+    assert np.all(np.abs(yl - yf) <= 2e-12 * s)
+
+
+@pytest.mark.parametrize("name", sorted(SYM))
+@pytest.mark.parametrize("C,T,R", [(64, 16384, 2048), (256, 16384, 2048), (16, 512, 64), (1024, 4096, 300)])
+def test_sym_plan_bitexact(ctx, name, C, T, R):
+    A = SYM[name]
+    M = ctx.matrix_from_csr(A)
+    try:
+        P = ctx.plan(M, xab.SYM_S3, col_block=C, tile_nnz=T, tile_rows=R)
+    except xab.XabError as e:
+        assert e.status == -6  # transpose part does not fit this block size
+        return
+    want = oracle.plan_sym(A, T, R, C)
+    assert np.array_equal(P.array(0), want["b"])
+    assert np.array_equal(P.array(4), want["tm_ptr"])
+    assert np.array_equal(P.array(5), want["tm_tile"])
+    assert np.array_equal(P.array(6), want["tile_ptr"])
+    assert np.array_equal(P.array(7), want["tile_blk"])
+    assert np.array_equal(P.array(8), want["tile_slot"])
+    x = gen.int_vec(A.n, 1)
+    Ai = _int_version(A)
+    Mi = ctx.matrix_from_csr(Ai)
+    Pi = ctx.plan(Mi, xab.SYM_S3, col_block=C, tile_nnz=T, tile_rows=R)
+    assert np.array_equal(ctx.spmv(Pi, dev(x)).cpu().numpy(), oracle.spmv(Ai, x)[0])
+
+
+@pytest.mark.parametrize("k", [10, 11])
+@pytest.mark.parametrize("combo", range(3))
+def test_sym_fp32(ctx, k, combo):
+    ydt, acc = FP32_COMBOS[combo]
+    A = SYM["st27_24"]
+    x64 = gen.uniform_vec(A.n, 13)
+    x32 = x64.astype(np.float32)
+    y_exact, s = oracle.spmv(A, x64)
+    M = ctx.matrix_from_csr(A, with_f32=True)
+    y = ctx.spmv(ctx.plan_class(M, k), dev(x32, torch.float32), ydtype=ydt, acc=acc).double().cpu().numpy()
+    L = np.diff(oracle.sym_expand(A)[0]).astype(np.float64)
+    bound = (L + 4) * U32 if acc == xab.F32 else np.full(A.n, 4.01 * U32)
+    assert np.all(np.abs(y - y_exact) <= bound * s)
+
+
+def test_sym_determinism(ctx):
+    A = SYM["st27_24"]
+    x = dev(gen.uniform_vec(A.n, 1))
+    M = ctx.matrix_from_csr(A)
+    P = ctx.plan_class(M, 10)
+    a = ctx.spmv(P, x).cpu().numpy()
+    b = ctx.spmv(P, x).cpu().numpy()
+    _, s = oracle.spmv(A, x.cpu().numpy())
+    assert np.all(np.abs(a - b) <= 1e-15 * s)
