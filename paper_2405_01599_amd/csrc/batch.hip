@@ -28,15 +28,6 @@ struct StoreSink {
     __device__ void entry(int32_t, int32_t, VT) {}
 };
 
-__device__ __forceinline__ int32_t lb_range(const int32_t *rowptr, int32_t lo, int32_t hi, int64_t target) {
-    while (lo < hi) {
-        int32_t mid = lo + (hi - lo) / 2;
-        if (rowptr[mid] >= target) hi = mid;
-        else lo = mid + 1;
-    }
-    return lo;
-}
-
 // Persistent nnz-split SpMV: the grid walks the tiles [b[t], b[t+1]) of the
 // global matrix; a tile whose first and last systems are inactive (and
 // which spans at most two systems) is skipped.
@@ -62,21 +53,25 @@ __global__ __launch_bounds__(kNT) void k_batch_spmv(const int32_t *__restrict__ 
         Seg<double> seed{0, 0.0, -1};
         int32_t rlo = r0;
         int64_t A = s - (s % CH);
+        xab::Run<kChunkJ, T, T> R;
+        xab::run_load<kNT, kChunkJ>(R, A, s, e < A + CH ? e : A + CH, colind, val);
         for (;;) {
             const int64_t Aend = A + CH;
             const bool last = Aend >= e;
-            const int32_t rhi = last ? r1 : lb_range(rowptr, rlo, r1, Aend);
-            __syncthreads();
             xab::clear_heads<kNT, kChunkJ>(head_row);
+            const xab::RowProbe probe = xab::first_row<kNT>(rowptr, rlo, r1);
+            xab::run_gather(R, x);
             __syncthreads();
-            xab::mark_heads<kNT>(rowptr, rlo, rhi, A, head_row, sink);
-            __syncthreads();
-            xab::ChunkResult<double> res = xab::seg_chunk<kNT, kChunkJ, T, T, double>(
-                A, s > A ? s : A, e < Aend ? e : Aend, colind, val, x, head_row, seed, wave_tot, sink);
+            const int32_t rhi = xab::mark_rows<kNT>(rowptr, probe, rlo, r1, A, Aend, last, head_row, sink);
+            xab::Run<kChunkJ, T, T> Rn;
+            if (!last) xab::run_load<kNT, kChunkJ>(Rn, Aend, Aend, e < Aend + CH ? e : Aend + CH, colind, val);
+            xab::ChunkResult<double> res =
+                xab::seg_chunk<kNT, kChunkJ, T, T, double>(R, head_row, seed, wave_tot, sink);
             seed = res.state;
             rlo = rhi;
             if (last) break;
             A = Aend;
+            R = Rn;
         }
         if (threadIdx.x == 0 && seed.f) y[seed.r] = (T)seed.v;
     }

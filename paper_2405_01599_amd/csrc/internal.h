@@ -67,6 +67,9 @@ struct xab_plan {
     int32_t *tile_minblk = nullptr;
     void *partial = nullptr;   // ntouch * col_block acc-type values
     size_t partial_elem = 0;   // bytes per element allocated (4 or 8)
+    int32_t s3_own_cap = 0;    // most rows of a tile
+    int32_t s3_ext_cap = 0;    // most touched blocks of a tile times col_block
+    int32_t s3_lut_cap = 0;    // widest span of touched block ids of a tile
 };
 
 struct xab_batch {

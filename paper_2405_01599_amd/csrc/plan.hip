@@ -393,13 +393,33 @@ int xab_build_plan(xab_ctx *ctx, const xab_matrix *A, xab_variant v, const xab_p
         // order the (tile, block) pairs by block, then tile: a stable
         // counting sort of the per-tile lists
         std::vector<int32_t> h_tptr(P + 1), h_blk(nt), h_slot(nt), h_tm_tile(nt), h_tm_ptr(pl->nblk + 1, 0);
+        std::vector<int32_t> h_b(P + 1);
         e = hipMemcpyAsync(h_tptr.data(), pl->tile_ptr, sizeof(int32_t) * (P + 1), hipMemcpyDeviceToHost, st);
         if (e == hipSuccess)
             e = hipMemcpyAsync(h_blk.data(), pl->tile_blk, sizeof(int32_t) * nt, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(h_b.data(), pl->b, sizeof(int32_t) * (P + 1), hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         xab_dfree(ctx, cnt);
         xab_dfree(ctx, bitmap);
         CHECKED(hip_ok(ctx, e, "touch map read-back"));
+        // LDS the kernel needs: most rows, most touched blocks, widest block span
+        int32_t own = 1, nbmax = 0, span = 1;
+        for (int32_t t = 0; t < P; ++t) {
+            own = std::max(own, h_b[t + 1] - h_b[t]);
+            int32_t k = h_tptr[t + 1] - h_tptr[t];
+            nbmax = std::max(nbmax, k);
+            if (k > 0) span = std::max(span, h_blk[h_tptr[t + 1] - 1] - h_blk[h_tptr[t]] + 1);
+        }
+        pl->s3_own_cap = own;
+        pl->s3_ext_cap = nbmax * C;
+        pl->s3_lut_cap = (span + 7) / 8 * 8;
+        size_t lds = xab::sym::kFixedBytes + 16 + 8 * (2 * (size_t)pl->s3_own_cap + pl->s3_ext_cap) + 2 * (size_t)pl->s3_lut_cap;
+        if (lds > (size_t)xab::sym::kLdsCap) {
+            free_plan_arrays(ctx, pl);
+            delete pl;
+            return xab_fail(ctx, XAB_E_UNSUPPORTED, "symmetric tile needs %zu bytes of LDS (col_block %d)", lds, C);
+        }
         for (int64_t q = 0; q < pl->ntouch; ++q) h_tm_ptr[h_blk[q] + 1]++;
         for (int64_t c = 0; c < pl->nblk; ++c) h_tm_ptr[c + 1] += h_tm_ptr[c];
         std::vector<int32_t> fill(h_tm_ptr.begin(), h_tm_ptr.end() - 1);

@@ -11,7 +11,7 @@
 // waits on a row boundary and rows of any length cost the same per entry.
 //
 // Heads are given as head_row[q - A] = row starting at entry q, or -1
-// (written by mark_heads from rowptr; empty rows never start a segment).
+// (written by mark_rows from rowptr; empty rows never start a segment).
 //
 // The caller seeds the scan with the row left open by the previous chunk
 // (K2, symmetric tiles) or with nothing (segmented-scan tiles), and gets
@@ -43,16 +43,47 @@ __device__ __forceinline__ void load_run_full(const T *__restrict__ p, int64_t b
     }
 }
 
-// Mark row starts of rows [rlo, rhi) in head_row (indices relative to A);
-// empty rows go to sink.empty_row.  head_row must hold -1 everywhere first.
+// Row starts of a chunk [A, Aend).  Candidate rows are taken 256 at a time
+// from `rlo`; a candidate starts in the chunk when r < rend and (all or
+// rowptr[r] < Aend); rowptr is monotone, so these form a prefix and a
+// block-wide count gives the next first row.  Non-empty rows write
+// head_row[rowptr[r] - A] = r, empty rows go to sink.empty_row.  The first
+// candidate's two row pointers (q0, q1) are loaded by the caller
+// (first_row) ahead of other work to overlap their latency; head_row must
+// hold -1 everywhere and that clearing must be complete (a barrier) first.
+// Returns one past the last row that starts in the chunk.
+struct RowProbe {
+    int32_t r, q0, q1;
+};
+
+template <int NT>
+__device__ __forceinline__ RowProbe first_row(const int32_t *__restrict__ rowptr, int32_t rlo, int32_t rend) {
+    RowProbe p;
+    p.r = rlo + (int32_t)threadIdx.x;
+    p.q0 = p.r < rend ? rowptr[p.r] : 0;
+    p.q1 = p.r < rend ? rowptr[p.r + 1] : 0;
+    return p;
+}
+
 template <int NT, class Sink>
-__device__ __forceinline__ void mark_heads(const int32_t *__restrict__ rowptr, int32_t rlo, int32_t rhi, int64_t A,
-                                           int32_t *head_row, Sink &sink) {
-    for (int32_t r = rlo + (int32_t)threadIdx.x; r < rhi; r += NT) {
-        int32_t q0 = rowptr[r], q1 = rowptr[r + 1];
-        if (q1 > q0) head_row[q0 - A] = r;
-        else sink.empty_row(r);
+__device__ __forceinline__ int32_t mark_rows(const int32_t *__restrict__ rowptr, RowProbe p, int32_t rlo,
+                                             int32_t rend, int64_t A, int64_t Aend, bool all, int32_t *head_row,
+                                             Sink &sink) {
+    int32_t rhi = rlo;
+    for (;;) {
+        const bool pred = p.r < rend && (all || p.q0 < Aend);
+        if (pred) {
+            if (p.q1 > p.q0) head_row[p.q0 - A] = p.r;
+            else sink.empty_row(p.r);
+        }
+        const int cnt = __syncthreads_count(pred);
+        rhi += cnt;
+        if (cnt < NT) break;
+        p.r += NT;
+        p.q0 = p.r < rend ? rowptr[p.r] : 0;
+        p.q1 = p.r < rend ? rowptr[p.r + 1] : 0;
     }
+    return rhi;
 }
 
 template <int NT, int J>
@@ -68,35 +99,50 @@ struct ChunkResult {
     int has_lead;   // this lane produced `lead`
 };
 
-template <int NT, int J, class VT, class XT, class AT, class Sink>
-__device__ __forceinline__ ChunkResult<AT> seg_chunk(int64_t A, int64_t c0, int64_t c1,
-                                                     const int32_t *__restrict__ colind,
-                                                     const VT *__restrict__ val, const XT *__restrict__ x,
-                                                     const int32_t *head_row, Seg<AT> seed, Seg<AT> *wave_tot,
-                                                     Sink &sink) {
-    constexpr int NW = NT / kWave;
-    const int tid = threadIdx.x, lane = tid % kWave, wid = tid / kWave;
-    const int64_t base = A + (int64_t)tid * J;
-
+// The lane's J entries of a chunk: values, columns and gathered x values
+// (dead slots hold v = 0, col = -1, xv = 0).  Loading is split in two so
+// kernels can overlap the latencies: run_load issues the value / column
+// loads, run_gather the x gathers (it waits only for the columns).
+template <int J, class VT, class XT>
+struct Run {
     VT v[J];
     int32_t col[J];
-    AT p[J];
-    int32_t hr[J];
+    XT xv[J];
+};
+
+template <int NT, int J, class VT, class XT>
+__device__ __forceinline__ void run_load(Run<J, VT, XT> &R, int64_t A, int64_t c0, int64_t c1,
+                                         const int32_t *__restrict__ colind, const VT *__restrict__ val) {
+    const int64_t base = A + (int64_t)threadIdx.x * J;
     if (base >= c0 && base + J <= c1) {
-        load_run_full<VT, J>(val, base, v);
-        load_run_full<int32_t, J>(colind, base, col);
-#pragma unroll
-        for (int k = 0; k < J; ++k) p[k] = (AT)v[k] * (AT)x[col[k]];
+        load_run_full<int32_t, J>(colind, base, R.col);
+        load_run_full<VT, J>(val, base, R.v);
     } else {
 #pragma unroll
         for (int k = 0; k < J; ++k) {
             int64_t q = base + k;
             bool live = q >= c0 && q < c1;
-            v[k] = live ? __builtin_nontemporal_load(val + q) : VT(0);
-            col[k] = live ? __builtin_nontemporal_load(colind + q) : -1;
-            p[k] = live ? (AT)v[k] * (AT)x[col[k]] : AT(0);
+            R.col[k] = live ? __builtin_nontemporal_load(colind + q) : -1;
+            R.v[k] = live ? __builtin_nontemporal_load(val + q) : VT(0);
         }
     }
+}
+
+template <int J, class VT, class XT>
+__device__ __forceinline__ void run_gather(Run<J, VT, XT> &R, const XT *__restrict__ x) {
+#pragma unroll
+    for (int k = 0; k < J; ++k) R.xv[k] = R.col[k] >= 0 ? x[R.col[k]] : XT(0);
+}
+
+template <int NT, int J, class VT, class XT, class AT, class Sink>
+__device__ __forceinline__ ChunkResult<AT> seg_chunk(const Run<J, VT, XT> &R, const int32_t *head_row,
+                                                     Seg<AT> seed, Seg<AT> *wave_tot, Sink &sink) {
+    constexpr int NW = NT / kWave;
+    const int tid = threadIdx.x, lane = tid % kWave, wid = tid / kWave;
+    AT p[J];
+    int32_t hr[J];
+#pragma unroll
+    for (int k = 0; k < J; ++k) p[k] = (AT)R.v[k] * (AT)R.xv[k];
 #pragma unroll
     for (int k = 0; k < J; ++k) hr[k] = head_row[tid * J + k];
 
@@ -147,7 +193,7 @@ __device__ __forceinline__ ChunkResult<AT> seg_chunk(int64_t A, int64_t c0, int6
         } else {
             acc += p[k];
         }
-        sink.entry(row, col[k], v[k]);
+        sink.entry(row, R.col[k], R.v[k]);
     }
     return res;
 }

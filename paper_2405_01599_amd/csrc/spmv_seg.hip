@@ -10,7 +10,20 @@ namespace xab {
 namespace {
 
 constexpr int kNT = 256;      // threads per workgroup
-constexpr int kChunkJ = 8;    // entries per lane per chunk (nnz-split, symmetric)
+constexpr int kChunkJ = 8;    // entries per lane per chunk (nnz-split)
+constexpr int kSymJ = 4;      // entries per lane per chunk (symmetric: keeps v and col live)
+
+// dynamic LDS layout of the symmetric kernel: heads, wave totals, then
+// own[own_cap], ext[ext_cap] (accumulation type), lut[lut_cap] (int16)
+__host__ __device__ constexpr int sym_off_wave() { return kNT * kSymJ * 4; }
+template <class AT>
+__host__ __device__ constexpr int sym_off_own() {
+    return (sym_off_wave() + (kNT / kWave) * (int)sizeof(Seg<AT>) + 15) / 16 * 16;
+}
+template <class AT>
+size_t sym_lds_bytes(int own_cap, int ext_cap, int lut_cap) {
+    return (size_t)sym_off_own<AT>() + sizeof(AT) * (2 * (size_t)own_cap + ext_cap) + 2 * (size_t)lut_cap;
+}
 
 template <class YT, class AT>
 struct StoreSink {
@@ -20,16 +33,6 @@ struct StoreSink {
     template <class VT>
     __device__ void entry(int32_t, int32_t, VT) {}
 };
-
-// smallest r in [lo, hi] with rowptr[r] >= target (rowptr[hi] >= target assumed)
-__device__ __forceinline__ int32_t lb_range(const int32_t *rowptr, int32_t lo, int32_t hi, int64_t target) {
-    while (lo < hi) {
-        int32_t mid = lo + (hi - lo) / 2;
-        if (rowptr[mid] >= target) hi = mid;
-        else lo = mid + 1;
-    }
-    return lo;
-}
 
 // ------------------------------------------------------------------ nnz-split
 // Workgroup p owns whole rows [b[p], b[p+1]) (about T entries).  It walks
@@ -52,20 +55,25 @@ __global__ __launch_bounds__(kNT) void k_spmv_nnz(const int32_t *__restrict__ ro
     Seg<AT> seed{0, AT(0), -1};
     int32_t rlo = r0;
     int64_t A = s - (s % CH);
+    Run<kChunkJ, VT, XT> R;
+    run_load<kNT, kChunkJ>(R, A, s, e < A + CH ? e : A + CH, colind, val);
     for (;;) {
         const int64_t Aend = A + CH;
         const bool last = Aend >= e;
-        const int32_t rhi = last ? r1 : lb_range(rowptr, rlo, r1, Aend);
         clear_heads<kNT, kChunkJ>(head_row);
+        const RowProbe probe = first_row<kNT>(rowptr, rlo, r1);
+        run_gather(R, x);
         __syncthreads();
-        mark_heads<kNT>(rowptr, rlo, rhi, A, head_row, sink);
-        __syncthreads();
-        ChunkResult<AT> res = seg_chunk<kNT, kChunkJ, VT, XT, AT>(A, s > A ? s : A, e < Aend ? e : Aend, colind,
-                                                                  val, x, head_row, seed, wave_tot, sink);
+        const int32_t rhi = mark_rows<kNT>(rowptr, probe, rlo, r1, A, Aend, last, head_row, sink);
+        // the next chunk's loads fly while this one is scanned
+        Run<kChunkJ, VT, XT> Rn;
+        if (!last) run_load<kNT, kChunkJ>(Rn, Aend, Aend, e < Aend + CH ? e : Aend + CH, colind, val);
+        ChunkResult<AT> res = seg_chunk<kNT, kChunkJ, VT, XT, AT>(R, head_row, seed, wave_tot, sink);
         seed = res.state;
         rlo = rhi;
         if (last) break;
         A = Aend;
+        R = Rn;
     }
     if (threadIdx.x == 0 && seed.f) y[seed.r] = (YT)seed.v;
 }
@@ -91,12 +99,17 @@ __global__ __launch_bounds__(kNT) void k_spmv_bss(const int32_t *__restrict__ ro
     const int64_t A = t * T;
     const int64_t c1 = (A + T < nnz) ? A + T : nnz;
     StoreSink<YT, AT> sink{y};
+    // loads first; the row-pointer probe and the gathers overlap them
+    Run<J, VT, XT> R;
+    run_load<kNT, J>(R, A, A, c1, colind, val);
     clear_heads<kNT, J>(head_row);
+    const int32_t rlo = row_lo[t], rend = row_lo[t + 1];
+    const RowProbe probe = first_row<kNT>(rowptr, rlo, rend);
+    run_gather(R, x);
     __syncthreads();
-    mark_heads<kNT>(rowptr, row_lo[t], row_lo[t + 1], A, head_row, sink);
-    __syncthreads();
+    mark_rows<kNT>(rowptr, probe, rlo, rend, A, A + T, true, head_row, sink);
     Seg<AT> seed{0, AT(0), -1};
-    ChunkResult<AT> res = seg_chunk<kNT, J, VT, XT, AT>(A, A, c1, colind, val, x, head_row, seed, wave_tot, sink);
+    ChunkResult<AT> res = seg_chunk<kNT, J, VT, XT, AT>(R, head_row, seed, wave_tot, sink);
     const int32_t cr = carry_row[t];
     if (res.has_lead && cr >= 0) carry_val[t] = res.lead;
     if (threadIdx.x == 0) {
@@ -137,6 +150,9 @@ __global__ void k_bss_fixup(YT *__restrict__ y, int64_t P, const int32_t *__rest
 // touched.  At the end the tile writes its rows of y and its block
 // partials; the block-reduce kernel adds, per touched block, the partials
 // of the later tiles in ascending tile order.
+// LDS is sized per plan (dynamic shared memory): own_cap = most rows in a
+// tile, ext_cap = most touched blocks in a tile times C, lut_cap = widest
+// span of touched block ids in a tile.
 template <class VT, class XT, class YT, class AT, int C>
 __global__ __launch_bounds__(kNT) void k_spmv_sym_s3(const int32_t *__restrict__ rowptr,
                                                      const int32_t *__restrict__ colind, const VT *__restrict__ val,
@@ -146,15 +162,16 @@ __global__ __launch_bounds__(kNT) void k_spmv_sym_s3(const int32_t *__restrict__
                                                      const int32_t *__restrict__ tile_blk,
                                                      const int32_t *__restrict__ tile_slot,
                                                      const int32_t *__restrict__ tile_minblk,
-                                                     AT *__restrict__ partial) {
-    constexpr int CH = kNT * kChunkJ;
-    constexpr int kOwnCap = sym::kRowCap;
-    constexpr int kExtCap = sym::kExtCap;
-    __shared__ int32_t head_row[CH];
-    __shared__ Seg<AT> wave_tot[kNT / kWave];
-    __shared__ AT own[kOwnCap];
-    __shared__ AT ext[kExtCap];
-    __shared__ int16_t lut[sym::kLutMax];
+                                                     AT *__restrict__ partial, int own_cap, int ext_cap,
+                                                     int lut_cap) {
+    constexpr int CH = kNT * kSymJ;
+    extern __shared__ __align__(16) char smem[];
+    int32_t *head_row = (int32_t *)smem;
+    Seg<AT> *wave_tot = (Seg<AT> *)(smem + sym_off_wave());
+    AT *own = (AT *)(smem + sym_off_own<AT>());
+    AT *xs = own + own_cap;  // x of the tile's own rows
+    AT *ext = xs + own_cap;
+    int16_t *lut = (int16_t *)(ext + ext_cap);
     const int64_t p = xcd_remap(blockIdx.x, P);
     const int32_t r0 = b[p], r1 = b[p + 1];
     if (r0 >= r1) return;
@@ -163,9 +180,12 @@ __global__ __launch_bounds__(kNT) void k_spmv_sym_s3(const int32_t *__restrict__
     const int32_t nb = q1 - q0;
     const int32_t minblk = tile_minblk[p];
     const int tid = threadIdx.x;
-    for (int i = tid; i < r1 - r0; i += kNT) own[i] = AT(0);
+    for (int i = tid; i < r1 - r0; i += kNT) {
+        own[i] = AT(0);
+        xs[i] = (AT)x[r0 + i];
+    }
     for (int i = tid; i < nb * C; i += kNT) ext[i] = AT(0);
-    for (int i = tid; i < sym::kLutMax; i += kNT) lut[i] = 0;
+    for (int i = tid; i < lut_cap; i += kNT) lut[i] = 0;
     __syncthreads();
     for (int i = tid; i < nb; i += kNT) lut[tile_blk[q0 + i] - minblk] = (int16_t)i;
 
@@ -173,41 +193,39 @@ __global__ __launch_bounds__(kNT) void k_spmv_sym_s3(const int32_t *__restrict__
         AT *own;
         AT *ext;
         const int16_t *lut;
-        const XT *x;
+        const AT *xs;
         int32_t r0, minblk;
-        int32_t xrow;
-        AT xr;
         __device__ void row_done(int32_t r, AT v) { atomicAdd(&own[r - r0], v); }
         __device__ void empty_row(int32_t) {}
         __device__ void entry(int32_t row, int32_t j, VT v) {
             if (j < 0 || j >= row) return;  // dead slot or diagonal
-            if (row != xrow) {
-                xrow = row;
-                xr = (AT)x[row];
-            }
-            AT tv = (AT)v * xr;
+            AT tv = (AT)v * xs[row - r0];
             if (j >= r0) atomicAdd(&own[j - r0], tv);
             else atomicAdd(&ext[(int)lut[j / C - minblk] * C + (j % C)], tv);
         }
-    } sink{own, ext, lut, x, r0, minblk, -1, AT(0)};
+    } sink{own, ext, lut, xs, r0, minblk};
 
     Seg<AT> seed{0, AT(0), -1};
     int32_t rlo = r0;
     int64_t A = s - (s % CH);
+    Run<kSymJ, VT, XT> R;
+    run_load<kNT, kSymJ>(R, A, s, e < A + CH ? e : A + CH, colind, val);
     for (;;) {
         const int64_t Aend = A + CH;
         const bool last = Aend >= e;
-        const int32_t rhi = last ? r1 : lb_range(rowptr, rlo, r1, Aend);
-        clear_heads<kNT, kChunkJ>(head_row);
+        clear_heads<kNT, kSymJ>(head_row);
+        const RowProbe probe = first_row<kNT>(rowptr, rlo, r1);
+        run_gather(R, x);
         __syncthreads();
-        mark_heads<kNT>(rowptr, rlo, rhi, A, head_row, sink);
-        __syncthreads();
-        ChunkResult<AT> res = seg_chunk<kNT, kChunkJ, VT, XT, AT>(A, s > A ? s : A, e < Aend ? e : Aend, colind,
-                                                                  val, x, head_row, seed, wave_tot, sink);
+        const int32_t rhi = mark_rows<kNT>(rowptr, probe, rlo, r1, A, Aend, last, head_row, sink);
+        Run<kSymJ, VT, XT> Rn;
+        if (!last) run_load<kNT, kSymJ>(Rn, Aend, Aend, e < Aend + CH ? e : Aend + CH, colind, val);
+        ChunkResult<AT> res = seg_chunk<kNT, kSymJ, VT, XT, AT>(R, head_row, seed, wave_tot, sink);
         seed = res.state;
         rlo = rhi;
         if (last) break;
         A = Aend;
+        R = Rn;
     }
     if (tid == 0 && seed.f) atomicAdd(&own[seed.r - r0], seed.v);
     __syncthreads();
@@ -275,9 +293,12 @@ int launch_bss(xab_ctx *ctx, const xab_plan *pl, const VT *val, const XT *x, YT 
 template <class VT, class XT, class YT, class AT, int C>
 static int launch_s3_c(xab_ctx *ctx, const xab_plan *pl, const VT *val, const XT *x, YT *y) {
     const xab_matrix *A = pl->A;
-    hipLaunchKernelGGL((k_spmv_sym_s3<VT, XT, YT, AT, C>), dim3((unsigned)pl->P), dim3(kNT), 0, ctx->stream,
+    const size_t lds = sym_lds_bytes<AT>(pl->s3_own_cap, pl->s3_ext_cap, pl->s3_lut_cap);
+    if (lds > (size_t)sym::kLdsCap)
+        return xab_fail(ctx, XAB_E_UNSUPPORTED, "symmetric tile needs %zu bytes of LDS", lds);
+    hipLaunchKernelGGL((k_spmv_sym_s3<VT, XT, YT, AT, C>), dim3((unsigned)pl->P), dim3(kNT), lds, ctx->stream,
                        A->rowptr, A->colind, val, x, y, pl->b, pl->P, pl->tile_ptr, pl->tile_blk, pl->tile_slot,
-                       pl->tile_minblk, (AT *)pl->partial);
+                       pl->tile_minblk, (AT *)pl->partial, pl->s3_own_cap, pl->s3_ext_cap, pl->s3_lut_cap);
     XAB_LAUNCH_CHECK(ctx, "k_spmv_sym_s3");
     if (pl->ntouch > 0) {
         hipLaunchKernelGGL((k_sym_block_reduce<YT, AT, C>), dim3(grid_for(A->n, 256)), dim3(256), 0, ctx->stream, y,

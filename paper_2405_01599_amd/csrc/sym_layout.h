@@ -1,6 +1,6 @@
 // Limits of the symmetric zero-block-omitted SpMV tile: shared by the plan
 // builder (which rejects matrices that do not fit) and the kernel (which
-// sizes its LDS with them).
+// sizes its LDS from the plan).
 #pragma once
 
 namespace xab {
@@ -9,5 +9,8 @@ constexpr int kRowCap = 2048;          // rows per tile (LDS accumulator of the 
 constexpr int kExtCap = 6144;          // LDS slots for column blocks below the tile
 constexpr int kLutMax = 2048;          // span of block ids one tile may touch
 constexpr int kLutWords = kLutMax / 32;
+constexpr int kLdsCap = 65536;         // LDS bytes one symmetric tile may use
+// bytes of the fixed part (head flags of a 1024-entry chunk + wave totals)
+constexpr int kFixedBytes = 256 * 4 * 4 + 4 * 24;
 }  // namespace sym
 }  // namespace xab
