@@ -78,8 +78,22 @@ typedef enum { XAB_TIME = 0, XAB_STABLE = 1, XAB_LEARNED = 2 } xab_policy;
  *   XAB_SYM_S3     symmetric, lower storage, zero-element omission in the
  *                  transpose reduction (column blocks of col_block rows)
  *   XAB_SYM_ATOMIC symmetric, lower storage, transpose part by device
- *                  atomics (baseline; not bitwise reproducible) */
-typedef enum { XAB_ROW = 0, XAB_NNZ = 1, XAB_BSS = 2, XAB_SYM_S3 = 3, XAB_SYM_ATOMIC = 4 } xab_variant;
+ *                  atomics (baseline; not bitwise reproducible)
+ *   XAB_XCB        column-blocked segmented scan: the plan copies the
+ *                  matrix into 8 column blocks (one per XCD of the MI355X)
+ *                  so each block's slice of x stays in one XCD's L2; each
+ *                  block is scanned with 256 * j_per_lane entries per
+ *                  workgroup and the 8 partial products are summed in
+ *                  block order.  The plan owns the copy: values changed
+ *                  after plan creation are not seen. */
+typedef enum {
+    XAB_ROW = 0,
+    XAB_NNZ = 1,
+    XAB_BSS = 2,
+    XAB_SYM_S3 = 3,
+    XAB_SYM_ATOMIC = 4,
+    XAB_XCB = 5
+} xab_variant;
 
 typedef struct {
     int32_t lanes_per_row; /* ROW, SYM_ATOMIC: 1, 2, 4, ..., 64 */
@@ -95,8 +109,9 @@ typedef struct {
 #define XAB_TRUST_INPUT 2u /* skip the structural validation pass */
 
 /* Selector classes: fixed (variant, params) pairs, the action space of the
- * selector.  0..8 apply to general matrices, 9..11 to XAB_SYM_LOWER. */
-#define XAB_NCLASSES 12
+ * selector.  0..8 and 12 apply to general matrices, 9..11 to
+ * XAB_SYM_LOWER. */
+#define XAB_NCLASSES 13
 int xab_class_params(int32_t k, xab_variant *variant, xab_params *params);
 
 typedef struct {

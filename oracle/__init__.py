@@ -35,6 +35,7 @@ def lib():
             "orc_plan_sym_ntiles": (i64, [i64, P, i64, i64]),
             "orc_plan_sym_tiles": (None, [i64, P, i64, i64, P]),
             "orc_plan_sym_touch": (i64, [i64, P, P, i64, P, i64, P, P, P, P, P]),
+            "orc_plan_xcb": (None, [i64, i64, P, P, ci, P, P]),
             "orc_features": (None, [i64, P, P, ci, P, P]),
             "orc_mlp_nparams": (i64, [ci, ci, ci]),
             "orc_mlp_forward": (None, [ci, ci, ci, P, i64, P, P]),
@@ -144,6 +145,15 @@ def plan_sym(A, T, Rmax, C):
                              _p(tile_blk), _p(tile_slot))
     return dict(b=b, tm_ptr=tm_ptr, tm_tile=tm_tile[:nt], tile_ptr=tile_ptr, tile_blk=tile_blk[:nt],
                 tile_slot=tile_slot[:nt])
+
+
+def plan_xcb(A, nb=8):
+    """Column-blocked split: (rp[nb, n+1] relative row pointers, concatenated colind)."""
+    rp, ci, _ = _csr(A)
+    out_rp = np.empty((nb, A.n + 1), dtype=np.int32)
+    out_ci = np.empty(max(A.nnz, 1), dtype=np.int32)
+    lib().orc_plan_xcb(A.n, A.ncols, _p(rp), _p(ci), nb, _p(out_rp), _p(out_ci))
+    return out_rp, out_ci[:A.nnz]
 
 
 # ------------------------------------------------------------------ features

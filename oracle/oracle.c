@@ -286,6 +286,30 @@ int64_t orc_plan_sym_touch(int64_t n, const int32_t *rowptr, const int32_t *coli
     return total;
 }
 
+/* Column blocking (a data transformation of the kind the paper lists as
+ * future work for SpMV, section 5): every entry goes to the block of its
+ * column, keeping row order and the order inside a row. */
+void orc_plan_xcb(int64_t n, int64_t ncols, const int32_t *rowptr, const int32_t *colind, int nb, int32_t *rp,
+                  int32_t *ci) {
+    int64_t *blk_lo = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nb + 1));
+    for (int k = 0; k <= nb; ++k) blk_lo[k] = ((int64_t)k * ncols) / nb;
+    int64_t pos = 0;
+    for (int k = 0; k < nb; ++k) {
+        int32_t *r = rp + (int64_t)k * (n + 1);
+        r[0] = 0;
+        for (int64_t i = 0; i < n; ++i) {
+            int32_t c = 0;
+            for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e)
+                if (colind[e] >= blk_lo[k] && colind[e] < blk_lo[k + 1]) {
+                    ci[pos++] = colind[e];
+                    c++;
+                }
+            r[i + 1] = r[i] + c;
+        }
+    }
+    free(blk_lo);
+}
+
 /* ------------------------------------------------------------- features */
 
 /* stats: [0] n, [1] nnz, [2] sum len^2, [3] max len, [4] max |i-j|,

@@ -57,6 +57,13 @@ int64_t orc_plan_sym_touch(int64_t n, const int32_t *rowptr, const int32_t *coli
                            const int32_t *b, int64_t C, int32_t *tm_ptr, int32_t *tm_tile,
                            int32_t *tile_ptr, int32_t *tile_blk, int32_t *tile_slot);
 
+/* Column-blocked split: block k holds columns [floor(k*ncols/nb),
+ * floor((k+1)*ncols/nb)).  rp[k*(n+1) + i] = entries of block k in rows < i
+ * (so rp[k*(n+1) + n] = block size); ci = the column indices of block 0 in
+ * row order (original order inside a row), then block 1, and so on. */
+void orc_plan_xcb(int64_t n, int64_t ncols, const int32_t *rowptr, const int32_t *colind, int nb, int32_t *rp,
+                  int32_t *ci);
+
 /* Selector features: integer statistics then the 12 features. */
 void orc_features(int64_t n, const int32_t *rowptr, const int32_t *colind, int sym_lower,
                   int64_t *stats, double *feat);

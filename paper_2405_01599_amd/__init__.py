@@ -15,10 +15,12 @@ LIB_PATH = os.path.join(HERE, "libxab.so")
 
 F64, F32 = 0, 1
 TIME, STABLE, LEARNED = 0, 1, 2
-ROW, NNZ, BSS, SYM_S3, SYM_ATOMIC = 0, 1, 2, 3, 4
-VARIANT_NAMES = {ROW: "row", NNZ: "nnz", BSS: "bss", SYM_S3: "sym_s3", SYM_ATOMIC: "sym_atomic"}
+ROW, NNZ, BSS, SYM_S3, SYM_ATOMIC, XCB = 0, 1, 2, 3, 4, 5
+VARIANT_NAMES = {ROW: "row", NNZ: "nnz", BSS: "bss", SYM_S3: "sym_s3", SYM_ATOMIC: "sym_atomic", XCB: "xcb"}
 GENERAL, SYM_LOWER, TRUST_INPUT = 0, 1, 2
-NCLASSES = 12
+NCLASSES = 13
+GENERAL_CLASSES = tuple(range(9)) + (12,)
+SYM_CLASSES = (9, 10, 11)
 NFEAT = 12
 MLP_NPARAMS = 64 * 12 + 64 + 64 * 64 + 64 + NCLASSES * 64 + NCLASSES
 MODE_FP64, MODE_IR = 0, 1

@@ -154,6 +154,7 @@ int xab_class_params(int32_t k, xab_variant *v, xab_params *p) {
         case 9: *v = XAB_SYM_ATOMIC; q.lanes_per_row = 8; break;
         case 10: *v = XAB_SYM_S3; q.col_block = 64; q.tile_nnz = 16384; break;
         case 11: *v = XAB_SYM_S3; q.col_block = 256; q.tile_nnz = 16384; break;
+        case 12: *v = XAB_XCB; q.j_per_lane = 2; break;
         default: return XAB_E_SHAPE;
     }
     *p = q;

@@ -203,6 +203,128 @@ __global__ void k_fill_flag(int *f) {
     if (threadIdx.x == 0) *f = 0;
 }
 
+// ---- column-blocked copy (XCB): block of a column, counts, scan, scatter
+struct ColBlocks {
+    int32_t cb[xab_plan::kXcb + 1];  // block k = columns [cb[k], cb[k+1])
+};
+
+__device__ __forceinline__ int col_block_of(const ColBlocks &c, int32_t col) {
+    int k = 0;
+#pragma unroll
+    for (int q = 1; q < xab_plan::kXcb; ++q) k += col >= c.cb[q];
+    return k;
+}
+
+// cnt[k * n + i] = entries of row i in column block k
+__global__ void k_xcb_count(const int32_t *rowptr, const int32_t *colind, int32_t n, ColBlocks c, int32_t *cnt) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int32_t m[xab_plan::kXcb] = {0};
+    for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+        int k = col_block_of(c, colind[e]);
+#pragma unroll
+        for (int q = 0; q < xab_plan::kXcb; ++q) m[q] += (q == k);
+    }
+#pragma unroll
+    for (int q = 0; q < xab_plan::kXcb; ++q) cnt[(int64_t)q * n + i] = m[q];
+}
+
+// Exclusive scan of in[0..m) into out[0..m] (out[m] = total) in three
+// steps: per-workgroup sums of 2048 elements, a scan of those sums, and a
+// per-workgroup rescan with its offset.
+constexpr int kScanItems = 8, kScanTile = 256 * kScanItems;
+
+__global__ void k_scan_tile_sums(const int32_t *in, int64_t m, int32_t *sums) {
+    __shared__ int32_t red[256];
+    int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+    int32_t a = 0;
+    for (int q = 0; q < kScanItems; ++q)
+        if (base + q < m) a += in[base + q];
+    red[threadIdx.x] = a;
+    __syncthreads();
+    for (int d = 128; d > 0; d >>= 1) {
+        if (threadIdx.x < d) red[threadIdx.x] += red[threadIdx.x + d];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) sums[blockIdx.x] = red[0];
+}
+
+__global__ void k_scan_tile_apply(const int32_t *in, int64_t m, const int32_t *offs, int32_t *out) {
+    __shared__ int32_t part[256];
+    int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+    int32_t v[kScanItems], a = 0;
+    for (int q = 0; q < kScanItems; ++q) {
+        v[q] = base + q < m ? in[base + q] : 0;
+        a += v[q];
+    }
+    part[threadIdx.x] = a;
+    __syncthreads();
+    for (int d = 1; d < 256; d <<= 1) {
+        int32_t u = threadIdx.x >= d ? part[threadIdx.x - d] : 0;
+        __syncthreads();
+        part[threadIdx.x] += u;
+        __syncthreads();
+    }
+    int32_t run = offs[blockIdx.x] + part[threadIdx.x] - a;
+    for (int q = 0; q < kScanItems; ++q) {
+        if (base + q < m) out[base + q] = run;
+        run += v[q];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) out[m] = offs[gridDim.x];  // the total
+}
+
+// mask[i] bit k = row i has entries in block k; flag_k[i] = that bit for one block
+__global__ void k_xcb_mask(const int32_t *cnt, int32_t n, uint8_t *mask) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t m = 0;
+    for (int k = 0; k < xab_plan::kXcb; ++k) m |= (cnt[(int64_t)k * n + i] > 0 ? 1u : 0u) << k;
+    mask[i] = (uint8_t)m;
+}
+
+__global__ void k_nonzero_flags(const int32_t *cnt, int32_t n, int32_t *flag) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) flag[i] = cnt[i] > 0;
+}
+
+// a block's CSR restricted to its non-empty rows: ridx[j] = global row of
+// the j-th such row, crp[j] = its start, crp[m] = the block's size
+__global__ void k_xcb_compress(const int32_t *flag, const int32_t *pos, const int32_t *rp_full, int32_t n,
+                               int32_t *ridx, int32_t *crp) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > n) return;
+    if (i == n) {
+        crp[pos[n]] = rp_full[n];
+        return;
+    }
+    if (flag[i]) {
+        ridx[pos[i]] = (int32_t)i;
+        crp[pos[i]] = rp_full[i];
+    }
+}
+
+// stable scatter of every row's entries into its column block's CSR
+__global__ void k_xcb_scatter(const int32_t *rowptr, const int32_t *colind, const double *v64, const float *v32,
+                              int32_t n, ColBlocks c, const int32_t *rp, const int64_t *base, int32_t *ci_out,
+                              double *v64_out, float *v32_out) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int64_t pos[xab_plan::kXcb];
+#pragma unroll
+    for (int q = 0; q < xab_plan::kXcb; ++q) pos[q] = base[q] + rp[(int64_t)q * (n + 1) + i];
+    for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+        int32_t col = colind[e];
+        int k = col_block_of(c, col);
+        int64_t p = 0;
+#pragma unroll
+        for (int q = 0; q < xab_plan::kXcb; ++q)
+            if (q == k) p = pos[q]++;
+        ci_out[p] = col;
+        if (v64) v64_out[p] = v64[e];
+        if (v32) v32_out[p] = v32[e];
+    }
+}
+
 unsigned grid_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 }  // namespace
@@ -222,6 +344,20 @@ static void free_plan_arrays(xab_ctx *ctx, xab_plan *pl) {
     xab_dfree(ctx, pl->tile_slot);
     xab_dfree(ctx, pl->tile_minblk);
     xab_dfree(ctx, pl->partial);
+    xab_dfree(ctx, pl->xcb_rowptr);
+    xab_dfree(ctx, pl->xcb_crowptr);
+    xab_dfree(ctx, pl->xcb_ridx);
+    xab_dfree(ctx, pl->xcb_mask);
+    xab_dfree(ctx, pl->xcb_colind);
+    xab_dfree(ctx, pl->xcb_val64);
+    xab_dfree(ctx, pl->xcb_val32);
+    xab_dfree(ctx, pl->xcb_row_lo);
+    xab_dfree(ctx, pl->xcb_tile_row);
+    xab_dfree(ctx, pl->xcb_carry_row);
+    xab_dfree(ctx, pl->xcb_tail_row);
+    xab_dfree(ctx, pl->xcb_carry_val);
+    xab_dfree(ctx, pl->xcb_tail_val);
+    xab_dfree(ctx, pl->xcb_Y);
 }
 
 #define ALLOC(ptr, T, count)                                              \
@@ -265,6 +401,7 @@ int xab_build_plan(xab_ctx *ctx, const xab_matrix *A, xab_variant v, const xab_p
             if (p.tile_nnz < 64) return xab_fail(ctx, XAB_E_UNSUPPORTED, "tile_nnz < 64");
             break;
         case XAB_BSS:
+        case XAB_XCB:
             if (p.j_per_lane < 1 || p.j_per_lane > 32 || !pow2(p.j_per_lane))
                 return xab_fail(ctx, XAB_E_UNSUPPORTED, "j_per_lane must be a power of two in [1, 32]");
             break;
@@ -310,6 +447,113 @@ int xab_build_plan(xab_ctx *ctx, const xab_matrix *A, xab_variant v, const xab_p
         hipLaunchKernelGGL(k_split_bss, dim3(grid_for(pl->P + 1, 256)), dim3(256), 0, st, A->rowptr, n, T, pl->P,
                            pl->row_lo, pl->tile_row, pl->carry_row);
         CHECKED(hip_ok(ctx, hipGetLastError(), "k_split_bss"));
+    } else if (v == XAB_XCB) {
+        constexpr int KB = xab_plan::kXcb;
+        const int64_t T = 256 * (int64_t)p.j_per_lane;
+        ColBlocks cbk;
+        for (int k = 0; k <= KB; ++k) cbk.cb[k] = (int32_t)((int64_t)k * A->ncols / KB);
+        pl->P = 0;
+        // per-row block counts -> per-block row pointers -> stable scatter
+        int32_t *cnt = nullptr, *sums = nullptr, *offs = nullptr;
+        int64_t *dbase = nullptr;
+        const int64_t ntile = (n + kScanTile - 1) / kScanTile;
+        ALLOC(pl->xcb_rowptr, int32_t, (int64_t)KB * (n + 1));
+        ALLOC(pl->xcb_colind, int32_t, std::max<int64_t>(1, nnz));
+        if (A->has64) ALLOC(pl->xcb_val64, double, std::max<int64_t>(1, nnz));
+        if (A->has32) ALLOC(pl->xcb_val32, float, std::max<int64_t>(1, nnz));
+        ALLOC(pl->xcb_Y, double, (int64_t)KB * std::max<int32_t>(1, n));
+        cnt = (int32_t *)xab_dalloc(ctx, sizeof(int32_t) * (size_t)KB * std::max<int32_t>(1, n));
+        sums = (int32_t *)xab_dalloc(ctx, sizeof(int32_t) * (ntile + 1));
+        offs = (int32_t *)xab_dalloc(ctx, sizeof(int32_t) * (ntile + 1));
+        dbase = (int64_t *)xab_dalloc(ctx, sizeof(int64_t) * (KB + 1));
+        auto free_tmp = [&]() {
+            xab_dfree(ctx, cnt);
+            xab_dfree(ctx, sums);
+            xab_dfree(ctx, offs);
+            xab_dfree(ctx, dbase);
+        };
+        if (!cnt || !sums || !offs || !dbase) {
+            free_tmp();
+            free_plan_arrays(ctx, pl);
+            delete pl;
+            return xab_fail(ctx, XAB_E_NOMEM, "plan allocation");
+        }
+        if (n > 0) hipLaunchKernelGGL(k_xcb_count, dim3(grid_for(n, 256)), dim3(256), 0, st, A->rowptr, A->colind, n, cbk, cnt);
+        for (int k = 0; k < KB; ++k) {
+            const int32_t *in = cnt + (int64_t)k * n;
+            int32_t *out = pl->xcb_rowptr + (int64_t)k * (n + 1);
+            const unsigned g = (unsigned)std::max<int64_t>(1, ntile);
+            hipLaunchKernelGGL(k_scan_tile_sums, dim3(g), dim3(256), 0, st, in, (int64_t)n, sums);
+            hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, st, sums, (int64_t)g, offs);
+            hipLaunchKernelGGL(k_scan_tile_apply, dim3(g), dim3(256), 0, st, in, (int64_t)n, offs, out);
+        }
+        int32_t tot[KB];
+        hipError_t e = hipGetLastError();
+        for (int k = 0; k < KB && e == hipSuccess; ++k)
+            e = hipMemcpyAsync(&tot[k], pl->xcb_rowptr + (int64_t)k * (n + 1) + n, sizeof(int32_t),
+                               hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) {
+            free_tmp();
+            free_plan_arrays(ctx, pl);
+            delete pl;
+            return xab_hip_check(ctx, e, "column-block counts");
+        }
+        pl->xcb_base[0] = 0;
+        pl->xcb_toff[0] = 0;
+        for (int k = 0; k < KB; ++k) {
+            pl->xcb_base[k + 1] = pl->xcb_base[k] + tot[k];
+            pl->xcb_P[k] = std::max<int64_t>(1, (tot[k] + T - 1) / T);
+            pl->xcb_toff[k + 1] = pl->xcb_toff[k] + pl->xcb_P[k] + 1;
+        }
+        e = hipMemcpyAsync(dbase, pl->xcb_base, sizeof(int64_t) * (KB + 1), hipMemcpyHostToDevice, st);
+        if (e == hipSuccess && n > 0)
+            hipLaunchKernelGGL(k_xcb_scatter, dim3(grid_for(n, 256)), dim3(256), 0, st, A->rowptr, A->colind, A->val64,
+                               A->val32, n, cbk, pl->xcb_rowptr, dbase, pl->xcb_colind, pl->xcb_val64, pl->xcb_val32);
+        // each block's CSR over its non-empty rows (so no tile walks rows the
+        // block does not touch), and the per-row block mask for the combine
+        ALLOC(pl->xcb_crowptr, int32_t, (int64_t)KB * (n + 1));
+        ALLOC(pl->xcb_ridx, int32_t, (int64_t)KB * std::max<int32_t>(1, n));
+        ALLOC(pl->xcb_mask, uint8_t, std::max<int32_t>(1, n));
+        int32_t *flag = (int32_t *)xab_dalloc(ctx, sizeof(int32_t) * (size_t)(n + 1));
+        int32_t *pos = (int32_t *)xab_dalloc(ctx, sizeof(int32_t) * (size_t)(n + 1));
+        if (!flag || !pos) e = hipErrorOutOfMemory;
+        if (e == hipSuccess && n > 0)
+            hipLaunchKernelGGL(k_xcb_mask, dim3(grid_for(n, 256)), dim3(256), 0, st, cnt, n, pl->xcb_mask);
+        int32_t mk[KB];
+        for (int k = 0; k < KB && e == hipSuccess; ++k) {
+            const unsigned g = (unsigned)std::max<int64_t>(1, ntile);
+            if (n > 0) hipLaunchKernelGGL(k_nonzero_flags, dim3(grid_for(n, 256)), dim3(256), 0, st, cnt + (int64_t)k * n, n, flag);
+            hipLaunchKernelGGL(k_scan_tile_sums, dim3(g), dim3(256), 0, st, flag, (int64_t)n, sums);
+            hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, st, sums, (int64_t)g, offs);
+            hipLaunchKernelGGL(k_scan_tile_apply, dim3(g), dim3(256), 0, st, flag, (int64_t)n, offs, pos);
+            hipLaunchKernelGGL(k_xcb_compress, dim3(grid_for(n + 1, 256)), dim3(256), 0, st, flag, pos,
+                               pl->xcb_rowptr + (int64_t)k * (n + 1), n, pl->xcb_ridx + (int64_t)k * n,
+                               pl->xcb_crowptr + (int64_t)k * (n + 1));
+            e = hipMemcpyAsync(&mk[k], pos + n, sizeof(int32_t), hipMemcpyDeviceToHost, st);
+            if (e == hipSuccess) e = hipStreamSynchronize(st);  // flag / pos are reused by the next block
+        }
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        xab_dfree(ctx, flag);
+        xab_dfree(ctx, pos);
+        free_tmp();
+        CHECKED(hip_ok(ctx, e, "column-block scatter"));
+        for (int k = 0; k < KB; ++k) pl->xcb_m[k] = mk[k];
+        const int64_t tt = pl->xcb_toff[KB];
+        ALLOC(pl->xcb_row_lo, int32_t, tt);
+        ALLOC(pl->xcb_tile_row, int32_t, tt);
+        ALLOC(pl->xcb_carry_row, int32_t, tt);
+        ALLOC(pl->xcb_tail_row, int32_t, tt);
+        ALLOC(pl->xcb_carry_val, double, tt);
+        ALLOC(pl->xcb_tail_val, double, tt);
+        for (int k = 0; k < KB; ++k) {
+            const int64_t o = pl->xcb_toff[k];
+            hipLaunchKernelGGL(k_split_bss, dim3(grid_for(pl->xcb_P[k] + 1, 256)), dim3(256), 0, st,
+                               pl->xcb_crowptr + (int64_t)k * (n + 1), (int32_t)pl->xcb_m[k], T, pl->xcb_P[k],
+                               pl->xcb_row_lo + o, pl->xcb_tile_row + o, pl->xcb_carry_row + o);
+            pl->P = std::max(pl->P, pl->xcb_P[k]);
+        }
+        CHECKED(hip_ok(ctx, hipGetLastError(), "column-block tiles"));
     } else {  // XAB_SYM_S3
         const int32_t C = p.col_block;
         const int32_t bmax = xab::sym::kExtCap / C;
@@ -488,6 +732,8 @@ int xab_plan_array(const xab_plan *pl, int32_t which, int32_t *h_out, int64_t *l
         case 6: src = pl->tile_ptr; m = pl->tile_ptr ? pl->P + 1 : 0; break;
         case 7: src = pl->tile_blk; m = pl->tile_blk ? pl->ntouch : 0; break;
         case 8: src = pl->tile_slot; m = pl->tile_slot ? pl->ntouch : 0; break;
+        case 9: src = pl->xcb_rowptr; m = pl->xcb_rowptr ? (int64_t)xab_plan::kXcb * (pl->A->n + 1) : 0; break;
+        case 10: src = pl->xcb_colind; m = pl->xcb_colind ? pl->A->nnz : 0; break;
         default: return XAB_E_SHAPE;
     }
     *len = m;

@@ -28,8 +28,10 @@ size_t sym_lds_bytes(int own_cap, int ext_cap, int lut_cap) {
 template <class YT, class AT>
 struct StoreSink {
     YT *y;
-    __device__ void row_done(int32_t r, AT v) { y[r] = (YT)v; }
-    __device__ void empty_row(int32_t r) { y[r] = YT(0); }
+    const int32_t *ridx;  // row r of the CSR is output row ridx[r] (null: r itself)
+    __device__ int64_t out(int32_t r) const { return ridx ? ridx[r] : r; }
+    __device__ void row_done(int32_t r, AT v) { y[out(r)] = (YT)v; }
+    __device__ void empty_row(int32_t r) { y[out(r)] = YT(0); }
     template <class VT>
     __device__ void entry(int32_t, int32_t, VT) {}
 };
@@ -51,7 +53,7 @@ __global__ __launch_bounds__(kNT) void k_spmv_nnz(const int32_t *__restrict__ ro
     const int32_t r0 = b[p], r1 = b[p + 1];
     if (r0 >= r1) return;
     const int64_t s = rowptr[r0], e = rowptr[r1];
-    StoreSink<YT, AT> sink{y};
+    StoreSink<YT, AT> sink{y, nullptr};
     Seg<AT> seed{0, AT(0), -1};
     int32_t rlo = r0;
     int64_t A = s - (s % CH);
@@ -86,19 +88,17 @@ __global__ __launch_bounds__(kNT) void k_spmv_nnz(const int32_t *__restrict__ ro
 // The fix-up kernel then writes each such row once: its start partial plus
 // the carries of the following tiles in ascending tile order.
 template <class VT, class XT, class YT, class AT, int J>
-__global__ __launch_bounds__(kNT) void k_spmv_bss(const int32_t *__restrict__ rowptr,
-                                                  const int32_t *__restrict__ colind, const VT *__restrict__ val,
-                                                  const XT *__restrict__ x, YT *__restrict__ y, int64_t nnz,
-                                                  int64_t P, const int32_t *__restrict__ row_lo,
-                                                  const int32_t *__restrict__ carry_row, AT *__restrict__ carry_val,
-                                                  AT *__restrict__ tail_val, int32_t *__restrict__ tail_row) {
+__device__ __forceinline__ void bss_tile(int64_t t, const int32_t *__restrict__ rowptr,
+                                         const int32_t *__restrict__ colind, const VT *__restrict__ val,
+                                         const XT *__restrict__ x, YT *__restrict__ y, int64_t nnz,
+                                         const int32_t *__restrict__ row_lo, const int32_t *__restrict__ carry_row,
+                                         AT *__restrict__ carry_val, AT *__restrict__ tail_val,
+                                         int32_t *__restrict__ tail_row, int32_t *head_row, Seg<AT> *wave_tot,
+                                         const int32_t *__restrict__ ridx) {
     constexpr int T = kNT * J;
-    __shared__ int32_t head_row[T];
-    __shared__ Seg<AT> wave_tot[kNT / kWave];
-    const int64_t t = xcd_remap(blockIdx.x, P);
     const int64_t A = t * T;
     const int64_t c1 = (A + T < nnz) ? A + T : nnz;
-    StoreSink<YT, AT> sink{y};
+    StoreSink<YT, AT> sink{y, ridx};
     // loads first; the row-pointer probe and the gathers overlap them
     Run<J, VT, XT> R;
     run_load<kNT, J>(R, A, A, c1, colind, val);
@@ -118,13 +118,89 @@ __global__ __launch_bounds__(kNT) void k_spmv_bss(const int32_t *__restrict__ ro
             // no row starts in this tile: all of it belongs to the carried row
             if (cr >= 0) carry_val[t] = res.state.v;
         } else if (rowptr[res.state.r + 1] <= c1) {
-            y[res.state.r] = (YT)res.state.v;
+            y[sink.out(res.state.r)] = (YT)res.state.v;
         } else {
             tr = res.state.r;
             tail_val[t] = res.state.v;
         }
         tail_row[t] = tr;
     }
+}
+
+template <class VT, class XT, class YT, class AT, int J>
+__global__ __launch_bounds__(kNT) void k_spmv_bss(const int32_t *__restrict__ rowptr,
+                                                  const int32_t *__restrict__ colind, const VT *__restrict__ val,
+                                                  const XT *__restrict__ x, YT *__restrict__ y, int64_t nnz,
+                                                  int64_t P, const int32_t *__restrict__ row_lo,
+                                                  const int32_t *__restrict__ carry_row, AT *__restrict__ carry_val,
+                                                  AT *__restrict__ tail_val, int32_t *__restrict__ tail_row) {
+    __shared__ int32_t head_row[kNT * J];
+    __shared__ Seg<AT> wave_tot[kNT / kWave];
+    bss_tile<VT, XT, YT, AT, J>(xcd_remap(blockIdx.x, P), rowptr, colind, val, x, y, nnz, row_lo, carry_row,
+                                carry_val, tail_val, tail_row, head_row, wave_tot, nullptr);
+}
+
+// ------------------------------------------------------------------ XCB
+// Column-blocked segmented scan: the columns are cut into kXcds blocks and
+// each block's entries form their own CSR (built at plan time).  Workgroup
+// ids are dealt round-robin to the XCDs, so giving block k every id with
+// id % kXcds == k keeps all of block k's gathers on one XCD, whose private
+// L2 then holds that block's slice of x.  Each block writes a full partial
+// product Y_k (every row, zero where the block has no entry); the combine
+// kernel sums the kXcds partials of each row in block order.
+struct XcbArgs {
+    const int32_t *rowptr[kXcds];
+    const int32_t *colind[kXcds];
+    const void *val[kXcds];
+    const int32_t *row_lo[kXcds];
+    const int32_t *carry_row[kXcds];
+    void *carry_val[kXcds];
+    void *tail_val[kXcds];
+    int32_t *tail_row[kXcds];
+    const int32_t *ridx[kXcds];  // block CSRs cover only their non-empty rows
+    int64_t nnz[kXcds];
+    int64_t P[kXcds];
+};
+
+template <class VT, class XT, class AT, int J>
+__global__ __launch_bounds__(kNT) void k_spmv_xcb(XcbArgs a, const XT *__restrict__ x, AT *__restrict__ Y,
+                                                  int64_t n) {
+    __shared__ int32_t head_row[kNT * J];
+    __shared__ Seg<AT> wave_tot[kNT / kWave];
+    const int k = blockIdx.x % kXcds;
+    const int64_t t = blockIdx.x / kXcds;
+    if (t >= a.P[k]) return;
+    bss_tile<VT, XT, AT, AT, J>(t, a.rowptr[k], a.colind[k], (const VT *)a.val[k], x, Y + (int64_t)k * n, a.nnz[k],
+                                a.row_lo[k], a.carry_row[k], (AT *)a.carry_val[k], (AT *)a.tail_val[k],
+                                a.tail_row[k], head_row, wave_tot, a.ridx[k]);
+}
+
+template <class AT>
+__global__ void k_xcb_fixup(XcbArgs a, AT *__restrict__ Y, int64_t n, int64_t pmax) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = (int)(g / pmax);
+    const int64_t t = g % pmax;
+    if (k >= kXcds || t >= a.P[k]) return;
+    const int32_t r = a.tail_row[k][t];
+    if (r < 0) return;
+    const AT *cv = (const AT *)a.carry_val[k];
+    AT acc = ((const AT *)a.tail_val[k])[t];
+    for (int64_t u = t + 1; u < a.P[k] && a.carry_row[k][u] == r; ++u) acc += cv[u];
+    Y[(int64_t)k * n + a.ridx[k][r]] = acc;
+}
+
+// y_i = sum over the blocks row i has entries in (mask bit k), in block order
+template <class YT, class AT>
+__global__ void k_xcb_combine(const AT *__restrict__ Y, const uint8_t *__restrict__ mask, int64_t n,
+                              YT *__restrict__ y) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t m = mask[i];
+    AT a = AT(0);
+#pragma unroll
+    for (int k = 0; k < kXcds; ++k)
+        if (m & (1u << k)) a += Y[(int64_t)k * n + i];
+    y[i] = (YT)a;
 }
 
 template <class YT, class AT>
@@ -290,6 +366,57 @@ int launch_bss(xab_ctx *ctx, const xab_plan *pl, const VT *val, const XT *x, YT 
     }
 }
 
+template <class VT, class XT, class YT, class AT, int J>
+static int launch_xcb_j(xab_ctx *ctx, const xab_plan *pl, const XT *x, YT *y) {
+    const xab_matrix *A = pl->A;
+    constexpr int KB = xab_plan::kXcb;
+    static_assert(KB == kXcds, "one column block per XCD");
+    const int64_t n = A->n;
+    XcbArgs a;
+    int64_t pmax = 1;
+    for (int k = 0; k < KB; ++k) {
+        const int64_t b = pl->xcb_base[k], o = pl->xcb_toff[k];
+        a.rowptr[k] = pl->xcb_crowptr + (int64_t)k * (n + 1);
+        a.ridx[k] = pl->xcb_ridx + (int64_t)k * n;
+        a.colind[k] = pl->xcb_colind + b;
+        if constexpr (sizeof(VT) == 8) a.val[k] = pl->xcb_val64 + b;
+        else a.val[k] = pl->xcb_val32 + b;
+        a.row_lo[k] = pl->xcb_row_lo + o;
+        a.carry_row[k] = pl->xcb_carry_row + o;
+        a.tail_row[k] = pl->xcb_tail_row + o;
+        a.carry_val[k] = (AT *)pl->xcb_carry_val + o;
+        a.tail_val[k] = (AT *)pl->xcb_tail_val + o;
+        a.nnz[k] = pl->xcb_base[k + 1] - b;
+        a.P[k] = pl->xcb_P[k];
+        pmax = std::max(pmax, pl->xcb_P[k]);
+    }
+    AT *Y = (AT *)pl->xcb_Y;
+    hipLaunchKernelGGL((k_spmv_xcb<VT, XT, AT, J>), dim3((unsigned)(KB * pmax)), dim3(kNT), 0, ctx->stream, a, x, Y, n);
+    XAB_LAUNCH_CHECK(ctx, "k_spmv_xcb");
+    hipLaunchKernelGGL((k_xcb_fixup<AT>), dim3(grid_for(KB * pmax, 256)), dim3(256), 0, ctx->stream, a, Y, n, pmax);
+    XAB_LAUNCH_CHECK(ctx, "k_xcb_fixup");
+    hipLaunchKernelGGL((k_xcb_combine<YT, AT>), dim3(grid_for(n, 256)), dim3(256), 0, ctx->stream, Y, pl->xcb_mask, n,
+                       y);
+    XAB_LAUNCH_CHECK(ctx, "k_xcb_combine");
+    return XAB_OK;
+}
+
+template <class VT, class XT, class YT, class AT>
+int launch_xcb(xab_ctx *ctx, const xab_plan *pl, const VT *val, const XT *x, YT *y) {
+    (void)val;  // the plan holds its own column-blocked copy of the values
+    if ((sizeof(VT) == 8 && !pl->xcb_val64) || (sizeof(VT) == 4 && !pl->xcb_val32))
+        return xab_fail(ctx, XAB_E_DTYPE, "column-blocked plan holds no values of this precision");
+    switch (pl->params.j_per_lane) {
+        case 1: return launch_xcb_j<VT, XT, YT, AT, 1>(ctx, pl, x, y);
+        case 2: return launch_xcb_j<VT, XT, YT, AT, 2>(ctx, pl, x, y);
+        case 4: return launch_xcb_j<VT, XT, YT, AT, 4>(ctx, pl, x, y);
+        case 8: return launch_xcb_j<VT, XT, YT, AT, 8>(ctx, pl, x, y);
+        case 16: return launch_xcb_j<VT, XT, YT, AT, 16>(ctx, pl, x, y);
+        case 32: return launch_xcb_j<VT, XT, YT, AT, 32>(ctx, pl, x, y);
+        default: return xab_fail(ctx, XAB_E_UNSUPPORTED, "j_per_lane %d", pl->params.j_per_lane);
+    }
+}
+
 template <class VT, class XT, class YT, class AT, int C>
 static int launch_s3_c(xab_ctx *ctx, const xab_plan *pl, const VT *val, const XT *x, YT *y) {
     const xab_matrix *A = pl->A;
@@ -327,5 +454,6 @@ int launch_sym_s3(xab_ctx *ctx, const xab_plan *pl, const VT *val, const XT *x, 
 XAB_INSTANTIATE_LAUNCHER(launch_nnz)
 XAB_INSTANTIATE_LAUNCHER(launch_bss)
 XAB_INSTANTIATE_LAUNCHER(launch_sym_s3)
+XAB_INSTANTIATE_LAUNCHER(launch_xcb)
 
 }  // namespace xab

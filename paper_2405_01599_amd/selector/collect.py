@@ -35,8 +35,7 @@ def measure(ctx, A, reps=10, warmup=2):
     build = np.full(K, np.nan, dtype=np.float32)
     valid = np.zeros(K, dtype=np.uint8)
     for k in range(K):
-        v, _ = xab.class_params(k)
-        if (k >= 9) != bool(A.sym_lower):
+        if k not in (xab.SYM_CLASSES if A.sym_lower else xab.GENERAL_CLASSES):
             continue
         torch.cuda.synchronize()
         t0 = time.perf_counter()

@@ -62,8 +62,9 @@ def test_class_table():
     assert [s[0] for s in seen[3:5]] == [xab.NNZ] * 2 and [s[2] for s in seen[3:5]] == [2048, 8192]
     assert [s[0] for s in seen[5:9]] == [xab.BSS] * 4 and [s[3] for s in seen[5:9]] == [4, 8, 16, 32]
     assert seen[9][0] == xab.SYM_ATOMIC and seen[10][0] == seen[11][0] == xab.SYM_S3
+    assert seen[12][0] == xab.XCB and seen[12][3] == 2
     with pytest.raises(xab.XabError):
-        xab.class_params(12)
+        xab.class_params(13)
 
 
 def test_status_strings_and_null_checks():
@@ -81,7 +82,7 @@ def test_status_strings_and_null_checks():
     assert L.xab_bicgstab(None, None, None, None, None, None, None) == -1
     assert L.xab_features(None, None, None, None) == -1
     assert L.xab_class_params(0, None, None) == -1
-    assert xab.MLP_NPARAMS == 64 * 12 + 64 + 64 * 64 + 64 + 12 * 64 + 12
+    assert xab.MLP_NPARAMS == 64 * 12 + 64 + 64 * 64 + 64 + 13 * 64 + 13
 
 
 def test_product_path_has_no_oracle_dependency():

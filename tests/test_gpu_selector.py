@@ -50,9 +50,9 @@ def test_select_time_is_argmin(ctx, name):
     valid = [k for k in range(K) if info.valid[k]]
     assert valid, "no valid class"
     if A.sym_lower:
-        assert all(k >= 9 for k in valid)
+        assert set(valid) <= set(xab.SYM_CLASSES)
     else:
-        assert valid == list(range(9))
+        assert valid == list(xab.GENERAL_CLASSES)
     t = {k: info.time_ms[k] for k in valid}
     best = min(valid, key=lambda k: (t[k], k))
     assert info.chosen == best
@@ -185,7 +185,7 @@ def _synthetic_costs(m, seed):
     W = rng.standard_normal((K, 12)) * 0.4
     cost = np.exp2(np.abs((feat - 3) @ W.T) * 0.5).astype(np.float32) * 1e-2
     valid = np.ones((m, K), dtype=np.uint8)
-    valid[:, 9:] = 0
+    valid[:, list(xab.SYM_CLASSES)] = 0
     return feat, cost, valid
 
 

@@ -63,7 +63,7 @@ def general_suite():
 
 
 GENERAL = general_suite()
-GENERAL_CLASSES = list(range(9))
+GENERAL_CLASSES = list(xab.GENERAL_CLASSES)
 
 
 def _int_version(A, seed=5):
@@ -122,6 +122,25 @@ def test_bss_plan_bitexact(ctx):
             assert np.array_equal(P.array(3), carry), (name, J)
 
 
+def test_xcb_plan_bitexact(ctx):
+    for name, A in GENERAL.items():
+        M = ctx.matrix_from_csr(A)
+        P = ctx.plan(M, xab.XCB, j_per_lane=4)
+        rp, ci = oracle.plan_xcb(A, 8)
+        assert np.array_equal(P.array(9), rp.reshape(-1)), name
+        assert np.array_equal(P.array(10), ci), name
+
+
+@pytest.mark.parametrize("J", [1, 4, 8, 32])
+def test_xcb_all_lane_widths(ctx, J):
+    A = _int_version(gen.powerlaw(50_000, seed=2))
+    x = gen.int_vec(A.ncols, 2)
+    yo, _ = oracle.spmv(A, x)
+    M = ctx.matrix_from_csr(A)
+    P = ctx.plan(M, xab.XCB, j_per_lane=J)
+    assert np.array_equal(ctx.spmv(P, dev(x)).cpu().numpy(), yo)
+
+
 @pytest.mark.parametrize("J", [1, 2, 4, 8, 16, 32])
 def test_bss_all_lane_widths(ctx, J):
     A = _int_version(gen.trans4_like())
@@ -151,7 +170,7 @@ FP32_COMBOS = [  # (y dtype, acc) with x and values FP32
 
 
 @pytest.mark.parametrize("name", ["powerlaw", "trans4", "lap2d", "one_long_row"])
-@pytest.mark.parametrize("k", [0, 1, 3, 6, 8])
+@pytest.mark.parametrize("k", [0, 1, 3, 6, 8, 12])
 @pytest.mark.parametrize("combo", range(3))
 def test_general_fp32(ctx, name, k, combo):
     ydt, acc = FP32_COMBOS[combo]

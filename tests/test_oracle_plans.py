@@ -248,3 +248,45 @@ def test_plan_sym_stencil_touch_is_sparse():
     per_tile = np.diff(plan["tile_ptr"])
     assert per_tile.max() <= 12
     assert plan["tm_tile"].size < 0.2 * P * nblk
+
+
+@pytest.mark.parametrize("case", sorted(ADVERSARIAL))
+@pytest.mark.parametrize("nb", [1, 3, 8])
+def test_plan_xcb_brute(case, nb):
+    """Column blocks k = [floor(k ncols/nb), floor((k+1) ncols/nb)): per-block
+    row pointers and the concatenated, order-preserving column lists."""
+    A = _mat(ADVERSARIAL[case], seed=2, ncols=50)
+    rp, ci = oracle.plan_xcb(A, nb)
+    bounds = [(k * A.ncols) // nb for k in range(nb + 1)]
+    want_ci = []
+    for k in range(nb):
+        cnt = [0]
+        for i in range(A.n):
+            row = [int(c) for c in A.colind[A.rowptr[i]:A.rowptr[i + 1]] if bounds[k] <= c < bounds[k + 1]]
+            want_ci.extend(row)
+            cnt.append(cnt[-1] + len(row))
+        assert np.array_equal(rp[k], np.array(cnt))
+    assert np.array_equal(ci, np.array(want_ci, dtype=np.int32))
+
+
+def test_xcb_decomposition_is_exact():
+    """Summing the per-block products reproduces A x exactly (integers)."""
+    A = _mat([3, 0, 7, 1, 12, 0, 5] * 5, seed=4, ncols=40)
+    x = gen.int_vec(A.ncols, 2)
+    rp, ci = oracle.plan_xcb(A, 8)
+    # values follow their column in the same stable order
+    vals = []
+    bounds = [(k * A.ncols) // 8 for k in range(9)]
+    for k in range(8):
+        for i in range(A.n):
+            for e in range(A.rowptr[i], A.rowptr[i + 1]):
+                if bounds[k] <= A.colind[e] < bounds[k + 1]:
+                    vals.append(A.val[e])
+    y = np.zeros(A.n)
+    base = 0
+    for k in range(8):
+        for i in range(A.n):
+            for q in range(base + rp[k][i], base + rp[k][i + 1]):
+                y[i] += vals[q] * x[ci[q]]
+        base += rp[k][A.n]
+    assert np.array_equal(y, oracle.spmv(A, x)[0])
