@@ -13,12 +13,26 @@ divided by the timed wall time of the K steps.
 
 Extra fields on the same JSON line: the FP32-value SpMV rate, the
 time-to-1e-10 of GMRES(30) in FP64 and in mixed precision with FP64
-refinement, the selector's choice and timings, the roofline of the dominant
-kernel and the CPU oracle baseline.
+refinement, the selector's choices (TIME and LEARNED) and timings, the
+roofline of the dominant kernel and the CPU oracle baseline.
+
+Hardware-counter traffic: before the timed region the script runs a plain
+streaming copy of known size (torch.neg over 256 MiB, read once, written
+once).  Two rocprofv3 counter runs of this script, one for FETCH_SIZE and one
+for WRITE_SIZE, are reduced by `--pmc-summary` into a JSON summary under
+profiles/: per SpMV kernel the counter per dispatch, scaled by
+known bytes / counter reading of the copy kernel.  The bench reports that
+figure as roofline.traffic while the SpMV sources still hash to the value
+recorded with the counters, else null.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+       python bench.py --pmc-summary FETCH_DIR WRITE_DIR --out FILE
 """
 import argparse
+import collections
+import csv
+import glob
+import hashlib
 import json
 import os
 import sys
@@ -30,6 +44,19 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+CAL_BYTES = 256 << 20
+PROFILES = os.path.join(ROOT, "profiles")
+# sources whose change invalidates recorded counter figures of the SpMV kernels
+SPMV_SOURCES = ("internal.h", "segchunk.h", "sym_layout.h", "spmv.hip", "spmv_seg.hip", "spmv_row.hip", "plan.hip")
+# kernels one SpMV of each implementation launches
+VARIANT_KERNELS = {
+    "ROW": ("k_spmv_row",),
+    "NNZ": ("k_spmv_nnz",),
+    "BSS": ("k_spmv_bss", "k_bss_fixup"),
+    "XCB": ("k_spmv_xcb", "k_xcb_fixup", "k_xcb_combine"),
+    "SYM_S3": ("k_spmv_sym_s3", "k_sym_block_reduce"),
+    "SYM_ATOMIC": ("k_zero", "k_spmv_sym_atomic"),
+}
 
 
 def alg_bytes(n, nnz, val_bytes, x_bytes, y_bytes, idx_bytes=4):
@@ -40,6 +67,87 @@ def alg_bytes(n, nnz, val_bytes, x_bytes, y_bytes, idx_bytes=4):
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def spmv_source_hash():
+    h = hashlib.sha256()
+    for f in SPMV_SOURCES:
+        with open(os.path.join(ROOT, "paper_2405_01599_amd", "csrc", f), "rb") as fh:
+            h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()
+
+
+def traffic_file(variant, n):
+    return os.path.join(PROFILES, f"spmv_{variant.lower()}_fp64_powerlaw_n{n}_traffic.json")
+
+
+def calibration_copy(torch):
+    """The plain streaming copy the counter runs are scaled by."""
+    a = torch.full((CAL_BYTES // 8,), 1.0, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        torch.neg(a, out=b)
+    torch.cuda.synchronize()
+
+
+def _counter_csv(d):
+    files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    if len(files) != 1:
+        raise SystemExit(f"expected one counter_collection.csv under {d}, found {files}")
+    per = collections.defaultdict(list)
+    with open(files[0]) as fh:
+        for r in csv.DictReader(fh):
+            per[(r["Kernel_Name"], r["Counter_Name"])].append(float(r["Counter_Value"]))
+    return per
+
+
+def pmc_summary(fetch_dir, write_dir, out, variant, n, cmd_fetch, cmd_write):
+    """Reduce the two counter runs to bytes per SpMV (FP64 instances)."""
+    F, W = _counter_csv(fetch_dir), _counter_csv(write_dir)
+    def mean(per, name, ctr):
+        v = per.get((name, ctr))
+        return (sum(v) / len(v), len(v)) if v else (None, 0)
+    names = sorted({k for k, _ in F} | {k for k, _ in W})
+    cal = [k for k in names if "neg" in k.lower() and "elementwise" in k.lower()]
+    if len(cal) != 1:
+        raise SystemExit(f"calibration kernel not found once: {cal}")
+    cf, _ = mean(F, cal[0], "FETCH_SIZE")
+    cw, _ = mean(W, cal[0], "WRITE_SIZE")
+    ff, fw = CAL_BYTES / (cf * 1024.0), CAL_BYTES / (cw * 1024.0)
+    ker = {}
+    rd = wr = 0.0
+    for frag in VARIANT_KERNELS[variant]:
+        cand = [k for k in names if f"::{frag}<" in k and "float" not in k]
+        if len(cand) != 1:
+            raise SystemExit(f"kernel {frag}: {len(cand)} FP64 instances found")
+        f, nf = mean(F, cand[0], "FETCH_SIZE")
+        w, nw = mean(W, cand[0], "WRITE_SIZE")
+        ker[frag] = {"name": cand[0][:160], "fetch_kib_per_dispatch": f, "write_kib_per_dispatch": w,
+                     "dispatches": [nf, nw], "read_bytes": f * 1024 * ff, "write_bytes": w * 1024 * fw}
+        rd += f * 1024 * ff
+        wr += w * 1024 * fw
+    rep = {"workload": f"power-law CSR n={n}, FP64 SpMV", "variant": variant,
+           "command_fetch": cmd_fetch, "command_write": cmd_write,
+           "calibration": {"kernel": cal[0][:160], "bytes_read": CAL_BYTES, "bytes_written": CAL_BYTES,
+                           "fetch_kib": cf, "write_kib": cw, "fetch_factor": ff, "write_factor": fw},
+           "kernels": ker, "traffic_bytes_per_spmv": {"read": rd, "write": wr, "total": rd + wr},
+           "source_sha256": spmv_source_hash()}
+    with open(out, "w") as fh:
+        json.dump(rep, fh, indent=1)
+    print(json.dumps(rep["traffic_bytes_per_spmv"]))
+
+
+def recorded_traffic(variant, n):
+    """HBM bytes per SpMV from the committed counter summary, if it still
+    describes the current kernels; (value, note)."""
+    path = traffic_file(variant, n)
+    if not os.path.exists(path):
+        return None, "no counter summary for this kernel and workload"
+    with open(path) as fh:
+        rep = json.load(fh)
+    if rep.get("source_sha256") != spmv_source_hash():
+        return None, "SpMV sources changed since the counters were taken"
+    return round(rep["traffic_bytes_per_spmv"]["total"]), os.path.relpath(path, ROOT)
 
 
 def cpu_baseline(A, x, budget_s=10.0):
@@ -67,7 +175,15 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-gmres", action="store_true")
     ap.add_argument("--n", type=int, default=2_000_000)
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
+    ap.add_argument("--variant", default="XCB")
+    ap.add_argument("--out")
+    ap.add_argument("--cmd-fetch", default="")
+    ap.add_argument("--cmd-write", default="")
     args = ap.parse_args()
+    if args.pmc_summary:
+        pmc_summary(*args.pmc_summary, args.out, args.variant, args.n, args.cmd_fetch, args.cmd_write)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding "
               "is a design note, not a measured path", file=sys.stderr)
@@ -88,8 +204,21 @@ def main():
     y32 = torch.empty(A.n, dtype=torch.float32, device="cuda")
     torch.cuda.synchronize()
 
-    log("selecting (TIME policy)")
+    calibration_copy(torch)
+
+    log("selecting (LEARNED, then TIME policy)")
+    ctx.select(M, xab.LEARNED)[0].close()  # first call loads the shipped model
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lplan, linfo = ctx.select(M, xab.LEARNED)
+    torch.cuda.synchronize()
+    learned = {"chosen_class": int(linfo.chosen), "select_ms": round((time.perf_counter() - t0) * 1e3, 2)}
+    lplan.close()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
     plan, info = ctx.select(M, xab.TIME)
+    torch.cuda.synchronize()
+    time_wall_ms = (time.perf_counter() - t0) * 1e3
     chosen = int(info.chosen)
     times = {k: round(float(info.time_ms[k]) * 1e3, 2) for k in range(xab.NCLASSES) if info.valid[k]}
 
@@ -110,9 +239,12 @@ def main():
     # context stream (the stream the kernels are queued on)
     ev_ms = ctx.time_spmv(plan, xd, y, warmup=5, reps=100)
     ach = by64 / (ev_ms * 1e-3) / 1e9
+    variant = plan.describe()["variant"]
+    traffic, tnote = recorded_traffic(variant, A.n)
     roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": plan.describe()["variant"], "bytes_per_launch": by64, "us_per_launch": round(ev_ms * 1e3, 2)}
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic, "traffic_source": tnote,
+                "kernel": f"{variant} SpMV: " + " + ".join(VARIANT_KERNELS.get(variant, ())),
+                "bytes_per_launch": by64, "us_per_launch": round(ev_ms * 1e3, 2)}
 
     # FP32 values and x, FP64 accumulation, FP32 y (the inner SpMV of GMRES-IR)
     plan32 = ctx.plan_class(M, chosen)
@@ -161,7 +293,8 @@ def main():
         "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
         "gflops": round(2 * A.nnz / (wall / args.steps) / 1e9, 1),
         "fp32_values": fp32,
-        "selector": {"chosen_class": chosen, "us_per_class": times, "select_ms": round(float(info.select_ms), 2)},
+        "selector": {"chosen_class": chosen, "us_per_class": times, "select_ms": round(float(info.select_ms), 2),
+                     "select_wall_ms": round(time_wall_ms, 2), "learned": learned},
         "gmres": gm,
         "roofline": roofline,
         "cpu_baseline": cpu,

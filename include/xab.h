@@ -157,8 +157,9 @@ int xab_plan_fixed(xab_ctx *ctx, const xab_matrix *A, xab_variant v, const xab_p
 void xab_plan_destroy(xab_plan *plan);
 /* Read back plan arrays (for checking).  which: 0 nnz-split b / sym tiles b,
  * 1 BSS row_lo, 2 BSS tile_row, 3 BSS carry_row, 4 tm_ptr, 5 tm_tile,
- * 6 tile_ptr, 7 tile_blk, 8 tile_slot.  *len receives the length; h_out may
- * be NULL to query it.  Synchronous. */
+ * 6 tile_ptr, 7 tile_blk, 8 tile_slot, 9 XCB per-block row pointers
+ * (8 x (nrows+1), block-major), 10 XCB column indices in block order.
+ * *len receives the length; h_out may be NULL to query it.  Synchronous. */
 int xab_plan_array(const xab_plan *plan, int32_t which, int32_t *h_out, int64_t *len);
 int xab_plan_info(const xab_plan *plan, xab_variant *v, xab_params *p);
 
@@ -205,9 +206,9 @@ int xab_select(xab_ctx *ctx, const xab_matrix *A, xab_policy policy, xab_plan **
  * Synchronous. */
 int xab_features(xab_ctx *ctx, const xab_matrix *A, float *h_out, int64_t *h_stats);
 
-/* Cost model: MLP 12-64-64-12, FP32, ReLU, outputs = predicted
- * log2(t_k / t_best).  Parameters in the flat layout W1[64x12] b1[64]
- * W2[64x64] b2[64] W3[12x64] b3[12] (row-major, out x in), preceded by the
+/* Cost model: MLP 12-64-64-K with K = XAB_NCLASSES, FP32, ReLU, outputs =
+ * predicted log2(t_k / t_best).  Parameters in the flat layout W1[64x12]
+ * b1[64] W2[64x64] b2[64] W3[Kx64] b3[K] (row-major, out x in), preceded by the
  * feature standardisation mean[12] and std[12].  XAB_MLP_NPARAMS counts
  * only the network. */
 #define XAB_MLP_NPARAMS (64 * 12 + 64 + 64 * 64 + 64 + XAB_NCLASSES * 64 + XAB_NCLASSES)
@@ -231,8 +232,8 @@ typedef struct {
 /* Train the cost model on the GPU with the library's own forward, backward
  * and Adam kernels.  d_feat[m*12] raw features (standardised internally
  * with the training-set mean/std, which are stored with the weights),
- * d_cost[m*12] measured times (ms; entries with d_valid = 0 ignored),
- * d_valid[m*12] uint8.  Starts from the parameters last set with
+ * d_cost[m*K] measured times (ms; entries with d_valid = 0 ignored),
+ * d_valid[m*K] uint8 (K = XAB_NCLASSES).  Starts from the parameters last set with
  * xab_selector_set.  h_order[epochs*m] gives the sample order of each epoch
  * (the caller's shuffle).  h_loss (may be NULL) receives one loss per
  * epoch.  Synchronous. */

@@ -178,6 +178,7 @@ class Context:
         h = ctypes.c_void_p()
         self._check(lib().xab_init(ctypes.byref(h), ctypes.byref(opts)), "xab_init", ctx=False)
         self.h = h
+        self._has_model = False
 
     def _check(self, s, what, ctx=True):
         if s < 0:
@@ -223,6 +224,11 @@ class Context:
         return Plan(self, A, v, params=p)
 
     def select(self, A, policy=TIME):
+        """Run the selector.  LEARNED uses the cost model last set, loaded or
+        trained on this context, else the one shipped with the package."""
+        if policy == LEARNED and not self._has_model:
+            from .selector import MODEL_PATH
+            self.selector_load(MODEL_PATH)
         h = ctypes.c_void_p()
         info = SelectInfo()
         self._check(lib().xab_select(self.h, A.h, policy, ctypes.byref(h), ctypes.byref(info)), "xab_select")
@@ -266,6 +272,7 @@ class Context:
         assert p.size == MLP_NPARAMS and m.size == NFEAT and s.size == NFEAT
         self._check(lib().xab_selector_set(self.h, p.ctypes.data_as(_P), m.ctypes.data_as(_P), s.ctypes.data_as(_P)),
                     "xab_selector_set")
+        self._has_model = True
 
     def selector_get(self):
         p = np.zeros(MLP_NPARAMS, dtype=np.float32)
@@ -280,6 +287,7 @@ class Context:
 
     def selector_load(self, path):
         self._check(lib().xab_selector_load(self.h, str(path).encode()), "xab_selector_load")
+        self._has_model = True
 
     def selector_train(self, feat, cost, valid, order, epochs=300, batch=128, lr=1e-3):
         torch = _torch()

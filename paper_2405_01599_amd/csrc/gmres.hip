@@ -15,6 +15,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstring>
 #include <vector>
 
 #include "blas.h"
@@ -32,8 +33,11 @@ struct Work {
     int *gate = nullptr;
     void *V = nullptr, *w = nullptr, *z = nullptr;
     int64_t ldv = 0;
+    size_t small_bytes = 0;  // h1 .. gate, read back in one copy per step
+    double *host = nullptr;  // pinned mirror of that region
     ~Work() {
         if (base) xab_dfree(ctx, base);
+        if (host) (void)hipHostFree(host);
     }
 };
 
@@ -59,6 +63,11 @@ int alloc_work(xab_ctx *ctx, Work &W, int64_t n, int m, size_t tsize) {
     W.V = b + off_V;
     W.w = b + off_w;
     W.z = b + off_z;
+    W.small_bytes = sizeof(double) * (3 * (size_t)(m + 2) + 8) + sizeof(int);
+    if (hipHostMalloc((void **)&W.host, W.small_bytes, hipHostMallocDefault) != hipSuccess) {
+        W.host = nullptr;
+        return xab_fail(ctx, XAB_E_NOMEM, "pinned host buffer");
+    }
     return XAB_OK;
 }
 
@@ -84,7 +93,7 @@ int cycle(xab_ctx *ctx, const xab_plan *pl, xab_matrix *A, Work &W, int m, doubl
     int s;
     // v0 = r / beta, z = M^-1 v0
     if ((s = xab::scale_from<double, T>(ctx, W.r, 1.0 / beta, V, z, d, n)) != XAB_OK) return s;
-    std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), g(m + 1, 0.0), hb(2 * (m + 2) + 2);
+    std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), g(m + 1, 0.0);
     g[0] = beta;
     int k = 0;
     out.breakdown = false;
@@ -105,15 +114,14 @@ int cycle(xab_ctx *ctx, const xab_plan *pl, xab_matrix *A, Work &W, int m, doubl
         // v_{j+1} = w / ||w||, z = M^-1 v_{j+1}
         T *vn = V + (int64_t)(j + 1) * W.ldv;
         if ((s = xab::scale_precond<T>(ctx, w, W.sc, vn, z, d, n)) != XAB_OK) return s;
-        int gate = 0;
-        XAB_HIP(ctx, hipMemcpyAsync(hb.data(), W.h1, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, ctx->stream));
-        XAB_HIP(ctx, hipMemcpyAsync(hb.data() + (m + 2), W.h2, sizeof(double) * (j + 1), hipMemcpyDeviceToHost,
-                                    ctx->stream));
-        XAB_HIP(ctx, hipMemcpyAsync(&hb[2 * (m + 2)], W.sc, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
-        XAB_HIP(ctx, hipMemcpyAsync(&gate, W.gate, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+        // one read-back of h1, h2, ||w||^2 and the DGKS gate (contiguous)
+        XAB_HIP(ctx, hipMemcpyAsync(W.host, W.h1, W.small_bytes, hipMemcpyDeviceToHost, ctx->stream));
         XAB_HIP(ctx, hipStreamSynchronize(ctx->stream));
-        for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hb[i] + (gate ? hb[(m + 2) + i] : 0.0);
-        const double hn = std::sqrt(hb[2 * (m + 2)]);
+        const double *hh = W.host;
+        int gate = 0;
+        memcpy(&gate, (const char *)W.gate - (const char *)W.h1 + (const char *)W.host, sizeof(int));
+        for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hh[i] + (gate ? hh[(m + 2) + i] : 0.0);
+        const double hn = std::sqrt(hh[2 * (m + 2)]);
         H[(size_t)(j + 1) * m + j] = hn;
         // earlier rotations on column j, then a new one
         for (int i = 0; i < j; ++i) {
