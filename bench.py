@@ -239,7 +239,7 @@ def main():
     # context stream (the stream the kernels are queued on)
     ev_ms = ctx.time_spmv(plan, xd, y, warmup=5, reps=100)
     ach = by64 / (ev_ms * 1e-3) / 1e9
-    variant = plan.describe()["variant"]
+    variant = plan.describe()["variant"].upper()
     traffic, tnote = recorded_traffic(variant, A.n)
     roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic, "traffic_source": tnote,

@@ -158,7 +158,8 @@ void xab_plan_destroy(xab_plan *plan);
 /* Read back plan arrays (for checking).  which: 0 nnz-split b / sym tiles b,
  * 1 BSS row_lo, 2 BSS tile_row, 3 BSS carry_row, 4 tm_ptr, 5 tm_tile,
  * 6 tile_ptr, 7 tile_blk, 8 tile_slot, 9 XCB per-block row pointers
- * (8 x (nrows+1), block-major), 10 XCB column indices in block order.
+ * (8 x (nrows+1), block-major), 10 XCB column indices in block order,
+ * bit 31 set on the first entry of each row within its block.
  * *len receives the length; h_out may be NULL to query it.  Synchronous. */
 int xab_plan_array(const xab_plan *plan, int32_t which, int32_t *h_out, int64_t *len);
 int xab_plan_info(const xab_plan *plan, xab_variant *v, xab_params *p);

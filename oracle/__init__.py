@@ -36,6 +36,7 @@ def lib():
             "orc_plan_sym_tiles": (None, [i64, P, i64, i64, P]),
             "orc_plan_sym_touch": (i64, [i64, P, P, i64, P, i64, P, P, P, P, P]),
             "orc_plan_xcb": (None, [i64, i64, P, P, ci, P, P]),
+            "orc_xcb_flag_heads": (None, [i64, ci, P, P]),
             "orc_features": (None, [i64, P, P, ci, P, P]),
             "orc_mlp_nparams": (i64, [ci, ci, ci]),
             "orc_mlp_forward": (None, [ci, ci, ci, P, i64, P, P]),
@@ -147,12 +148,16 @@ def plan_sym(A, T, Rmax, C):
                 tile_slot=tile_slot[:nt])
 
 
-def plan_xcb(A, nb=8):
-    """Column-blocked split: (rp[nb, n+1] relative row pointers, concatenated colind)."""
+def plan_xcb(A, nb=8, flagged=False):
+    """Column-blocked split: (rp[nb, n+1] relative row pointers, concatenated
+    colind); with flagged=True the first entry of each row of each block
+    carries bit 31 in its column index."""
     rp, ci, _ = _csr(A)
     out_rp = np.empty((nb, A.n + 1), dtype=np.int32)
     out_ci = np.empty(max(A.nnz, 1), dtype=np.int32)
     lib().orc_plan_xcb(A.n, A.ncols, _p(rp), _p(ci), nb, _p(out_rp), _p(out_ci))
+    if flagged:
+        lib().orc_xcb_flag_heads(A.n, nb, _p(out_rp), _p(out_ci))
     return out_rp, out_ci[:A.nnz]
 
 

@@ -310,6 +310,20 @@ void orc_plan_xcb(int64_t n, int64_t ncols, const int32_t *rowptr, const int32_t
     free(blk_lo);
 }
 
+/* The column-blocked copy's row-start flags: within each block, the first
+ * entry of every row that has entries in the block gets bit 31 of its
+ * column index set (the head flag of a segmented-scan format, stored in the
+ * otherwise unused sign bit).  rp and ci as orc_plan_xcb wrote them. */
+void orc_xcb_flag_heads(int64_t n, int nb, const int32_t *rp, int32_t *ci) {
+    int64_t base = 0;
+    for (int k = 0; k < nb; ++k) {
+        const int32_t *r = rp + (int64_t)k * (n + 1);
+        for (int64_t i = 0; i < n; ++i)
+            if (r[i + 1] > r[i]) ci[base + r[i]] = (int32_t)((uint32_t)ci[base + r[i]] | 0x80000000u);
+        base += r[n];
+    }
+}
+
 /* ------------------------------------------------------------- features */
 
 /* stats: [0] n, [1] nnz, [2] sum len^2, [3] max len, [4] max |i-j|,

@@ -63,6 +63,7 @@ int64_t orc_plan_sym_touch(int64_t n, const int32_t *rowptr, const int32_t *coli
  * row order (original order inside a row), then block 1, and so on. */
 void orc_plan_xcb(int64_t n, int64_t ncols, const int32_t *rowptr, const int32_t *colind, int nb, int32_t *rp,
                   int32_t *ci);
+void orc_xcb_flag_heads(int64_t n, int nb, const int32_t *rp, int32_t *ci);
 
 /* Selector features: integer statistics then the 12 features. */
 void orc_features(int64_t n, const int32_t *rowptr, const int32_t *colind, int sym_lower,

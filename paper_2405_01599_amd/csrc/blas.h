@@ -5,7 +5,7 @@
 namespace xab {
 
 constexpr int kPartLd = 72;    // stride of one workgroup's partial sums (>= 64 vectors + norm)
-constexpr int kRedBlocks = 512; // workgroups of the reduction kernels
+constexpr int kRedBlocks = 2048; // workgroups of the reduction kernels (8 per CU)
 
 template <class T>
 int mdot(xab_ctx *ctx, const T *V, int64_t ldv, int nv, const T *w, int64_t n, double *part, int nb,

@@ -107,17 +107,26 @@ __global__ __launch_bounds__(kNT) void k_mdot_gated(const T *__restrict__ V, int
 
 }  // namespace
 
-// out[i] = sum over b (ascending) of part[b * ldp + i], i < m.  Optional
-// accumulate: out[i] += ... when add != 0.  When `gate` is non-null and
-// *gate == 0 nothing happens.
-__global__ void k_reduce_parts(const double *__restrict__ part, int nb, int ldp, int m, double *__restrict__ out,
-                               int add, const int *__restrict__ gate) {
+// out[i] = sum over b of part[b * ldp + i], i < m, one workgroup per i:
+// lane t sums slots t, t + 256, ... in ascending order, then a fixed LDS
+// tree joins the lanes.  Optional accumulate: out[i] += ... when add != 0.
+// When `gate` is non-null and *gate == 0 nothing happens.
+__global__ __launch_bounds__(kNT) void k_reduce_parts(const double *__restrict__ part, int nb, int ldp, int m,
+                                                      double *__restrict__ out, int add,
+                                                      const int *__restrict__ gate) {
+    __shared__ double sh[kNT];
     if (gate && *gate == 0) return;
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= m) return;
+    const int i = blockIdx.x;
     double a = 0.0;
-    for (int b = 0; b < nb; ++b) a += part[(int64_t)b * ldp + i];
-    out[i] = add ? out[i] + a : a;
+    for (int b = threadIdx.x; b < nb; b += kNT) a += part[(int64_t)b * ldp + i];
+    sh[threadIdx.x] = a;
+    __syncthreads();
+#pragma unroll
+    for (int d = kNT / 2; d > 0; d >>= 1) {
+        if (threadIdx.x < d) sh[threadIdx.x] += sh[threadIdx.x + d];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[i] = add ? out[i] + sh[0] : sh[0];
 }
 
 // DGKS test: *gate = ||w'|| < eta ||w|| given squared norms (one thread).
@@ -242,7 +251,8 @@ template int update_norm<float>(xab_ctx *, const float *, int64_t, int, const do
                                 int, const int *);
 
 int reduce_parts(xab_ctx *ctx, const double *part, int nb, int ldp, int m, double *out, int add, const int *gate) {
-    hipLaunchKernelGGL(k_reduce_parts, dim3((m + 63) / 64), dim3(64), 0, ctx->stream, part, nb, ldp, m, out, add, gate);
+    if (m <= 0) return XAB_OK;
+    hipLaunchKernelGGL(k_reduce_parts, dim3(m), dim3(kNT), 0, ctx->stream, part, nb, ldp, m, out, add, gate);
     XAB_LAUNCH_CHECK(ctx, "k_reduce_parts");
     return XAB_OK;
 }

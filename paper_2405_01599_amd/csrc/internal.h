@@ -73,11 +73,9 @@ struct xab_plan {
     // XCB: column-blocked copy of the matrix, one CSR per column block
     static constexpr int kXcb = 8;
     int32_t *xcb_rowptr = nullptr;      // kXcb * (n + 1), each relative to its block's first entry
-    int32_t *xcb_crowptr = nullptr;     // the same over each block's non-empty rows: kXcb * (n + 1) slots
-    int32_t *xcb_ridx = nullptr;        // kXcb * n slots: global row of each block's j-th non-empty row
     uint8_t *xcb_mask = nullptr;        // n: bit k set when row i has entries in block k
-    int64_t xcb_m[kXcb] = {0};          // non-empty rows per block
-    int32_t *xcb_colind = nullptr;      // nnz, the blocks concatenated
+    int64_t xcb_m[kXcb] = {0};          // non-empty rows per block (the block's compressed rows)
+    int32_t *xcb_colind = nullptr;      // nnz, the blocks concatenated; bit 31 flags a compressed row's first entry
     double *xcb_val64 = nullptr;        // copies of the values in the same order
     float *xcb_val32 = nullptr;
     int64_t xcb_base[kXcb + 1] = {0};   // block k holds entries [base[k], base[k+1])
@@ -85,7 +83,10 @@ struct xab_plan {
     int64_t xcb_toff[kXcb + 1] = {0};   // tile offsets of the blocks in the descriptor arrays
     int32_t *xcb_row_lo = nullptr, *xcb_carry_row = nullptr, *xcb_tail_row = nullptr, *xcb_tile_row = nullptr;
     void *xcb_carry_val = nullptr, *xcb_tail_val = nullptr;  // acc-type, per tile
-    void *xcb_Y = nullptr;              // kXcb partial products, acc-type, kXcb * n
+    int64_t xcb_ybase[kXcb + 1] = {0};  // block k's partials: Y[ybase[k] .. ybase[k] + m_k)
+    void *xcb_Y = nullptr;              // compressed partial products, acc-type, ybase[kXcb] slots
+    int64_t xcb_G = 0;                  // row groups of 256 (the combine's workgroups)
+    int32_t *xcb_gbase = nullptr;       // kXcb * (G + 1): compressed index of group g's first row in block k
 };
 
 struct xab_batch {

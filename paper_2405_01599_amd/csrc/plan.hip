@@ -287,20 +287,38 @@ __global__ void k_nonzero_flags(const int32_t *cnt, int32_t n, int32_t *flag) {
     if (i < n) flag[i] = cnt[i] > 0;
 }
 
-// a block's CSR restricted to its non-empty rows: ridx[j] = global row of
-// the j-th such row, crp[j] = its start, crp[m] = the block's size
+// a block's CSR restricted to its non-empty rows: crp[j] = start of the
+// j-th such row, crp[m] = the block's size
 __global__ void k_xcb_compress(const int32_t *flag, const int32_t *pos, const int32_t *rp_full, int32_t n,
-                               int32_t *ridx, int32_t *crp) {
+                               int32_t *crp) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i > n) return;
     if (i == n) {
         crp[pos[n]] = rp_full[n];
         return;
     }
-    if (flag[i]) {
-        ridx[pos[i]] = (int32_t)i;
-        crp[pos[i]] = rp_full[i];
-    }
+    if (flag[i]) crp[pos[i]] = rp_full[i];
+}
+
+// bit 31 on the first entry of each of the block's m non-empty rows
+__global__ void k_xcb_flag_heads(const int32_t *crp, int32_t m, int32_t *ci) {
+    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= m) return;
+    const int32_t e = crp[r];
+    ci[e] = (int32_t)((uint32_t)ci[e] | 0x80000000u);
+}
+
+// cnt[k * G + g] = rows of group g (256 rows) with entries in block k
+__global__ void k_xcb_group_counts(const uint8_t *mask, int32_t n, int64_t G, int32_t *cnt) {
+    __shared__ int32_t c[xab_plan::kXcb];
+    if (threadIdx.x < xab_plan::kXcb) c[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const uint32_t m = i < n ? mask[i] : 0u;
+    for (int k = 0; k < xab_plan::kXcb; ++k)
+        if ((m >> k) & 1u) atomicAdd(&c[k], 1);
+    __syncthreads();
+    if (threadIdx.x < xab_plan::kXcb) cnt[(int64_t)threadIdx.x * G + blockIdx.x] = c[threadIdx.x];
 }
 
 // stable scatter of every row's entries into its column block's CSR
@@ -345,8 +363,7 @@ static void free_plan_arrays(xab_ctx *ctx, xab_plan *pl) {
     xab_dfree(ctx, pl->tile_minblk);
     xab_dfree(ctx, pl->partial);
     xab_dfree(ctx, pl->xcb_rowptr);
-    xab_dfree(ctx, pl->xcb_crowptr);
-    xab_dfree(ctx, pl->xcb_ridx);
+    xab_dfree(ctx, pl->xcb_gbase);
     xab_dfree(ctx, pl->xcb_mask);
     xab_dfree(ctx, pl->xcb_colind);
     xab_dfree(ctx, pl->xcb_val64);
@@ -461,10 +478,10 @@ int xab_build_plan(xab_ctx *ctx, const xab_matrix *A, xab_variant v, const xab_p
         ALLOC(pl->xcb_colind, int32_t, std::max<int64_t>(1, nnz));
         if (A->has64) ALLOC(pl->xcb_val64, double, std::max<int64_t>(1, nnz));
         if (A->has32) ALLOC(pl->xcb_val32, float, std::max<int64_t>(1, nnz));
-        ALLOC(pl->xcb_Y, double, (int64_t)KB * std::max<int32_t>(1, n));
         cnt = (int32_t *)xab_dalloc(ctx, sizeof(int32_t) * (size_t)KB * std::max<int32_t>(1, n));
-        sums = (int32_t *)xab_dalloc(ctx, sizeof(int32_t) * (ntile + 1));
-        offs = (int32_t *)xab_dalloc(ctx, sizeof(int32_t) * (ntile + 1));
+        // scans of up to max(1, ntile) tile sums write one slot past them
+        sums = (int32_t *)xab_dalloc(ctx, sizeof(int32_t) * (ntile + 2));
+        offs = (int32_t *)xab_dalloc(ctx, sizeof(int32_t) * (ntile + 2));
         dbase = (int64_t *)xab_dalloc(ctx, sizeof(int64_t) * (KB + 1));
         auto free_tmp = [&]() {
             xab_dfree(ctx, cnt);
@@ -511,49 +528,90 @@ int xab_build_plan(xab_ctx *ctx, const xab_matrix *A, xab_variant v, const xab_p
             hipLaunchKernelGGL(k_xcb_scatter, dim3(grid_for(n, 256)), dim3(256), 0, st, A->rowptr, A->colind, A->val64,
                                A->val32, n, cbk, pl->xcb_rowptr, dbase, pl->xcb_colind, pl->xcb_val64, pl->xcb_val32);
         // each block's CSR over its non-empty rows (so no tile walks rows the
-        // block does not touch), and the per-row block mask for the combine
-        ALLOC(pl->xcb_crowptr, int32_t, (int64_t)KB * (n + 1));
-        ALLOC(pl->xcb_ridx, int32_t, (int64_t)KB * std::max<int32_t>(1, n));
-        ALLOC(pl->xcb_mask, uint8_t, std::max<int32_t>(1, n));
+        // block does not touch), the head flags in its columns, and the
+        // per-row block mask for the combine
+        int32_t *crowptr = (int32_t *)xab_dalloc(ctx, sizeof(int32_t) * (size_t)KB * (n + 1));
+        pl->xcb_mask = (uint8_t *)xab_dalloc(ctx, (size_t)std::max<int32_t>(1, n));
         int32_t *flag = (int32_t *)xab_dalloc(ctx, sizeof(int32_t) * (size_t)(n + 1));
         int32_t *pos = (int32_t *)xab_dalloc(ctx, sizeof(int32_t) * (size_t)(n + 1));
-        if (!flag || !pos) e = hipErrorOutOfMemory;
+        if (!flag || !pos || !crowptr || !pl->xcb_mask) e = hipErrorOutOfMemory;
         if (e == hipSuccess && n > 0)
             hipLaunchKernelGGL(k_xcb_mask, dim3(grid_for(n, 256)), dim3(256), 0, st, cnt, n, pl->xcb_mask);
-        int32_t mk[KB];
+        int32_t mk[KB] = {0};
         for (int k = 0; k < KB && e == hipSuccess; ++k) {
             const unsigned g = (unsigned)std::max<int64_t>(1, ntile);
+            int32_t *crp = crowptr + (int64_t)k * (n + 1);
             if (n > 0) hipLaunchKernelGGL(k_nonzero_flags, dim3(grid_for(n, 256)), dim3(256), 0, st, cnt + (int64_t)k * n, n, flag);
             hipLaunchKernelGGL(k_scan_tile_sums, dim3(g), dim3(256), 0, st, flag, (int64_t)n, sums);
             hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, st, sums, (int64_t)g, offs);
             hipLaunchKernelGGL(k_scan_tile_apply, dim3(g), dim3(256), 0, st, flag, (int64_t)n, offs, pos);
             hipLaunchKernelGGL(k_xcb_compress, dim3(grid_for(n + 1, 256)), dim3(256), 0, st, flag, pos,
-                               pl->xcb_rowptr + (int64_t)k * (n + 1), n, pl->xcb_ridx + (int64_t)k * n,
-                               pl->xcb_crowptr + (int64_t)k * (n + 1));
+                               pl->xcb_rowptr + (int64_t)k * (n + 1), n, crp);
             e = hipMemcpyAsync(&mk[k], pos + n, sizeof(int32_t), hipMemcpyDeviceToHost, st);
             if (e == hipSuccess) e = hipStreamSynchronize(st);  // flag / pos are reused by the next block
+            if (e == hipSuccess && mk[k] > 0)
+                hipLaunchKernelGGL(k_xcb_flag_heads, dim3(grid_for(mk[k], 256)), dim3(256), 0, st, crp, mk[k],
+                                   pl->xcb_colind + pl->xcb_base[k]);
+        }
+        if (e == hipSuccess) e = hipGetLastError();
+        // the combine's group offsets: exclusive scans over 256-row groups
+        pl->xcb_G = std::max<int64_t>(1, (n + 255) / 256);
+        const int64_t G = pl->xcb_G;
+        int32_t *gcnt = nullptr;
+        if (e == hipSuccess) {
+            pl->xcb_gbase = (int32_t *)xab_dalloc(ctx, sizeof(int32_t) * (size_t)KB * (G + 1));
+            gcnt = (int32_t *)xab_dalloc(ctx, sizeof(int32_t) * (size_t)KB * G);
+            if (!pl->xcb_gbase || !gcnt) e = hipErrorOutOfMemory;
+        }
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(k_xcb_group_counts, dim3((unsigned)G), dim3(256), 0, st, pl->xcb_mask, n, G, gcnt);
+            const int64_t gt = (G + kScanTile - 1) / kScanTile;  // <= ntile + 1 slots of sums / offs
+            for (int k = 0; k < KB; ++k) {
+                hipLaunchKernelGGL(k_scan_tile_sums, dim3((unsigned)gt), dim3(256), 0, st, gcnt + (int64_t)k * G, G, sums);
+                hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, st, sums, gt, offs);
+                hipLaunchKernelGGL(k_scan_tile_apply, dim3((unsigned)gt), dim3(256), 0, st, gcnt + (int64_t)k * G, G,
+                                   offs, pl->xcb_gbase + (int64_t)k * (G + 1));
+            }
+            e = hipGetLastError();
         }
         if (e == hipSuccess) e = hipStreamSynchronize(st);
+        xab_dfree(ctx, gcnt);
         xab_dfree(ctx, flag);
         xab_dfree(ctx, pos);
         free_tmp();
+        if (e != hipSuccess) xab_dfree(ctx, crowptr);
         CHECKED(hip_ok(ctx, e, "column-block scatter"));
-        for (int k = 0; k < KB; ++k) pl->xcb_m[k] = mk[k];
+        pl->xcb_ybase[0] = 0;
+        for (int k = 0; k < KB; ++k) {
+            pl->xcb_m[k] = mk[k];
+            pl->xcb_ybase[k + 1] = pl->xcb_ybase[k] + mk[k];
+        }
         const int64_t tt = pl->xcb_toff[KB];
-        ALLOC(pl->xcb_row_lo, int32_t, tt);
-        ALLOC(pl->xcb_tile_row, int32_t, tt);
-        ALLOC(pl->xcb_carry_row, int32_t, tt);
-        ALLOC(pl->xcb_tail_row, int32_t, tt);
-        ALLOC(pl->xcb_carry_val, double, tt);
-        ALLOC(pl->xcb_tail_val, double, tt);
+        pl->xcb_row_lo = (int32_t *)xab_dalloc(ctx, sizeof(int32_t) * (size_t)tt);
+        pl->xcb_tile_row = (int32_t *)xab_dalloc(ctx, sizeof(int32_t) * (size_t)tt);
+        pl->xcb_carry_row = (int32_t *)xab_dalloc(ctx, sizeof(int32_t) * (size_t)tt);
+        pl->xcb_tail_row = (int32_t *)xab_dalloc(ctx, sizeof(int32_t) * (size_t)tt);
+        pl->xcb_carry_val = xab_dalloc(ctx, sizeof(double) * (size_t)tt);
+        pl->xcb_tail_val = xab_dalloc(ctx, sizeof(double) * (size_t)tt);
+        pl->xcb_Y = xab_dalloc(ctx, sizeof(double) * (size_t)std::max<int64_t>(1, pl->xcb_ybase[KB]));
+        if (!pl->xcb_row_lo || !pl->xcb_tile_row || !pl->xcb_carry_row || !pl->xcb_tail_row || !pl->xcb_carry_val ||
+            !pl->xcb_tail_val || !pl->xcb_Y) {
+            xab_dfree(ctx, crowptr);
+            free_plan_arrays(ctx, pl);
+            delete pl;
+            return xab_fail(ctx, XAB_E_NOMEM, "plan allocation");
+        }
         for (int k = 0; k < KB; ++k) {
             const int64_t o = pl->xcb_toff[k];
             hipLaunchKernelGGL(k_split_bss, dim3(grid_for(pl->xcb_P[k] + 1, 256)), dim3(256), 0, st,
-                               pl->xcb_crowptr + (int64_t)k * (n + 1), (int32_t)pl->xcb_m[k], T, pl->xcb_P[k],
+                               crowptr + (int64_t)k * (n + 1), (int32_t)pl->xcb_m[k], T, pl->xcb_P[k],
                                pl->xcb_row_lo + o, pl->xcb_tile_row + o, pl->xcb_carry_row + o);
             pl->P = std::max(pl->P, pl->xcb_P[k]);
         }
-        CHECKED(hip_ok(ctx, hipGetLastError(), "column-block tiles"));
+        e = hipGetLastError();
+        if (e == hipSuccess) e = hipStreamSynchronize(st);  // crowptr is freed next
+        xab_dfree(ctx, crowptr);
+        CHECKED(hip_ok(ctx, e, "column-block tiles"));
     } else {  // XAB_SYM_S3
         const int32_t C = p.col_block;
         const int32_t bmax = xab::sym::kExtCap / C;

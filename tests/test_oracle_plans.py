@@ -290,3 +290,51 @@ def test_xcb_decomposition_is_exact():
                 y[i] += vals[q] * x[ci[q]]
         base += rp[k][A.n]
     assert np.array_equal(y, oracle.spmv(A, x)[0])
+
+
+@pytest.mark.parametrize("case", sorted(ADVERSARIAL))
+@pytest.mark.parametrize("nb", [1, 3, 8])
+def test_xcb_flags_brute(case, nb):
+    """Bit 31 is set exactly on the first entry of every row of every block;
+    clearing it gives back the unflagged columns."""
+    A = _mat(ADVERSARIAL[case], seed=3, ncols=50)
+    rp, ci = oracle.plan_xcb(A, nb)
+    _, cf = oracle.plan_xcb(A, nb, flagged=True)
+    want = ci.copy()
+    base = 0
+    for k in range(nb):
+        for i in range(A.n):
+            if rp[k][i + 1] > rp[k][i]:
+                want[base + rp[k][i]] = np.int32(int(want[base + rp[k][i]]) - 2**31)
+        base += rp[k][A.n]
+    assert np.array_equal(cf, want)
+    assert np.array_equal(cf & 0x7FFFFFFF, ci)
+
+
+def test_xcb_flag_walk_is_exact():
+    """Walking each block's flagged entries in order, counting heads to find
+    compressed rows (no row pointers), and adding the block partials in
+    block order reproduces A x exactly (integers): the decoding the
+    column-blocked kernel performs."""
+    A = _mat([3, 0, 7, 1, 12, 0, 5, 0, 0, 1] * 4, seed=6, ncols=40)
+    x = gen.int_vec(A.ncols, 2)
+    rp, cf = oracle.plan_xcb(A, 8, flagged=True)
+    bounds = [(k * A.ncols) // 8 for k in range(9)]
+    vals = [A.val[e] for k in range(8) for i in range(A.n) for e in range(A.rowptr[i], A.rowptr[i + 1])
+            if bounds[k] <= A.colind[e] < bounds[k + 1]]
+    y = np.zeros(A.n)
+    base = 0
+    for k in range(8):
+        rows = [i for i in range(A.n) if rp[k][i + 1] > rp[k][i]]  # the block's compressed rows
+        nk = int(rp[k][A.n])
+        part = np.zeros(len(rows))
+        r = -1
+        for q in range(base, base + nk):
+            if cf[q] < 0:
+                r += 1
+            part[r] += vals[q] * x[cf[q] & 0x7FFFFFFF]
+        assert r == len(rows) - 1
+        for j, i in enumerate(rows):
+            y[i] += part[j]
+        base += nk
+    assert np.array_equal(y, oracle.spmv(A, x)[0])
