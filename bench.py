@@ -13,8 +13,11 @@ divided by the timed wall time of the K steps.
 
 Extra fields on the same JSON line: the FP32-value SpMV rate, the
 time-to-1e-10 of GMRES(30) in FP64 and in mixed precision with FP64
-refinement, the selector's choices (TIME and LEARNED) and timings, the
-roofline of the dominant kernel and the CPU oracle baseline.
+refinement (median of 3), the same pair plus the symmetric SpMV rates on the
+128^3 27-point stencil stored as its lower triangle, the batched SpMV and
+BiCGStab over 512 uneven systems, the selector's choices
+(TIME and LEARNED) and timings, the roofline of the dominant kernel and the
+CPU oracle baseline.
 
 Hardware-counter traffic: before the timed region the script runs a plain
 streaming copy of known size (torch.neg over 256 MiB, read once, written
@@ -46,8 +49,13 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 CAL_BYTES = 256 << 20
 PROFILES = os.path.join(ROOT, "profiles")
-# sources whose change invalidates recorded counter figures of the SpMV kernels
-SPMV_SOURCES = ("internal.h", "segchunk.h", "sym_layout.h", "spmv.hip", "spmv_seg.hip", "spmv_row.hip", "plan.hip")
+# sources whose change invalidates recorded counter figures of an implementation's kernels
+COMMON_SOURCES = ("internal.h", "segchunk.h", "spmv_launch.h", "spmv.hip", "plan.hip")
+VARIANT_SOURCES = {
+    "ROW": ("spmv_row.hip",), "SYM_ATOMIC": ("spmv_row.hip",),
+    "NNZ": ("spmv_seg.hip",), "BSS": ("spmv_seg.hip",), "SYM_S3": ("spmv_seg.hip", "sym_layout.h"),
+    "XCB": ("spmv_xcb.hip",),
+}
 # kernels one SpMV of each implementation launches
 VARIANT_KERNELS = {
     "ROW": ("k_spmv_row",),
@@ -69,9 +77,9 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def spmv_source_hash():
+def spmv_source_hash(variant):
     h = hashlib.sha256()
-    for f in SPMV_SOURCES:
+    for f in COMMON_SOURCES + VARIANT_SOURCES[variant]:
         with open(os.path.join(ROOT, "paper_2405_01599_amd", "csrc", f), "rb") as fh:
             h.update(f.encode() + b"\0" + fh.read())
     return h.hexdigest()
@@ -131,7 +139,7 @@ def pmc_summary(fetch_dir, write_dir, out, variant, n, cmd_fetch, cmd_write):
            "calibration": {"kernel": cal[0][:160], "bytes_read": CAL_BYTES, "bytes_written": CAL_BYTES,
                            "fetch_kib": cf, "write_kib": cw, "fetch_factor": ff, "write_factor": fw},
            "kernels": ker, "traffic_bytes_per_spmv": {"read": rd, "write": wr, "total": rd + wr},
-           "source_sha256": spmv_source_hash()}
+           "source_sha256": spmv_source_hash(variant)}
     with open(out, "w") as fh:
         json.dump(rep, fh, indent=1)
     print(json.dumps(rep["traffic_bytes_per_spmv"]))
@@ -145,7 +153,7 @@ def recorded_traffic(variant, n):
         return None, "no counter summary for this kernel and workload"
     with open(path) as fh:
         rep = json.load(fh)
-    if rep.get("source_sha256") != spmv_source_hash():
+    if rep.get("source_sha256") != spmv_source_hash(variant):
         return None, "SpMV sources changed since the counters were taken"
     return round(rep["traffic_bytes_per_spmv"]["total"]), os.path.relpath(path, ROOT)
 
@@ -163,8 +171,103 @@ def cpu_baseline(A, x, budget_s=10.0):
         if el >= budget_s:
             break
     by = alg_bytes(A.n, A.nnz, 8, 8, 8)
+    host = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            host = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), host)
+    except OSError:
+        pass
     return {"value": round(by * reps / el / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
-            "sample": f"{reps} full FP64 SpMVs of the n=2M power-law matrix ({el:.1f} s, 1 thread)"}
+            "sample": f"{reps} full FP64 SpMVs of the n=2M power-law matrix ({el:.1f} s, 1 thread)",
+            "host_cpu": host, "host_nproc": os.cpu_count()}
+
+
+def gmres_pair(ctx, xab, torch, plan, n, reps=3):
+    """Time-to-1e-10 of GMRES(30) with Jacobi, FP64 and mixed precision
+    (FP32 inner solve, FP64 refinement): b = 1, x0 = 0, median of `reps`."""
+    b = torch.ones(n, dtype=torch.float64, device="cuda")
+    res = {}
+    for mode, name in ((xab.MODE_FP64, "fp64"), (xab.MODE_IR, "ir")):
+        runs = []
+        for _ in range(reps):
+            xs, inf, st = ctx.gmres(plan, b, m=30, tol=1e-10, mode=mode, precond=xab.PRECOND_JACOBI)
+            runs.append(inf)
+        runs.sort(key=lambda r: r["seconds"])
+        med = runs[len(runs) // 2]
+        res[name] = {"s": round(med["seconds"], 5), "iters": med["iters"], "restarts": med["restarts"],
+                     "refinements": med["refinements"], "relres": med["true_relres"], "status": med["status"]}
+    res["ir_speedup"] = round(res["fp64"]["s"] / res["ir"]["s"], 3)
+    return res
+
+
+def sym_stencil_leg(ctx, xab, torch, gen, gmres=True):
+    """Symmetric SpMV from lower storage on the 128^3 27-point stencil:
+    TIME-selected implementation, FP64 and FP32 values (FP64 accumulation),
+    then GMRES(30) FP64 vs mixed precision on it."""
+    L = gen.stencil27(128, lower=True)
+    M = ctx.matrix_from_csr(L, with_f32=True)
+    plan, info = ctx.select(M, xab.TIME)
+    x = torch.from_numpy(gen.uniform_vec(L.n, 13)).cuda()
+    y = torch.empty(L.n, dtype=torch.float64, device="cuda")
+    ms64 = ctx.time_spmv(plan, x, y, warmup=5, reps=100)
+    x32, y32 = x.float(), y.float()
+    ms32 = ctx.time_spmv(plan, x32, y32, acc=xab.F64, warmup=5, reps=100)
+    by64, by32 = alg_bytes(L.n, L.nnz, 8, 8, 8), alg_bytes(L.n, L.nnz, 4, 4, 4)
+    out = {"workload": f"27-point stencil 128^3, lower triangle stored: n={L.n} nnz_L={L.nnz}",
+           "selected": plan.describe(), "chosen_class": int(info.chosen),
+           "us_per_class": {k: round(float(info.time_ms[k]) * 1e3, 2) for k in range(xab.NCLASSES) if info.valid[k]},
+           "fp64": {"us": round(ms64 * 1e3, 2), "gbs": round(by64 / (ms64 * 1e-3) / 1e9, 1),
+                    "frac": round(by64 / (ms64 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                    "gflops": round(2 * (2 * L.nnz - L.n) / (ms64 * 1e-3) / 1e9, 1)},
+           "fp32_values": {"us": round(ms32 * 1e3, 2), "gbs": round(by32 / (ms32 * 1e-3) / 1e9, 1),
+                           "frac": round(by32 / (ms32 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}}
+    if gmres:
+        out["gmres"] = gmres_pair(ctx, xab, torch, plan, L.n)
+    plan.close()
+    M.close()
+    return out
+
+
+def batch_leg(ctx, xab, torch, gen):
+    """512 uneven systems (banded and random rows, n log-uniform in
+    [1000, 65536]) as one block-diagonal CSR: the persistent batched SpMV in
+    FP64 and FP32 (HIP events on the context stream, 50 launches), and
+    batched BiCGStab with Jacobi to 1e-10 (FP64) / 1e-5 (FP32), graph-captured
+    iterations vs eager launches."""
+    B = gen.batch()
+    out = {"workload": f"512 systems, n={B.n} nnz={B.nnz}, block-diagonal CSR"}
+    for dt, tol, vb in (("f64", 1e-10, 8), ("f32", 1e-5, 4)):
+        bt = ctx.batch(B, dtype=dt)
+        x = torch.ones(B.n, dtype=bt.dtype, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(5):
+            bt.spmv(x, y)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(50):
+            bt.spmv(x, y)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 50
+        by = alg_bytes(B.n, B.nnz, vb, vb, vb)
+        leg = {"spmv_us": round(ms * 1e3, 2), "spmv_gbs": round(by / (ms * 1e-3) / 1e9, 1),
+               "spmv_frac": round(by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        b = torch.ones(B.n, dtype=bt.dtype, device="cuda")
+        for graph in (True, False):
+            ctx.bicgstab(bt, b, tol=tol, graph=graph)  # warm (graph instantiation, code paths)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            xs, per, agg, st = ctx.bicgstab(bt, b, tol=tol, graph=graph)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            leg["bicgstab_graph" if graph else "bicgstab_eager"] = {
+                "s": round(wall, 5), "status": st, "max_iters": max(p["iters"] for p in per),
+                "converged": sum(1 for p in per if p["status"] == 0),
+                "max_relres": max(p["true_relres"] for p in per)}
+        out[dt] = leg
+        bt.close()
+        del x, y, b
+    return out
 
 
 def main():
@@ -174,6 +277,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-gmres", action="store_true")
+    ap.add_argument("--no-c3", action="store_true", help="skip the symmetric 27-point stencil leg")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 512-system batch leg")
     ap.add_argument("--n", type=int, default=2_000_000)
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     ap.add_argument("--variant", default="XCB")
@@ -255,19 +360,17 @@ def main():
 
     gm = None
     if not args.no_gmres:
-        log("GMRES(30) FP64 vs mixed precision")
-        b = torch.ones(A.n, dtype=torch.float64, device="cuda")
-        res = {}
-        for mode, name in ((xab.MODE_FP64, "fp64"), (xab.MODE_IR, "ir")):
-            best = None
-            for _ in range(3):
-                xs, inf, st = ctx.gmres(plan, b, m=30, tol=1e-10, mode=mode, precond=xab.PRECOND_JACOBI)
-                if best is None or inf["seconds"] < best["seconds"]:
-                    best = inf
-            res[name] = {"s": round(best["seconds"], 5), "iters": best["iters"], "restarts": best["restarts"],
-                         "refinements": best["refinements"], "relres": best["true_relres"], "status": best["status"]}
-        res["ir_speedup"] = round(res["fp64"]["s"] / res["ir"]["s"], 3)
-        gm = res
+        log("GMRES(30) FP64 vs mixed precision (power-law)")
+        gm = gmres_pair(ctx, xab, torch, plan, A.n)
+
+    c3 = None
+    if not args.no_c3:
+        log("symmetric 27-point stencil 128^3 (lower storage)")
+        c3 = sym_stencil_leg(ctx, xab, torch, gen, gmres=not args.no_gmres)
+    c4 = None
+    if not args.no_batch:
+        log("batch of 512 systems: batched SpMV and BiCGStab")
+        c4 = batch_leg(ctx, xab, torch, gen)
 
     cpu = None
     if not args.no_cpu:
@@ -296,6 +399,8 @@ def main():
         "selector": {"chosen_class": chosen, "us_per_class": times, "select_ms": round(float(info.select_ms), 2),
                      "select_wall_ms": round(time_wall_ms, 2), "learned": learned},
         "gmres": gm,
+        "sym27": c3,
+        "batch512": c4,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -16,65 +16,53 @@ namespace {
 
 using xab::Seg;
 constexpr int kNT = 256;
-constexpr int kChunkJ = 8;
-constexpr int kTileNnz = 2048;
+constexpr int kBatchJ = 4;  // entries per lane of the batched SpMV tiles
 
-template <class YT, class AT>
-struct StoreSink {
-    YT *y;
-    __device__ void row_done(int32_t r, AT v) { y[r] = (YT)v; }
-    __device__ void empty_row(int32_t r) { y[r] = YT(0); }
-    template <class VT>
-    __device__ void entry(int32_t, int32_t, VT) {}
-};
 
-// Persistent nnz-split SpMV: the grid walks the tiles [b[t], b[t+1]) of the
-// global matrix; a tile whose first and last systems are inactive (and
-// which spans at most two systems) is skipped.
+// Batched SpMV over the concatenation, in segmented-scan tiles of
+// kNT * kBatchJ entries (the BSS layout).  A tile whose rows span at most two
+// systems, both converged, is skipped: it only marks that it leaves no
+// partial row (any row it shares with a neighbouring tile belongs to one of
+// those converged systems, whose products are never read).
 template <class T>
 __global__ __launch_bounds__(kNT) void k_batch_spmv(const int32_t *__restrict__ rowptr,
                                                     const int32_t *__restrict__ colind, const T *__restrict__ val,
-                                                    const T *__restrict__ x, T *__restrict__ y,
-                                                    const int32_t *__restrict__ b, int64_t P,
-                                                    const int32_t *__restrict__ sys_of_row,
+                                                    const T *__restrict__ x, T *__restrict__ y, int64_t nnz, int64_t P,
+                                                    const int32_t *__restrict__ row_lo,
+                                                    const int32_t *__restrict__ tile_row,
+                                                    const int32_t *__restrict__ carry_row,
+                                                    double *__restrict__ carry_val, double *__restrict__ tail_val,
+                                                    int32_t *__restrict__ tail_row,
+                                                    const int32_t *__restrict__ sys_of_row, int32_t n,
                                                     const int *__restrict__ active) {
-    constexpr int CH = kNT * kChunkJ;
-    __shared__ int32_t head_row[CH];
+    __shared__ int32_t head_row[kNT * kBatchJ];
     __shared__ Seg<double> wave_tot[kNT / xab::kWave];
-    StoreSink<T, double> sink{y};
-    for (int64_t t = blockIdx.x; t < P; t += gridDim.x) {
-        const int32_t r0 = b[t], r1 = b[t + 1];
-        if (r0 >= r1) continue;
-        if (active) {
-            int32_t s0 = sys_of_row[r0], s1 = sys_of_row[r1 - 1];
-            if (s1 - s0 <= 1 && !active[s0] && !active[s1]) continue;
+    const int64_t t = xab::xcd_remap(blockIdx.x, P);
+    if (active) {
+        const int32_t ra = tile_row[t], rb = tile_row[t + 1] < n ? tile_row[t + 1] : n - 1;
+        const int32_t s0 = sys_of_row[ra], s1 = sys_of_row[rb];
+        if (s1 - s0 <= 1 && !active[s0] && !active[s1]) {
+            if (threadIdx.x == 0) tail_row[t] = -1;
+            return;
         }
-        const int64_t s = rowptr[r0], e = rowptr[r1];
-        Seg<double> seed{0, 0.0, -1};
-        int32_t rlo = r0;
-        int64_t A = s - (s % CH);
-        xab::Run<kChunkJ, T, T> R;
-        xab::run_load<kNT, kChunkJ>(R, A, s, e < A + CH ? e : A + CH, colind, val);
-        for (;;) {
-            const int64_t Aend = A + CH;
-            const bool last = Aend >= e;
-            xab::clear_heads<kNT, kChunkJ>(head_row);
-            const xab::RowProbe probe = xab::first_row<kNT>(rowptr, rlo, r1);
-            xab::run_gather(R, x);
-            __syncthreads();
-            const int32_t rhi = xab::mark_rows<kNT>(rowptr, probe, rlo, r1, A, Aend, last, head_row, sink);
-            xab::Run<kChunkJ, T, T> Rn;
-            if (!last) xab::run_load<kNT, kChunkJ>(Rn, Aend, Aend, e < Aend + CH ? e : Aend + CH, colind, val);
-            xab::ChunkResult<double> res =
-                xab::seg_chunk<kNT, kChunkJ, T, T, double>(R, head_row, seed, wave_tot, sink);
-            seed = res.state;
-            rlo = rhi;
-            if (last) break;
-            A = Aend;
-            R = Rn;
-        }
-        if (threadIdx.x == 0 && seed.f) y[seed.r] = (T)seed.v;
     }
+    xab::bss_tile<kNT, T, T, T, double, kBatchJ>(t, rowptr, colind, val, x, y, nnz, row_lo, carry_row, carry_val,
+                                                 tail_val, tail_row, head_row, wave_tot, nullptr);
+}
+
+// rows cut by a tile end: start partial plus the following tiles' carries,
+// in ascending tile order
+template <class T>
+__global__ void k_batch_fixup(T *__restrict__ y, int64_t P, const int32_t *__restrict__ carry_row,
+                              const double *__restrict__ carry_val, const double *__restrict__ tail_val,
+                              const int32_t *__restrict__ tail_row) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= P) return;
+    const int32_t r = tail_row[t];
+    if (r < 0) return;
+    double acc = tail_val[t];
+    for (int64_t u = t + 1; u < P && carry_row[u] == r; ++u) acc += carry_val[u];
+    y[r] = (T)acc;
 }
 
 __device__ __forceinline__ double bsum(double v, double *sh) {
@@ -344,38 +332,22 @@ __global__ void k_zero_int(int *p) {
     if (threadIdx.x == 0) *p = 0;
 }
 
-__global__ void k_split_nnz_b(const int32_t *rowptr, int64_t n, int64_t nnz, int64_t P, int32_t *b) {
-    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p > P) return;
-    if (p == 0) { b[0] = 0; return; }
-    if (p == P) { b[P] = (int32_t)n; return; }
-    int64_t target = (p * nnz) / P;
-    int64_t lo = 0, hi = n + 1;
-    while (lo < hi) {
-        int64_t mid = (lo + hi) / 2;
-        if (rowptr[mid] >= target) hi = mid;
-        else lo = mid + 1;
-    }
-    b[p] = (int32_t)lo;
-}
-
 unsigned grid_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
-int persistent_grid() {
-    static int g = 0;
-    if (!g) {
-        int dev = 0, cu = 256;
-        (void)hipGetDevice(&dev);
-        if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cu = 256;
-        g = cu * 8;
-    }
-    return g;
+
+template <class T>
+void launch_batch_spmv(const xab_batch *B, const T *x, T *y, const int *active, hipStream_t st) {
+    hipLaunchKernelGGL((k_batch_spmv<T>), dim3((unsigned)B->P), dim3(kNT), 0, st, B->rowptr, B->colind,
+                       (const T *)B->val, x, y, B->nnz, B->P, B->row_lo, B->tile_row, B->carry_row, B->carry_val,
+                       B->tail_val, B->tail_row, B->d_sys_of_row, (int32_t)B->n, active);
+    hipLaunchKernelGGL((k_batch_fixup<T>), dim3(grid_for(B->P, 256)), dim3(256), 0, st, y, B->P, B->carry_row,
+                       B->carry_val, B->tail_val, B->tail_row);
 }
 
 template <class T>
 int batch_spmv_t(xab_ctx *ctx, const xab_batch *B, const T *x, T *y, const int *active, hipStream_t st) {
-    hipLaunchKernelGGL((k_batch_spmv<T>), dim3((unsigned)std::min<int64_t>(B->P, persistent_grid())), dim3(kNT), 0, st,
-                       B->rowptr, B->colind, (const T *)B->val, x, y, B->b, B->P, B->d_sys_of_row, active);
+    if (B->n == 0) return XAB_OK;
+    launch_batch_spmv<T>(B, x, y, active, st);
     XAB_LAUNCH_CHECK(ctx, "k_batch_spmv");
     return XAB_OK;
 }
@@ -436,12 +408,10 @@ int bicgstab_t(xab_ctx *ctx, const xab_batch *B, const T *bvec, T *x, const xab_
     auto enqueue_iter = [&](hipStream_t q) {
         hipLaunchKernelGGL((k_bi_p<T>), dim3(ns), dim3(kNT), 0, q, B->d_row_off, r, rh, p, v, ph, dd, stt, active, rho,
                            n_active);
-        hipLaunchKernelGGL((k_batch_spmv<T>), dim3((unsigned)std::min<int64_t>(B->P, persistent_grid())), dim3(kNT), 0, q,
-                           B->rowptr, B->colind, (const T *)B->val, ph, v, B->b, B->P, B->d_sys_of_row, active);
+        launch_batch_spmv<T>(B, ph, v, active, q);
         hipLaunchKernelGGL((k_bi_s<T>), dim3(ns), dim3(kNT), 0, q, B->d_row_off, r, rh, v, s, shv, ph, x, dd, stt, active,
                            rho, tol, n_active);
-        hipLaunchKernelGGL((k_batch_spmv<T>), dim3((unsigned)std::min<int64_t>(B->P, persistent_grid())), dim3(kNT), 0, q,
-                           B->rowptr, B->colind, (const T *)B->val, shv, t, B->b, B->P, B->d_sys_of_row, active);
+        launch_batch_spmv<T>(B, shv, t, active, q);
         hipLaunchKernelGGL((k_bi_x<T>), dim3(ns), dim3(kNT), 0, q, B->d_row_off, s, t, ph, shv, x, r, stt, active, rho, tol,
                            maxiter, n_active);
     };
@@ -556,18 +526,25 @@ int xab_batch_csr(xab_ctx *ctx, int32_t nsys, const int64_t *h_row_off, const in
     B->val = d_val;
     B->vt = vt;
     xab_matrix_destroy(A);
-    B->P = std::max<int64_t>(1, (nnz + kTileNnz - 1) / kTileNnz);
-    B->b = (int32_t *)xab_dalloc(ctx, sizeof(int32_t) * (B->P + 1));
+    const int64_t T = (int64_t)kNT * kBatchJ;
+    B->P = std::max<int64_t>(1, (nnz + T - 1) / T);
+    B->row_lo = (int32_t *)xab_dalloc(ctx, sizeof(int32_t) * (B->P + 1));
+    B->tile_row = (int32_t *)xab_dalloc(ctx, sizeof(int32_t) * (B->P + 1));
+    B->carry_row = (int32_t *)xab_dalloc(ctx, sizeof(int32_t) * B->P);
+    B->tail_row = (int32_t *)xab_dalloc(ctx, sizeof(int32_t) * B->P);
+    B->carry_val = (double *)xab_dalloc(ctx, sizeof(double) * B->P);
+    B->tail_val = (double *)xab_dalloc(ctx, sizeof(double) * B->P);
     B->d_sys_of_row = (int32_t *)xab_dalloc(ctx, sizeof(int32_t) * (n > 0 ? n : 1));
     B->d_row_off = (int64_t *)xab_dalloc(ctx, sizeof(int64_t) * (nsys + 1));
-    if (!B->b || !B->d_sys_of_row || !B->d_row_off) {
+    if (!B->row_lo || !B->tile_row || !B->carry_row || !B->tail_row || !B->carry_val || !B->tail_val ||
+        !B->d_sys_of_row || !B->d_row_off) {
         xab_batch_destroy(B);
         return xab_fail(ctx, XAB_E_NOMEM, "batch plan");
     }
     hipStream_t st = ctx->stream;
     hipError_t e = hipMemcpyAsync(B->d_row_off, h_row_off, sizeof(int64_t) * (nsys + 1), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_split_nnz_b, dim3(grid_for(B->P + 1, 256)), dim3(256), 0, st, d_rowptr, n, nnz, B->P, B->b);
+        xab_launch_split_bss(st, d_rowptr, (int32_t)n, T, B->P, B->row_lo, B->tile_row, B->carry_row);
         hipLaunchKernelGGL(k_sys_of_row, dim3(nsys), dim3(256), 0, st, B->d_row_off, nsys, B->d_sys_of_row);
         if (!(flags & XAB_TRUST_INPUT) && n > 0) {
             hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, st, ctx->d_flag);
@@ -595,7 +572,12 @@ int xab_batch_csr(xab_ctx *ctx, int32_t nsys, const int64_t *h_row_off, const in
 void xab_batch_destroy(xab_batch *B) {
     if (!B) return;
     (void)hipStreamSynchronize(B->ctx->stream);
-    xab_dfree(B->ctx, B->b);
+    xab_dfree(B->ctx, B->row_lo);
+    xab_dfree(B->ctx, B->tile_row);
+    xab_dfree(B->ctx, B->carry_row);
+    xab_dfree(B->ctx, B->tail_row);
+    xab_dfree(B->ctx, B->carry_val);
+    xab_dfree(B->ctx, B->tail_val);
     xab_dfree(B->ctx, B->d_sys_of_row);
     xab_dfree(B->ctx, B->d_row_off);
     delete B;

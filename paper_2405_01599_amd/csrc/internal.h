@@ -70,6 +70,8 @@ struct xab_plan {
     int32_t s3_own_cap = 0;    // most rows of a tile
     int32_t s3_ext_cap = 0;    // most touched blocks of a tile times col_block
     int32_t s3_lut_cap = 0;    // widest span of touched block ids of a tile
+    int32_t *s3_ci = nullptr;  // copy of colind, bit 31 on the first entry of every non-empty row
+    uint8_t *s3_dense = nullptr; // per tile: 1 when none of its rows is empty (the flagged walk applies)
     // XCB: column-blocked copy of the matrix, one CSR per column block
     static constexpr int kXcb = 8;
     int32_t *xcb_rowptr = nullptr;      // kXcb * (n + 1), each relative to its block's first entry
@@ -97,9 +99,10 @@ struct xab_batch {
     const int32_t *rowptr = nullptr, *colind = nullptr;
     const void *val = nullptr;
     xab_dtype vt = XAB_F64;
-    // persistent SpMV split: P parts of whole rows, balanced by nnz
+    // segmented-scan tiles of the concatenated matrix (kBatchJ entries per lane)
     int64_t P = 0;
-    int32_t *b = nullptr;
+    int32_t *row_lo = nullptr, *tile_row = nullptr, *carry_row = nullptr, *tail_row = nullptr;
+    double *carry_val = nullptr, *tail_val = nullptr;
     int32_t *d_sys_of_row = nullptr; // system index of every row
     int64_t *d_row_off = nullptr;    // [nsys+1]
 };
@@ -126,6 +129,10 @@ void *xab_scratch(xab_ctx *ctx, size_t bytes);
 
 // plan builders (plan.hip)
 int xab_build_plan(xab_ctx *ctx, const xab_matrix *A, xab_variant v, const xab_params *p, xab_plan **out);
+// segmented-scan tile descriptors (row_lo, tile_row [P+1], carry_row [P]) of a
+// CSR with T entries per tile, queued on `st`
+void xab_launch_split_bss(hipStream_t st, const int32_t *rowptr, int32_t n, int64_t T, int64_t P, int32_t *row_lo,
+                          int32_t *tile_row, int32_t *carry_row);
 
 // SpMV dispatch (spmv.hip)
 int xab_spmv_dispatch(xab_ctx *ctx, const xab_plan *plan, const void *x, xab_dtype xt, void *y, xab_dtype yt,

@@ -308,6 +308,23 @@ __global__ void k_xcb_flag_heads(const int32_t *crp, int32_t m, int32_t *ci) {
     ci[e] = (int32_t)((uint32_t)ci[e] | 0x80000000u);
 }
 
+// bit 31 on the first entry of every non-empty row of a CSR (in place on a copy)
+__global__ void k_flag_row_heads(const int32_t *rowptr, int32_t n, int32_t *ci) {
+    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const int32_t e0 = rowptr[r];
+    if (rowptr[r + 1] > e0) ci[e0] = (int32_t)((uint32_t)ci[e0] | 0x80000000u);
+}
+
+// dense[p] = 1 when every row of tile p (rows [b[p], b[p+1])) has an entry
+__global__ void k_tile_dense(const int32_t *rowptr, const int32_t *b, int64_t P, uint8_t *dense) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    uint8_t d = 1;
+    for (int32_t r = b[p]; r < b[p + 1] && d; ++r) d = rowptr[r + 1] > rowptr[r];
+    dense[p] = d;
+}
+
 // cnt[k * G + g] = rows of group g (256 rows) with entries in block k
 __global__ void k_xcb_group_counts(const uint8_t *mask, int32_t n, int64_t G, int32_t *cnt) {
     __shared__ int32_t c[xab_plan::kXcb];
@@ -364,6 +381,8 @@ static void free_plan_arrays(xab_ctx *ctx, xab_plan *pl) {
     xab_dfree(ctx, pl->partial);
     xab_dfree(ctx, pl->xcb_rowptr);
     xab_dfree(ctx, pl->xcb_gbase);
+    xab_dfree(ctx, pl->s3_ci);
+    xab_dfree(ctx, pl->s3_dense);
     xab_dfree(ctx, pl->xcb_mask);
     xab_dfree(ctx, pl->xcb_colind);
     xab_dfree(ctx, pl->xcb_val64);
@@ -398,6 +417,12 @@ static void free_plan_arrays(xab_ctx *ctx, xab_plan *pl) {
     } while (0)
 
 static int hip_ok(xab_ctx *ctx, hipError_t e, const char *w) { return xab_hip_check(ctx, e, w); }
+
+void xab_launch_split_bss(hipStream_t st, const int32_t *rowptr, int32_t n, int64_t T, int64_t P, int32_t *row_lo,
+                          int32_t *tile_row, int32_t *carry_row) {
+    hipLaunchKernelGGL(k_split_bss, dim3(grid_for(P + 1, 256)), dim3(256), 0, st, rowptr, n, T, P, row_lo, tile_row,
+                       carry_row);
+}
 
 int xab_build_plan(xab_ctx *ctx, const xab_matrix *A, xab_variant v, const xab_params *pp, xab_plan **out) {
     if (!ctx || !A || !pp || !out) return XAB_E_NULL;
@@ -745,6 +770,18 @@ int xab_build_plan(xab_ctx *ctx, const xab_matrix *A, xab_variant v, const xab_p
             delete pl;
             return xab_fail(ctx, XAB_E_NOMEM, "partial buffer");
         }
+        // flagged copy of the columns and the per-tile "no empty row" marks
+        ALLOC(pl->s3_ci, int32_t, std::max<int64_t>(1, nnz));
+        ALLOC(pl->s3_dense, uint8_t, std::max<int64_t>(1, P));
+        if (nnz > 0) {
+            e = hipMemcpyAsync(pl->s3_ci, A->colind, sizeof(int32_t) * (size_t)nnz, hipMemcpyDeviceToDevice, st);
+            CHECKED(hip_ok(ctx, e, "column copy"));
+            hipLaunchKernelGGL(k_flag_row_heads, dim3(grid_for(n, 256)), dim3(256), 0, st, A->rowptr, n, pl->s3_ci);
+        }
+        if (P > 0)
+            hipLaunchKernelGGL(k_tile_dense, dim3(grid_for(P, 256)), dim3(256), 0, st, A->rowptr, pl->b, (int64_t)P,
+                               pl->s3_dense);
+        CHECKED(hip_ok(ctx, hipGetLastError(), "flagged columns"));
     }
     hipError_t e = hipStreamSynchronize(st);
     if (e != hipSuccess) {

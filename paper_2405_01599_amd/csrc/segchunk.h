@@ -198,4 +198,156 @@ __device__ __forceinline__ ChunkResult<AT> seg_chunk(const Run<J, VT, XT> &R, co
     return res;
 }
 
+// ------------------------------------------------------------------ flagged entry streams
+// Plan-owned copies of the column indices can carry the head flags in bit
+// 31 (the first entry of every non-empty row).  Kernels over such a stream
+// count heads to find rows instead of reading row pointers.
+
+// scan element over flagged entries: heads seen, sum since the last head
+template <class AT>
+struct CSeg {
+    int c;
+    AT v;
+};
+template <class AT>
+__device__ __forceinline__ CSeg<AT> cseg_combine(const CSeg<AT> &a, const CSeg<AT> &b) {
+    return CSeg<AT>{a.c + b.c, b.c ? b.v : a.v + b.v};
+}
+
+// a live flagged column is never -1: flagged values are INT_MIN + col with
+// col < 2^31 - 1, so -1 can mark the dead slots outside the live range
+constexpr int32_t kDeadCol = -1;
+
+__device__ __forceinline__ int is_head(int32_t c) { return (c < 0) & (c != kDeadCol); }
+__device__ __forceinline__ int32_t col_of(int32_t c) { return c == kDeadCol ? kDeadCol : (c & 0x7fffffff); }
+
+
+
+template <int J, class VT, class XT>
+__device__ __forceinline__ void run_gather_flagged(Run<J, VT, XT> &R, const XT *__restrict__ x) {
+#pragma unroll
+    for (int k = 0; k < J; ++k) R.xv[k] = R.col[k] != kDeadCol ? x[R.col[k] & 0x7fffffff] : XT(0);
+}
+
+// One chunk of a flagged stream whose tile starts at a row start.  `seed`
+// holds the heads seen in the tile before the chunk and the open row's
+// partial.  Rows are numbered 0, 1, ... from the tile's first head: at
+// every head after the first, the lane hands the finished row to
+// sink.row_done(row, sum), and every entry goes to sink.entry(row, col,
+// val) (dead slots with col = kDeadCol).  Returns the block-uniform state
+// after the chunk.  Contains two barriers; the second makes wave_tot free
+// for the next chunk.
+template <int NT, int J, class VT, class XT, class AT, class Sink>
+__device__ __forceinline__ CSeg<AT> flag_chunk(const Run<J, VT, XT> &R, CSeg<AT> seed, CSeg<AT> *wave_tot,
+                                               Sink &sink) {
+    constexpr int NW = NT / kWave;
+    const int tid = threadIdx.x, lane = tid % kWave, wid = tid / kWave;
+    AT p[J];
+    int hd[J];
+#pragma unroll
+    for (int k = 0; k < J; ++k) {
+        hd[k] = is_head(R.col[k]);
+        p[k] = (AT)R.v[k] * (AT)R.xv[k];
+    }
+    CSeg<AT> s{0, AT(0)};
+#pragma unroll
+    for (int k = 0; k < J; ++k) {
+        s.v = hd[k] ? p[k] : s.v + p[k];
+        s.c += hd[k];
+    }
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        CSeg<AT> u{shfl_up(s.c, d), shfl_up(s.v, d)};
+        if (lane >= d) s = cseg_combine(u, s);
+    }
+    if (lane == kWave - 1) wave_tot[wid] = s;
+    __syncthreads();
+    CSeg<AT> pre = seed, total = seed;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        const CSeg<AT> t = wave_tot[w];
+        if (w < wid) pre = cseg_combine(pre, t);
+        total = cseg_combine(total, t);
+    }
+    __syncthreads();
+    const CSeg<AT> ex{shfl_up(s.c, 1), shfl_up(s.v, 1)};
+    const CSeg<AT> in = lane == 0 ? pre : cseg_combine(pre, ex);
+    AT acc = in.v;
+    int cnt = in.c;
+#pragma unroll
+    for (int k = 0; k < J; ++k) {
+        if (hd[k]) {
+            if (cnt > 0) sink.row_done(cnt - 1, acc);
+            acc = p[k];
+            ++cnt;
+        } else {
+            acc += p[k];
+        }
+        sink.entry(cnt - 1, col_of(R.col[k]), R.v[k]);
+    }
+    return total;
+}
+
+
+// ------------------------------------------------------------------ BSS tile
+// Output sink of the row-sum kernels: row r of the CSR goes to y[ridx[r]]
+// (or y[r] when ridx is null).
+template <class YT, class AT>
+struct StoreSink {
+    YT *y;
+    const int32_t *ridx;  // row r of the CSR is output row ridx[r] (null: r itself)
+    __device__ int64_t out(int32_t r) const { return ridx ? ridx[r] : r; }
+    __device__ void row_done(int32_t r, AT v) { y[out(r)] = (YT)v; }
+    __device__ void empty_row(int32_t r) { y[out(r)] = YT(0); }
+    template <class VT>
+    __device__ void entry(int32_t, int32_t, VT) {}
+};
+
+// One branchless segmented-scan tile (the BSS layout).
+// Tile t = entries [tT, min((t+1)T, nnz)), T = 256 * J.  Rows that start
+// and end in the tile are written directly.  The last row started in the
+// tile, if it runs past the tile, leaves its partial in tail_val[t]; the
+// leading partial of a row begun in an earlier tile goes to carry_val[t].
+// The fix-up kernel then writes each such row once: its start partial plus
+// the carries of the following tiles in ascending tile order.
+template <int NT, class VT, class XT, class YT, class AT, int J>
+__device__ __forceinline__ void bss_tile(int64_t t, const int32_t *__restrict__ rowptr,
+                                         const int32_t *__restrict__ colind, const VT *__restrict__ val,
+                                         const XT *__restrict__ x, YT *__restrict__ y, int64_t nnz,
+                                         const int32_t *__restrict__ row_lo, const int32_t *__restrict__ carry_row,
+                                         AT *__restrict__ carry_val, AT *__restrict__ tail_val,
+                                         int32_t *__restrict__ tail_row, int32_t *head_row, Seg<AT> *wave_tot,
+                                         const int32_t *__restrict__ ridx) {
+    constexpr int T = NT * J;
+    const int64_t A = t * T;
+    const int64_t c1 = (A + T < nnz) ? A + T : nnz;
+    StoreSink<YT, AT> sink{y, ridx};
+    // loads first; the row-pointer probe and the gathers overlap them
+    Run<J, VT, XT> R;
+    run_load<NT, J>(R, A, A, c1, colind, val);
+    clear_heads<NT, J>(head_row);
+    const int32_t rlo = row_lo[t], rend = row_lo[t + 1];
+    const RowProbe probe = first_row<NT>(rowptr, rlo, rend);
+    run_gather(R, x);
+    __syncthreads();
+    mark_rows<NT>(rowptr, probe, rlo, rend, A, A + T, true, head_row, sink);
+    Seg<AT> seed{0, AT(0), -1};
+    ChunkResult<AT> res = seg_chunk<NT, J, VT, XT, AT>(R, head_row, seed, wave_tot, sink);
+    const int32_t cr = carry_row[t];
+    if (res.has_lead && cr >= 0) carry_val[t] = res.lead;
+    if (threadIdx.x == 0) {
+        int32_t tr = -1;
+        if (!res.state.f) {
+            // no row starts in this tile: all of it belongs to the carried row
+            if (cr >= 0) carry_val[t] = res.state.v;
+        } else if (rowptr[res.state.r + 1] <= c1) {
+            y[sink.out(res.state.r)] = (YT)res.state.v;
+        } else {
+            tr = res.state.r;
+            tail_val[t] = res.state.v;
+        }
+        tail_row[t] = tr;
+    }
+}
+
 }  // namespace xab

@@ -10,7 +10,8 @@ constexpr int kExtCap = 6144;          // LDS slots for column blocks below the 
 constexpr int kLutMax = 2048;          // span of block ids one tile may touch
 constexpr int kLutWords = kLutMax / 32;
 constexpr int kLdsCap = 65536;         // LDS bytes one symmetric tile may use
-// bytes of the fixed part (head flags of a 1024-entry chunk + wave totals)
-constexpr int kFixedBytes = 256 * 4 * 4 + 4 * 24;
+constexpr int kChunkJ = 4;             // entries per lane per chunk
+// bytes of the fixed part (head flags of a 256 * kChunkJ chunk + wave totals)
+constexpr int kFixedBytes = 256 * kChunkJ * 4 + 4 * 24;
 }  // namespace sym
 }  // namespace xab

@@ -201,8 +201,21 @@ def test_general_fp32(ctx, name, k, combo):
 
 
 # ----------------------------------------------------------------- symmetric
+def _drop_rows(L, rows):
+    """L with every entry of `rows` removed (empty rows inside some tiles)."""
+    keep = np.ones(L.n, dtype=bool)
+    keep[rows] = False
+    lens = np.diff(L.rowptr) * keep
+    rp = np.zeros(L.n + 1, dtype=np.int32)
+    rp[1:] = np.cumsum(lens)
+    m = np.repeat(keep, np.diff(L.rowptr))
+    return gen.CSR(L.n, L.ncols, rp, L.colind[m].copy(), L.val[m].copy(), sym_lower=True, name="holes")
+
+
 def sym_suite():
+    B = gen.banded(20_000, 30, 9, lower=True)
     return {
+        "banded_holes": _drop_rows(B, np.r_[0:5, 7000:7100, 13001:20000:997, 19999]),
         "lap2d_lower": gen.laplacian2d(64, lower=True),
         "st27_16": gen.stencil27(16, lower=True),
         "st27_24": gen.stencil27(24, lower=True),
