@@ -194,18 +194,59 @@ __device__ __forceinline__ Seg<AT> seg_combine(const Seg<AT> &a, const Seg<AT> &
     return o;
 }
 
+// Cross-lane moves with the data-parallel primitives (DPP) of the GFX9 ISA:
+// a VALU move that reads another lane of the wave, no LDS round trip.
+// Lanes whose source is disabled (outside the 16-lane row for row_shr, or
+// in rows left out of ROW_MASK for the row broadcasts) read 0: the all-zero
+// state is the identity of every scan combine that uses these moves.
+constexpr int kDppRowShr1 = 0x111, kDppRowShr2 = 0x112, kDppRowShr4 = 0x114, kDppRowShr8 = 0x118;
+constexpr int kDppRowBcast15 = 0x142, kDppRowBcast31 = 0x143;
+
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ int dpp_move(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, ROW_MASK, 0xf, false);
+}
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_move(float v) {
+    return __builtin_bit_cast(float, dpp_move<CTRL, ROW_MASK>(__builtin_bit_cast(int, v)));
+}
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_move(double v) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)dpp_move<CTRL, ROW_MASK>((int)(unsigned)(b & 0xffffffffull));
+    const unsigned hi = (unsigned)dpp_move<CTRL, ROW_MASK>((int)(unsigned)(b >> 32));
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// Inclusive scan across the 64 lanes of a wave for an associative combine
+// whose identity is the all-zero state: Kogge-Stone inside each 16-lane
+// row (shifts 1, 2, 4, 8), then row 0's total into row 1 and row 2's into
+// row 3 (broadcast of lane 15), then the first half's total into rows 2
+// and 3 (broadcast of lane 31).  Step(u, s) must return combine(u, s) with
+// u the DPP-moved copy of s.
+template <class S, class Step>
+__device__ __forceinline__ S wave_scan_dpp(S s, Step step) {
+    s = step.template apply<kDppRowShr1, 0xf>(s);
+    s = step.template apply<kDppRowShr2, 0xf>(s);
+    s = step.template apply<kDppRowShr4, 0xf>(s);
+    s = step.template apply<kDppRowShr8, 0xf>(s);
+    s = step.template apply<kDppRowBcast15, 0xa>(s);
+    s = step.template apply<kDppRowBcast31, 0xc>(s);
+    return s;
+}
+
+struct SegStep {
+    template <int CTRL, int RM, class AT>
+    __device__ __forceinline__ Seg<AT> apply(const Seg<AT> &s) const {
+        const Seg<AT> u{dpp_move<CTRL, RM>(s.f), dpp_move<CTRL, RM>(s.v), dpp_move<CTRL, RM>(s.r)};
+        return seg_combine(u, s);
+    }
+};
+
 // Inclusive segmented scan across the 64 lanes of a wave.
 template <class AT>
-__device__ __forceinline__ Seg<AT> wave_seg_scan(Seg<AT> s, int lane) {
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        Seg<AT> u;
-        u.f = shfl_up(s.f, d);
-        u.v = shfl_up(s.v, d);
-        u.r = shfl_up(s.r, d);
-        if (lane >= d) s = seg_combine(u, s);
-    }
-    return s;
+__device__ __forceinline__ Seg<AT> wave_seg_scan(Seg<AT> s, int) {
+    return wave_scan_dpp(s, SegStep{});
 }
 
 template <class T>

@@ -214,6 +214,14 @@ __device__ __forceinline__ CSeg<AT> cseg_combine(const CSeg<AT> &a, const CSeg<A
     return CSeg<AT>{a.c + b.c, b.c ? b.v : a.v + b.v};
 }
 
+struct CSegStep {
+    template <int CTRL, int RM, class AT>
+    __device__ __forceinline__ CSeg<AT> apply(const CSeg<AT> &s) const {
+        const CSeg<AT> u{dpp_move<CTRL, RM>(s.c), dpp_move<CTRL, RM>(s.v)};
+        return cseg_combine(u, s);
+    }
+};
+
 // a live flagged column is never -1: flagged values are INT_MIN + col with
 // col < 2^31 - 1, so -1 can mark the dead slots outside the live range
 constexpr int32_t kDeadCol = -1;
@@ -255,11 +263,7 @@ __device__ __forceinline__ CSeg<AT> flag_chunk(const Run<J, VT, XT> &R, CSeg<AT>
         s.v = hd[k] ? p[k] : s.v + p[k];
         s.c += hd[k];
     }
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        CSeg<AT> u{shfl_up(s.c, d), shfl_up(s.v, d)};
-        if (lane >= d) s = cseg_combine(u, s);
-    }
+    s = wave_scan_dpp(s, CSegStep{});
     if (lane == kWave - 1) wave_tot[wid] = s;
     __syncthreads();
     CSeg<AT> pre = seed, total = seed;

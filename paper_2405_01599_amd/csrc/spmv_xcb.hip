@@ -87,11 +87,7 @@ __global__ __launch_bounds__(kNT) void k_spmv_xcb(XcbArgs a, const XT *__restric
         s.v = hd[q] ? p[q] : s.v + p[q];
         s.c += hd[q];
     }
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        CSeg<AT> u{shfl_up(s.c, d), shfl_up(s.v, d)};
-        if (lane >= d) s = cseg_combine(u, s);
-    }
+    s = wave_scan_dpp(s, CSegStep{});
     if (lane == kWave - 1) wave_tot[wid] = s;
     __syncthreads();
     CSeg<AT> pre{0, AT(0)}, total{0, AT(0)};
