@@ -17,6 +17,7 @@ namespace {
 using xab::Seg;
 constexpr int kNT = 256;
 constexpr int kBatchJ = 4;  // entries per lane of the batched SpMV tiles
+constexpr int kBiNT = 1024; // threads of the per-system solver kernels (one workgroup per system)
 
 
 // Batched SpMV over the concatenation, in segmented-scan tiles of
@@ -72,7 +73,7 @@ __device__ __forceinline__ double bsum(double v, double *sh) {
     __syncthreads();
     double t = 0.0;
 #pragma unroll
-    for (int i = 0; i < kNT / xab::kWave; ++i) t += sh[i];
+    for (int i = 0; i < kBiNT / xab::kWave; ++i) t += sh[i];
     __syncthreads();
     return t;
 }
@@ -85,15 +86,15 @@ struct SysState {
 
 // ||b||, r = b - A x0 (A x0 given in t), rhat = r, p = v = 0, scalars reset.
 template <class T>
-__global__ __launch_bounds__(kNT) void k_bi_init(const int64_t *__restrict__ row_off, const T *__restrict__ bvec,
+__global__ __launch_bounds__(kBiNT) void k_bi_init(const int64_t *__restrict__ row_off, const T *__restrict__ bvec,
                                                  const T *__restrict__ ax, T *__restrict__ r, T *__restrict__ rh,
                                                  T *__restrict__ p, T *__restrict__ v, SysState *__restrict__ st,
                                                  int *__restrict__ active, double tol, int *__restrict__ n_active) {
-    __shared__ double sh[kNT / xab::kWave];
+    __shared__ double sh[kBiNT / xab::kWave];
     const int k = blockIdx.x;
     const int64_t r0 = row_off[k], r1 = row_off[k + 1];
     double bb = 0.0, rr = 0.0;
-    for (int64_t i = r0 + threadIdx.x; i < r1; i += kNT) {
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += kBiNT) {
         double bi = (double)bvec[i];
         T ri = (T)(bi - (double)ax[i]);
         r[i] = ri;
@@ -122,18 +123,18 @@ __global__ __launch_bounds__(kNT) void k_bi_init(const int64_t *__restrict__ row
 
 // rho = <rhat, r>, beta, p = r + beta (p - omega v), phat = M^-1 p
 template <class T>
-__global__ __launch_bounds__(kNT) void k_bi_p(const int64_t *__restrict__ row_off, const T *__restrict__ r,
+__global__ __launch_bounds__(kBiNT) void k_bi_p(const int64_t *__restrict__ row_off, const T *__restrict__ r,
                                               const T *__restrict__ rh, T *__restrict__ p, const T *__restrict__ v,
                                               T *__restrict__ ph, const T *__restrict__ d, SysState *__restrict__ st,
                                               int *__restrict__ active, double *__restrict__ rho_out,
                                               int *__restrict__ n_active) {
-    __shared__ double sh[kNT / xab::kWave];
+    __shared__ double sh[kBiNT / xab::kWave];
     __shared__ double beta_s;
     const int k = blockIdx.x;
     if (!active[k]) return;
     const int64_t r0 = row_off[k], r1 = row_off[k + 1];
     double a = 0.0;
-    for (int64_t i = r0 + threadIdx.x; i < r1; i += kNT) a += (double)rh[i] * (double)r[i];
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += kBiNT) a += (double)rh[i] * (double)r[i];
     const double rho = bsum(a, sh);
     if (threadIdx.x == 0) {
         SysState s = st[k];
@@ -152,7 +153,7 @@ __global__ __launch_bounds__(kNT) void k_bi_p(const int64_t *__restrict__ row_of
     const double beta = beta_s;
     if (beta != beta) return;
     const double om = st[k].omega;
-    for (int64_t i = r0 + threadIdx.x; i < r1; i += kNT) {
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += kBiNT) {
         T pi = (T)((double)r[i] + beta * ((double)p[i] - om * (double)v[i]));
         p[i] = pi;
         ph[i] = d ? (T)((double)pi / (double)d[i]) : pi;
@@ -162,20 +163,20 @@ __global__ __launch_bounds__(kNT) void k_bi_p(const int64_t *__restrict__ row_of
 // alpha = rho / <rhat, v>, s = r - alpha v, ||s||; early exit when ||s||
 // meets tol (x += alpha phat); else shat = M^-1 s
 template <class T>
-__global__ __launch_bounds__(kNT) void k_bi_s(const int64_t *__restrict__ row_off, const T *__restrict__ r,
+__global__ __launch_bounds__(kBiNT) void k_bi_s(const int64_t *__restrict__ row_off, const T *__restrict__ r,
                                               const T *__restrict__ rh, const T *__restrict__ v, T *__restrict__ s,
                                               T *__restrict__ sh_vec, const T *__restrict__ ph, T *__restrict__ x,
                                               const T *__restrict__ d, SysState *__restrict__ st,
                                               int *__restrict__ active, const double *__restrict__ rho_in, double tol,
                                               int *__restrict__ n_active) {
-    __shared__ double sh[kNT / xab::kWave];
+    __shared__ double sh[kBiNT / xab::kWave];
     __shared__ double alpha_s;
     __shared__ int done_s;
     const int k = blockIdx.x;
     if (!active[k]) return;
     const int64_t r0 = row_off[k], r1 = row_off[k + 1];
     double a = 0.0;
-    for (int64_t i = r0 + threadIdx.x; i < r1; i += kNT) a += (double)rh[i] * (double)v[i];
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += kBiNT) a += (double)rh[i] * (double)v[i];
     const double rv = bsum(a, sh);
     if (threadIdx.x == 0) {
         if (rv == 0.0) {
@@ -193,7 +194,7 @@ __global__ __launch_bounds__(kNT) void k_bi_s(const int64_t *__restrict__ row_of
     const double alpha = alpha_s;
     if (alpha != alpha) return;
     double ss = 0.0;
-    for (int64_t i = r0 + threadIdx.x; i < r1; i += kNT) {
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += kBiNT) {
         T si = (T)((double)r[i] - alpha * (double)v[i]);
         s[i] = si;
         ss += (double)si * (double)si;
@@ -215,28 +216,28 @@ __global__ __launch_bounds__(kNT) void k_bi_s(const int64_t *__restrict__ row_of
     }
     __syncthreads();
     if (done_s) {
-        for (int64_t i = r0 + threadIdx.x; i < r1; i += kNT) x[i] = (T)((double)x[i] + alpha * (double)ph[i]);
+        for (int64_t i = r0 + threadIdx.x; i < r1; i += kBiNT) x[i] = (T)((double)x[i] + alpha * (double)ph[i]);
         return;
     }
-    for (int64_t i = r0 + threadIdx.x; i < r1; i += kNT) sh_vec[i] = d ? (T)((double)s[i] / (double)d[i]) : s[i];
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += kBiNT) sh_vec[i] = d ? (T)((double)s[i] / (double)d[i]) : s[i];
 }
 
 // omega = <t, s> / <t, t>, x += alpha phat + omega shat, r = s - omega t,
 // ||r|| -> convergence
 template <class T>
-__global__ __launch_bounds__(kNT) void k_bi_x(const int64_t *__restrict__ row_off, const T *__restrict__ s,
+__global__ __launch_bounds__(kBiNT) void k_bi_x(const int64_t *__restrict__ row_off, const T *__restrict__ s,
                                               const T *__restrict__ t, const T *__restrict__ ph,
                                               const T *__restrict__ shv, T *__restrict__ x, T *__restrict__ r,
                                               SysState *__restrict__ st, int *__restrict__ active,
                                               const double *__restrict__ rho_in, double tol, int64_t maxiter,
                                               int *__restrict__ n_active) {
-    __shared__ double sh[kNT / xab::kWave];
+    __shared__ double sh[kBiNT / xab::kWave];
     __shared__ double om_s;
     const int k = blockIdx.x;
     if (!active[k]) return;
     const int64_t r0 = row_off[k], r1 = row_off[k + 1];
     double ts = 0.0, tt = 0.0;
-    for (int64_t i = r0 + threadIdx.x; i < r1; i += kNT) {
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += kBiNT) {
         double ti = (double)t[i];
         ts += ti * (double)s[i];
         tt += ti * ti;
@@ -248,7 +249,7 @@ __global__ __launch_bounds__(kNT) void k_bi_x(const int64_t *__restrict__ row_of
     const double om = om_s;
     const double al = st[k].alpha;
     double rr = 0.0;
-    for (int64_t i = r0 + threadIdx.x; i < r1; i += kNT) {
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += kBiNT) {
         x[i] = (T)((double)x[i] + al * (double)ph[i] + om * (double)shv[i]);
         T ri = (T)((double)s[i] - om * (double)t[i]);
         r[i] = ri;
@@ -281,14 +282,14 @@ __global__ __launch_bounds__(kNT) void k_bi_x(const int64_t *__restrict__ row_of
 
 // true residual per system: res[k] = ||b - A x||_k / ||b||_k (A x given)
 template <class T>
-__global__ __launch_bounds__(kNT) void k_bi_true(const int64_t *__restrict__ row_off, const T *__restrict__ bvec,
+__global__ __launch_bounds__(kBiNT) void k_bi_true(const int64_t *__restrict__ row_off, const T *__restrict__ bvec,
                                                  const T *__restrict__ ax, const SysState *__restrict__ st,
                                                  double *__restrict__ out) {
-    __shared__ double sh[kNT / xab::kWave];
+    __shared__ double sh[kBiNT / xab::kWave];
     const int k = blockIdx.x;
     const int64_t r0 = row_off[k], r1 = row_off[k + 1];
     double a = 0.0;
-    for (int64_t i = r0 + threadIdx.x; i < r1; i += kNT) {
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += kBiNT) {
         double e = (double)bvec[i] - (double)ax[i];
         a += e * e;
     }
@@ -317,15 +318,20 @@ __global__ void k_check_blockdiag(const int32_t *__restrict__ rowptr, const int3
         }
 }
 
+// Jacobi diagonal: 8 lanes per row, each summing the row's diagonal entries
+// among its strided share, then a fixed xor tree over the 8 lanes.
 template <class T>
-__global__ void k_diag_b(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colind,
-                         const T *__restrict__ val, int64_t n, T *__restrict__ d) {
-    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= n) return;
+__global__ __launch_bounds__(256) void k_diag_b(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colind,
+                                                const T *__restrict__ val, int64_t n, T *__restrict__ d) {
+    const int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 8;
+    const int l = threadIdx.x % 8;
     double a = 0.0;
-    for (int64_t k = rowptr[r]; k < rowptr[r + 1]; ++k)
-        if (colind[k] == r) a += (double)val[k];
-    d[r] = a != 0.0 ? (T)a : T(1);
+    if (r < n)
+        for (int64_t k = rowptr[r] + l; k < rowptr[r + 1]; k += 8)
+            if (colind[k] == r) a += (double)val[k];
+#pragma unroll
+    for (int m = 4; m > 0; m >>= 1) a += __shfl_xor(a, m, 8);
+    if (r < n && l == 0) d[r] = a != 0.0 ? (T)a : T(1);
 }
 
 __global__ void k_zero_int(int *p) {
@@ -368,7 +374,7 @@ int bicgstab_t(xab_ctx *ctx, const xab_batch *B, const T *bvec, T *x, const xab_
     char *w = (char *)xab_dalloc(ctx, total);
     if (!w) return xab_fail(ctx, XAB_E_NOMEM, "BiCGStab workspace");
     T *r = (T *)w, *rh = (T *)(w + vb), *p = (T *)(w + 2 * vb), *v = (T *)(w + 3 * vb), *ph = (T *)(w + 4 * vb);
-    T *s = (T *)(w + 5 * vb), *shv = (T *)(w + 6 * vb), *t = (T *)(w + 7 * vb), *d = (T *)(w + 8 * vb);
+    T *s = (T *)(w + 5 * vb), *shv = (T *)(w + 6 * vb), *t = (T *)(w + 7 * vb);
     T *ax = (T *)(w + 9 * vb);
     SysState *stt = (SysState *)(w + off_st);
     double *rho = (double *)(w + off_rho);
@@ -395,24 +401,31 @@ int bicgstab_t(xab_ctx *ctx, const xab_batch *B, const T *bvec, T *x, const xab_
     const int64_t maxiter = o->maxiter > 0 ? o->maxiter : 10000;
     auto t0 = std::chrono::steady_clock::now();
     int sres;
-    if (jac) hipLaunchKernelGGL((k_diag_b<T>), dim3(grid_for(n, 256)), dim3(256), 0, st, B->rowptr, B->colind,
-                                (const T *)B->val, n, d);
+    if (jac && !B->diag) {
+        // computed once per batch and kept with it
+        xab_batch *Bm = const_cast<xab_batch *>(B);
+        Bm->diag = xab_dalloc(ctx, sizeof(T) * (size_t)(n > 0 ? n : 1));
+        if (!Bm->diag) return cleanup(xab_fail(ctx, XAB_E_NOMEM, "Jacobi diagonal"));
+        if (n > 0)
+            hipLaunchKernelGGL((k_diag_b<T>), dim3(grid_for(n * 8, 256)), dim3(256), 0, st, B->rowptr, B->colind,
+                               (const T *)B->val, n, (T *)Bm->diag);
+    }
     hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, st, n_active);
     if ((sres = batch_spmv_t<T>(ctx, B, x, ax, nullptr, st)) != XAB_OK) return cleanup(sres);
-    hipLaunchKernelGGL((k_bi_init<T>), dim3(ns), dim3(kNT), 0, st, B->d_row_off, bvec, ax, r, rh, p, v, stt, active, tol,
+    hipLaunchKernelGGL((k_bi_init<T>), dim3(ns), dim3(kBiNT), 0, st, B->d_row_off, bvec, ax, r, rh, p, v, stt, active, tol,
                        n_active);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return cleanup(xab_hip_check(ctx, e, "BiCGStab init"));
-    const T *dd = jac ? d : nullptr;
+    const T *dd = jac ? (const T *)B->diag : nullptr;
     // one iteration over all systems
     auto enqueue_iter = [&](hipStream_t q) {
-        hipLaunchKernelGGL((k_bi_p<T>), dim3(ns), dim3(kNT), 0, q, B->d_row_off, r, rh, p, v, ph, dd, stt, active, rho,
+        hipLaunchKernelGGL((k_bi_p<T>), dim3(ns), dim3(kBiNT), 0, q, B->d_row_off, r, rh, p, v, ph, dd, stt, active, rho,
                            n_active);
         launch_batch_spmv<T>(B, ph, v, active, q);
-        hipLaunchKernelGGL((k_bi_s<T>), dim3(ns), dim3(kNT), 0, q, B->d_row_off, r, rh, v, s, shv, ph, x, dd, stt, active,
+        hipLaunchKernelGGL((k_bi_s<T>), dim3(ns), dim3(kBiNT), 0, q, B->d_row_off, r, rh, v, s, shv, ph, x, dd, stt, active,
                            rho, tol, n_active);
         launch_batch_spmv<T>(B, shv, t, active, q);
-        hipLaunchKernelGGL((k_bi_x<T>), dim3(ns), dim3(kNT), 0, q, B->d_row_off, s, t, ph, shv, x, r, stt, active, rho, tol,
+        hipLaunchKernelGGL((k_bi_x<T>), dim3(ns), dim3(kBiNT), 0, q, B->d_row_off, s, t, ph, shv, x, r, stt, active, rho, tol,
                            maxiter, n_active);
     };
     const int every = o->check_every > 0 ? o->check_every : 8;
@@ -458,7 +471,7 @@ int bicgstab_t(xab_ctx *ctx, const xab_batch *B, const T *bvec, T *x, const xab_
     }
     // true residuals
     if ((sres = batch_spmv_t<T>(ctx, B, x, ax, nullptr, st)) != XAB_OK) return cleanup(sres);
-    hipLaunchKernelGGL((k_bi_true<T>), dim3(ns), dim3(kNT), 0, st, B->d_row_off, bvec, ax, stt, res);
+    hipLaunchKernelGGL((k_bi_true<T>), dim3(ns), dim3(kBiNT), 0, st, B->d_row_off, bvec, ax, stt, res);
     std::vector<SysState> hs(ns);
     std::vector<double> hr(ns);
     e = hipMemcpyAsync(hs.data(), stt, sizeof(SysState) * ns, hipMemcpyDeviceToHost, st);
@@ -578,6 +591,7 @@ void xab_batch_destroy(xab_batch *B) {
     xab_dfree(B->ctx, B->tail_row);
     xab_dfree(B->ctx, B->carry_val);
     xab_dfree(B->ctx, B->tail_val);
+    xab_dfree(B->ctx, B->diag);
     xab_dfree(B->ctx, B->d_sys_of_row);
     xab_dfree(B->ctx, B->d_row_off);
     delete B;

@@ -21,13 +21,22 @@ __device__ __forceinline__ double block_sum(double v, double *sh) {
     return t;
 }
 
+// Wave sum through DPP moves: the total lands in the last lane.
+struct AddStep {
+    template <int CTRL, int RM>
+    __device__ __forceinline__ double apply(double s) const {
+        return s + dpp_move<CTRL, RM>(s);
+    }
+};
+
 // part[b * ldp + i] = sum over this workgroup's rows of V_i[r] * w[r]
 // (i < nv), part[b * ldp + nv] = sum of w[r]^2.  Rows are dealt in
-// contiguous chunks of 256 to the workgroups.
+// contiguous chunks of 256 to the workgroups.  The nv + 1 sums are reduced
+// per wave with DPP (fixed order), then across the waves in wave order.
 template <class T, int NV>
-__global__ __launch_bounds__(kNT) void k_mdot(const T *__restrict__ V, int64_t ldv, int nv, const T *__restrict__ w,
-                                              int64_t n, double *__restrict__ part, int ldp) {
-    __shared__ double sh[kNT / kWave];
+__device__ __forceinline__ void mdot_body(const T *__restrict__ V, int64_t ldv, int nv, const T *__restrict__ w,
+                                          int64_t n, double *__restrict__ part, int ldp) {
+    __shared__ double sh[kNT / kWave][NV + 1];
     double acc[NV + 1];
 #pragma unroll
     for (int i = 0; i <= NV; ++i) acc[i] = 0.0;
@@ -38,16 +47,26 @@ __global__ __launch_bounds__(kNT) void k_mdot(const T *__restrict__ V, int64_t l
         for (int i = 0; i < NV; ++i)
             if (i < nv) acc[i] += (double)V[i * ldv + r] * wr;
     }
-    for (int i = 0; i < nv; ++i) {
+    const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+#pragma unroll
+    for (int i = 0; i <= NV; ++i) {
+        const double t = wave_scan_dpp(acc[i], AddStep{});
+        if (lane == kWave - 1) sh[wv][i] = t;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x <= nv) {
+        const int src = (int)threadIdx.x < nv ? (int)threadIdx.x : NV;
         double t = 0.0;
 #pragma unroll
-        for (int q = 0; q < NV; ++q)
-            if (q == i) t = acc[q];
-        t = block_sum(t, sh);
-        if (threadIdx.x == 0) part[(int64_t)blockIdx.x * ldp + i] = t;
+        for (int q = 0; q < kNT / kWave; ++q) t += sh[q][src];
+        part[(int64_t)blockIdx.x * ldp + threadIdx.x] = t;
     }
-    double t = block_sum(acc[NV], sh);
-    if (threadIdx.x == 0) part[(int64_t)blockIdx.x * ldp + nv] = t;
+}
+
+template <class T, int NV>
+__global__ __launch_bounds__(kNT) void k_mdot(const T *__restrict__ V, int64_t ldv, int nv, const T *__restrict__ w,
+                                              int64_t n, double *__restrict__ part, int ldp) {
+    mdot_body<T, NV>(V, ldv, nv, w, n, part, ldp);
 }
 
 // w -= sum_i h[i] V_i (i < nv); part[b] = sum of the new w^2.  When `gate`
@@ -76,33 +95,13 @@ __global__ __launch_bounds__(kNT) void k_update_norm(const T *__restrict__ V, in
     if (threadIdx.x == 0) part[blockIdx.x] = acc;
 }
 
+// the gated launch of the second Gram-Schmidt pass
 template <class T, int NV>
 __global__ __launch_bounds__(kNT) void k_mdot_gated(const T *__restrict__ V, int64_t ldv, int nv,
                                                     const T *__restrict__ w, int64_t n, double *__restrict__ part,
                                                     int ldp, const int *__restrict__ gate) {
     if (*gate == 0) return;
-    // same body as k_mdot (a gated launch of the second pass)
-    __shared__ double sh[kNT / kWave];
-    double acc[NV + 1];
-#pragma unroll
-    for (int i = 0; i <= NV; ++i) acc[i] = 0.0;
-    for (int64_t r = (int64_t)blockIdx.x * kNT + threadIdx.x; r < n; r += (int64_t)gridDim.x * kNT) {
-        const double wr = (double)w[r];
-        acc[NV] += wr * wr;
-#pragma unroll
-        for (int i = 0; i < NV; ++i)
-            if (i < nv) acc[i] += (double)V[i * ldv + r] * wr;
-    }
-    for (int i = 0; i < nv; ++i) {
-        double t = 0.0;
-#pragma unroll
-        for (int q = 0; q < NV; ++q)
-            if (q == i) t = acc[q];
-        t = block_sum(t, sh);
-        if (threadIdx.x == 0) part[(int64_t)blockIdx.x * ldp + i] = t;
-    }
-    double t = block_sum(acc[NV], sh);
-    if (threadIdx.x == 0) part[(int64_t)blockIdx.x * ldp + nv] = t;
+    mdot_body<T, NV>(V, ldv, nv, w, n, part, ldp);
 }
 
 }  // namespace

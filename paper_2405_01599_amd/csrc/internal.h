@@ -105,6 +105,7 @@ struct xab_batch {
     double *carry_val = nullptr, *tail_val = nullptr;
     int32_t *d_sys_of_row = nullptr; // system index of every row
     int64_t *d_row_off = nullptr;    // [nsys+1]
+    void *diag = nullptr;            // Jacobi diagonal (value type; lazy, library-owned)
 };
 
 // ------------------------------------------------------------------ helpers
