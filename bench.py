@@ -98,6 +98,46 @@ def calibration_copy(torch):
     torch.cuda.synchronize()
 
 
+def stream_rates(torch):
+    """Achievable streaming rates on this GPU (HIP events, 10 launches each):
+    a 256 MiB read + 256 MiB write elementwise copy, and a 1 GiB read-only
+    reduction."""
+    a = torch.full((CAL_BYTES // 8,), 1.0, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    big = torch.ones((1 << 30) // 8, dtype=torch.float64, device="cuda")
+    out = {}
+    for name, fn, by in (("copy_gbs", lambda: torch.neg(a, out=b), 2 * CAL_BYTES),
+                         ("read_gbs", lambda: big.sum(), 1 << 30)):
+        for _ in range(3):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        out[name] = round(by / (e0.elapsed_time(e1) / 10 * 1e-3) / 1e9, 1)
+    del a, b, big
+    return out
+
+
+def cold_spmv_us(ctx, torch, plan, x, y, reps=5):
+    """Single SpMVs after writing a 1 GiB buffer (x, y and the matrix are
+    evicted from L2 and the 256 MB MALL first); median of `reps`."""
+    flush = torch.empty((1 << 30) // 8, dtype=torch.float64, device="cuda")
+    ts = []
+    for _ in range(reps):
+        flush.zero_()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        ctx.spmv(plan, x, y)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1) * 1e3)
+    del flush
+    return round(sorted(ts)[len(ts) // 2], 2)
+
+
 def _counter_csv(d):
     files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
     if len(files) != 1:
@@ -200,6 +240,21 @@ def gmres_pair(ctx, xab, torch, plan, n, reps=3):
     return res
 
 
+def restart_tuning_leg(ctx, xab, torch, plan, n):
+    """Restart-length tuning by the MM ratio: FP64 GMRES with Jacobi from
+    m = 5, fixed vs grown by 5 (up to 30) after each cycle whose MM ratio is
+    below 10; median of 3 each."""
+    b = torch.ones(n, dtype=torch.float64, device="cuda")
+    res = {}
+    for name, kw in (("fixed_m5", {}), ("tuned_m5_step5_max30", dict(restart_step=5, m_max=30, mm_ratio=10.0))):
+        runs = sorted((ctx.gmres(plan, b, m=5, tol=1e-10, precond=xab.PRECOND_JACOBI, **kw)[1] for _ in range(3)),
+                      key=lambda r: r["seconds"])
+        med = runs[1]
+        res[name] = {"s": round(med["seconds"], 5), "iters": med["iters"], "cycles": med["restarts"],
+                     "m_final": med["m_final"], "relres": med["true_relres"], "status": med["status"]}
+    return res
+
+
 def sym_stencil_leg(ctx, xab, torch, gen, gmres=True):
     """Symmetric SpMV from lower storage on the 128^3 27-point stencil:
     TIME-selected implementation, FP64 and FP32 values (FP64 accumulation),
@@ -210,19 +265,21 @@ def sym_stencil_leg(ctx, xab, torch, gen, gmres=True):
     x = torch.from_numpy(gen.uniform_vec(L.n, 13)).cuda()
     y = torch.empty(L.n, dtype=torch.float64, device="cuda")
     ms64 = ctx.time_spmv(plan, x, y, warmup=5, reps=100)
+    cold64 = cold_spmv_us(ctx, torch, plan, x, y)
     x32, y32 = x.float(), y.float()
     ms32 = ctx.time_spmv(plan, x32, y32, acc=xab.F64, warmup=5, reps=100)
     by64, by32 = alg_bytes(L.n, L.nnz, 8, 8, 8), alg_bytes(L.n, L.nnz, 4, 4, 4)
     out = {"workload": f"27-point stencil 128^3, lower triangle stored: n={L.n} nnz_L={L.nnz}",
            "selected": plan.describe(), "chosen_class": int(info.chosen),
            "us_per_class": {k: round(float(info.time_ms[k]) * 1e3, 2) for k in range(xab.NCLASSES) if info.valid[k]},
-           "fp64": {"us": round(ms64 * 1e3, 2), "gbs": round(by64 / (ms64 * 1e-3) / 1e9, 1),
+           "fp64": {"us": round(ms64 * 1e3, 2), "cold_us": cold64, "gbs": round(by64 / (ms64 * 1e-3) / 1e9, 1),
                     "frac": round(by64 / (ms64 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                     "gflops": round(2 * (2 * L.nnz - L.n) / (ms64 * 1e-3) / 1e9, 1)},
            "fp32_values": {"us": round(ms32 * 1e3, 2), "gbs": round(by32 / (ms32 * 1e-3) / 1e9, 1),
                            "frac": round(by32 / (ms32 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}}
     if gmres:
         out["gmres"] = gmres_pair(ctx, xab, torch, plan, L.n)
+        out["gmres_restart_tuning"] = restart_tuning_leg(ctx, xab, torch, plan, L.n)
     plan.close()
     M.close()
     return out
@@ -351,6 +408,9 @@ def main():
                 "kernel": f"{variant} SpMV: " + " + ".join(VARIANT_KERNELS.get(variant, ())),
                 "bytes_per_launch": by64, "us_per_launch": round(ev_ms * 1e3, 2)}
 
+    cold = cold_spmv_us(ctx, torch, plan, xd, y)
+    stream = stream_rates(torch)
+
     # FP32 values and x, FP64 accumulation, FP32 y (the inner SpMV of GMRES-IR)
     plan32 = ctx.plan_class(M, chosen)
     ev32 = ctx.time_spmv(plan32, xd32, y32, acc=xab.F64, warmup=5, reps=100)
@@ -394,6 +454,8 @@ def main():
                                "TIME-policy selected implementation", "n": A.n, "nnz": A.nnz,
                    "selected": plan.describe()},
         "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+        "cold_us_per_step": cold,
+        "stream": dict(stream, frac_of_read=round(gbs / stream["read_gbs"], 4)),
         "gflops": round(2 * A.nnz / (wall / args.steps) / 1e9, 1),
         "fp32_values": fp32,
         "selector": {"chosen_class": chosen, "us_per_class": times, "select_ms": round(float(info.select_ms), 2),

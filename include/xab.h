@@ -265,6 +265,10 @@ typedef struct {
     double inner_tol;     /* IR: inner relative residual (1e-6) */
     int32_t graph;        /* batched BiCGStab: capture one iteration in a HIP graph */
     int32_t check_every;  /* batched BiCGStab: iterations between host convergence checks */
+    int32_t restart_step; /* GMRES restart-length tuning (0 = fixed m): grow m by this much after a
+                             cycle whose residual samples have an MM ratio below mm_ratio */
+    int32_t m_max;        /* GMRES restart-length tuning: upper bound on m (<= 63) */
+    double mm_ratio;      /* GMRES restart-length tuning: stagnation threshold on the MM ratio */
 } xab_krylov_opts;
 
 typedef struct {
@@ -274,6 +278,7 @@ typedef struct {
     double true_relres;   /* ||b - A x|| / ||b|| in FP64 at exit */
     double seconds;       /* wall time of the call */
     int32_t status;       /* same as the return value */
+    int32_t m_final;      /* GMRES: restart length of the last cycle */
 } xab_krylov_info;
 
 /* Restarted GMRES(m) (section 2.2) on A x = b.  d_x holds x0 on entry and
@@ -286,6 +291,12 @@ typedef struct {
  * variant is used for every SpMV.  Orthogonalisation: classical
  * Gram-Schmidt applied twice (the DGKS scheme, section 3.2.2).
  * Convergence is only declared on the true residual (section 3.3.2).
+ * Restart-length tuning (section 3.2.1 with the section 4.3 setting), when
+ * restart_step > 0: after every cycle the MM ratio of eq. (1) is taken over
+ * that cycle's residual samples (the relative true residual at its start
+ * and the relative recurrence residual after each of its steps); below
+ * mm_ratio the cycle is judged stagnant and m grows by restart_step, up to
+ * m_max.  In IR mode the samples are those of the inner cycle.
  * Synchronous. */
 int xab_gmres(xab_ctx *ctx, const xab_plan *plan, const double *d_b, double *d_x, const xab_krylov_opts *opts,
               xab_krylov_info *info);

@@ -44,6 +44,8 @@ def lib():
             "orc_adam_step": (None, [i64, P, P, P, P, i64, d, d, d, d]),
             "orc_mlp_train": (None, [ci, ci, ci, P, i64, P, P, P, P, ci, ci, d, P]),
             "orc_gmres": (ci, [i64, P, P, P, P, P, ci, d, i64, ci, P, P, P, P]),
+            "orc_mm_ratio": (d, [P, i64, i64]),
+            "orc_gmres_at": (ci, [i64, P, P, P, P, P, ci, ci, ci, d, d, i64, ci, P, P, P, P, P]),
             "orc_bicgstab": (ci, [i64, P, P, P, P, P, d, i64, ci, P, P, P]),
         }
         for name, (res, args) in sig.items():
@@ -227,6 +229,28 @@ def gmres(A, b, x0=None, m=30, tol=1e-10, maxiter=10000, precond=0, history=Fals
     if history:
         out["hist"] = hist[: out["iters"] + 1]
         out["arnoldi_err"] = float(aerr[0])
+    return out
+
+
+def mm_ratio(r, s, t):
+    """Eq. (1): max / min of r(z), z = s-t+1 .. s (1-based samples)."""
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    return float(lib().orc_mm_ratio(_p(r), s, t))
+
+
+def gmres_at(A, b, m0, m_max, step, ratio, x0=None, tol=1e-10, maxiter=10000, precond=0):
+    """GMRES with the restart length tuned by the MM ratio after every cycle;
+    returns the solve summary plus the m of every cycle."""
+    rp, ci, v = _csr(A)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    x = np.zeros(A.n) if x0 is None else np.array(x0, dtype=np.float64)
+    info = np.zeros(3, dtype=np.int64)
+    dinfo = np.zeros(1, dtype=np.float64)
+    mh = np.zeros(maxiter + 1, dtype=np.int32)
+    lib().orc_gmres_at(A.n, _p(rp), _p(ci), _p(v), _p(b), _p(x), m0, m_max, step, ratio, tol, maxiter, precond,
+                       _p(info), _p(dinfo), None, None, _p(mh))
+    out = dict(x=x, iters=int(info[0]), cycles=int(info[1]), status=int(info[2]), relres=float(dinfo[0]))
+    out["m_hist"] = mh[: out["cycles"]].tolist()
     return out
 
 

@@ -540,9 +540,32 @@ static void diag_of(int64_t n, const int32_t *rp, const int32_t *ci, const doubl
  * computed at every restart (the accuracy policy's outer check).
  * arnoldi_err (optional) receives max over cycles of
  * ||A M^-1 V_j - V_{j+1} Hbar_j||_F / ||H||_F before the rotations. */
-int orc_gmres(int64_t n, const int32_t *rowptr, const int32_t *colind, const double *val,
-              const double *b, double *x, int m, double tol, int64_t maxiter, int precond,
-              int64_t *info, double *dinfo, double *resid_hist, double *arnoldi_err) {
+/* The MM ratio of eq. (1): with residual samples r(1), r(2), ... (r[0]
+ * holds r(1)), R(s, t) = max over z = s-t+1 .. s of r(z) divided by the
+ * min over the same window. */
+double orc_mm_ratio(const double *r, int64_t s, int64_t t) {
+    double mx = r[s - t], mn = r[s - t];
+    for (int64_t z = s - t + 1; z <= s; ++z) {
+        if (r[z - 1] > mx) mx = r[z - 1];
+        if (r[z - 1] < mn) mn = r[z - 1];
+    }
+    return mx / mn;
+}
+
+/* Restarted GMRES(m).  With step > 0 the restart length is tuned at run
+ * time in the manner of section 3.2.1 and the section 4.3 setting: after
+ * every cycle the MM ratio of that cycle's residual samples (the relative
+ * residual at its start and the recurrence residual after each of its
+ * steps) is formed over the whole cycle, and when it is below `ratio` (the
+ * residual stagnated) the next cycle's m grows by `step`, up to m_max.
+ * m_hist (may be NULL) receives the m of every cycle. */
+int orc_gmres_at(int64_t n, const int32_t *rowptr, const int32_t *colind, const double *val,
+                 const double *b, double *x, int m0, int m_max, int step, double ratio, double tol,
+                 int64_t maxiter, int precond, int64_t *info, double *dinfo, double *resid_hist,
+                 double *arnoldi_err, int32_t *m_hist) {
+    const int m = (step > 0 && m_max > m0) ? m_max : m0; /* capacity: rows of H, columns of V */
+    int cm = m0;                                          /* restart length of the current cycle */
+    double *samp = malloc(sizeof(double) * (m + 1));
     double *V = malloc(sizeof(double) * (size_t)n * (m + 1));
     double *H = calloc((size_t)(m + 1) * m, sizeof(double));   /* H[i*m + j] */
     double *H0 = calloc((size_t)(m + 1) * m, sizeof(double));  /* unrotated copy */
@@ -565,12 +588,14 @@ int orc_gmres(int64_t n, const int32_t *rowptr, const int32_t *colind, const dou
         if (resid_hist && it == 0) resid_hist[0] = relres;
         if (relres <= tol) { status = 0; break; }
         if (it >= maxiter) { status = 1; break; }
+        if (m_hist) m_hist[restarts] = cm;
         restarts++; /* cycles started */
         for (int64_t i = 0; i < n; ++i) V[i] = r[i] / beta;
         memset(g, 0, sizeof(double) * (m + 1));
         g[0] = beta;
+        samp[0] = relres;
         int j, k = 0;
-        for (j = 0; j < m && it < maxiter; ++j) {
+        for (j = 0; j < cm && it < maxiter; ++j) {
             double *vj = V + (int64_t)j * n;
             if (precond) for (int64_t i = 0; i < n; ++i) z[i] = vj[i] / dg[i];
             else memcpy(z, vj, sizeof(double) * n);
@@ -602,8 +627,12 @@ int orc_gmres(int64_t n, const int32_t *rowptr, const int32_t *colind, const dou
             ++it;
             k = j + 1;
             if (resid_hist) resid_hist[it] = fabs(g[j + 1]) / bn;
+            samp[j + 1] = fabs(g[j + 1]) / bn;
             if (hn == 0.0 || fabs(g[j + 1]) / bn <= tol) break;
         }
+        /* restart-length judgment on this cycle's samples */
+        if (step > 0 && cm < m_max && k > 0 && orc_mm_ratio(samp, k + 1, k + 1) < ratio)
+            cm = cm + step < m_max ? cm + step : m_max;
         if (arnoldi_err && k > 0) {
             /* || A M^-1 V_k - V_{k+1} Hbar_k ||_F / ||Hbar_k||_F (unrotated H) */
             double num = 0.0, den = 0.0;
@@ -637,7 +666,15 @@ int orc_gmres(int64_t n, const int32_t *rowptr, const int32_t *colind, const dou
     if (dinfo) dinfo[0] = relres;
     if (arnoldi_err) *arnoldi_err = aerr;
     free(V); free(H); free(H0); free(cs); free(sn); free(g); free(yv); free(w); free(z); free(r); free(dg);
+    free(samp);
     return status;
+}
+
+int orc_gmres(int64_t n, const int32_t *rowptr, const int32_t *colind, const double *val,
+              const double *b, double *x, int m, double tol, int64_t maxiter, int precond,
+              int64_t *info, double *dinfo, double *resid_hist, double *arnoldi_err) {
+    return orc_gmres_at(n, rowptr, colind, val, b, x, m, m, 0, 0.0, tol, maxiter, precond, info, dinfo,
+                        resid_hist, arnoldi_err, NULL);
 }
 
 /* BiCGStab (van der Vorst 1992), right preconditioned by M = diag(A) when

@@ -89,6 +89,11 @@ void orc_mlp_train(int F, int H, int K, double *p, int64_t M, const double *feat
 int orc_gmres(int64_t n, const int32_t *rowptr, const int32_t *colind, const double *val,
               const double *b, double *x, int m, double tol, int64_t maxiter, int precond,
               int64_t *info, double *dinfo, double *resid_hist, double *arnoldi_err);
+double orc_mm_ratio(const double *r, int64_t s, int64_t t);
+int orc_gmres_at(int64_t n, const int32_t *rowptr, const int32_t *colind, const double *val,
+                 const double *b, double *x, int m0, int m_max, int step, double ratio, double tol,
+                 int64_t maxiter, int precond, int64_t *info, double *dinfo, double *resid_hist,
+                 double *arnoldi_err, int32_t *m_hist);
 int orc_bicgstab(int64_t n, const int32_t *rowptr, const int32_t *colind, const double *val,
                  const double *b, double *x, double tol, int64_t maxiter, int precond, int64_t *info,
                  double *dinfo, double *resid_hist);

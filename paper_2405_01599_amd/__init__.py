@@ -63,12 +63,14 @@ class TrainInfo(ctypes.Structure):
 class KrylovOpts(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int32), ("tol", ctypes.c_double), ("maxiter", ctypes.c_int64),
                 ("max_time_s", ctypes.c_double), ("mode", ctypes.c_int32), ("precond", ctypes.c_int32),
-                ("inner_tol", ctypes.c_double), ("graph", ctypes.c_int32), ("check_every", ctypes.c_int32)]
+                ("inner_tol", ctypes.c_double), ("graph", ctypes.c_int32), ("check_every", ctypes.c_int32),
+                ("restart_step", ctypes.c_int32), ("m_max", ctypes.c_int32), ("mm_ratio", ctypes.c_double)]
 
 
 class KrylovInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int64), ("restarts", ctypes.c_int64), ("refinements", ctypes.c_int64),
-                ("true_relres", ctypes.c_double), ("seconds", ctypes.c_double), ("status", ctypes.c_int32)]
+                ("true_relres", ctypes.c_double), ("seconds", ctypes.c_double), ("status", ctypes.c_int32),
+                ("m_final", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -326,12 +328,13 @@ class Context:
 
     # ----------------------------------------------------------- Krylov
     def gmres(self, plan, b, x=None, m=30, tol=1e-10, maxiter=100000, mode=MODE_FP64, precond=PRECOND_JACOBI,
-              inner_tol=1e-6, max_time_s=0.0):
+              inner_tol=1e-6, max_time_s=0.0, restart_step=0, m_max=0, mm_ratio=0.0):
         torch = _torch()
         if x is None:
             x = torch.zeros_like(b)
         opts = KrylovOpts(m=m, tol=tol, maxiter=maxiter, max_time_s=max_time_s, mode=mode, precond=precond,
-                          inner_tol=inner_tol, graph=0, check_every=0)
+                          inner_tol=inner_tol, graph=0, check_every=0, restart_step=restart_step,
+                          m_max=m_max if m_max else m, mm_ratio=mm_ratio)
         info = KrylovInfo()
         s = self._check(lib().xab_gmres(self.h, plan.h, _ptr(b), _ptr(x), ctypes.byref(opts), ctypes.byref(info)),
                         "xab_gmres")
@@ -346,7 +349,7 @@ class Context:
         if x is None:
             x = torch.zeros_like(b)
         opts = KrylovOpts(m=0, tol=tol, maxiter=maxiter, max_time_s=0.0, mode=0, precond=precond, inner_tol=0.0,
-                          graph=int(graph), check_every=check_every)
+                          graph=int(graph), check_every=check_every, restart_step=0, m_max=0, mm_ratio=0.0)
         infos = (KrylovInfo * batch.nsys)()
         allinfo = KrylovInfo()
         s = self._check(lib().xab_bicgstab(self.h, batch.h, _ptr(b), _ptr(x), ctypes.byref(opts),

@@ -13,10 +13,18 @@ int mdot(xab_ctx *ctx, const T *V, int64_t ldv, int nv, const T *w, int64_t n, d
 template <class T>
 int update_norm(xab_ctx *ctx, const T *V, int64_t ldv, int nv, const double *h, T *w, int64_t n, double *part,
                 int nb, const int *gate);
+// w -= V h and, in the same sweep, partials of V^T w and ||w||^2 of the new w
+// (the first Gram-Schmidt pass's update fused with the second pass's dots)
+template <class T>
+int update_mdot(xab_ctx *ctx, const T *V, int64_t ldv, int nv, const double *h, T *w, int64_t n, double *part,
+                int nb);
 int reduce_parts(xab_ctx *ctx, const double *part, int nb, int ldp, int m, double *out, int add, const int *gate);
 int dgks_gate(xab_ctx *ctx, const double *wn2, const double *wpn2, double eta, int *gate);
+// v = w / ||w||, z = M^-1 v; the squared norm is *nrm2_gated when gate is
+// non-null and set, else *nrm2
 template <class T>
-int scale_precond(xab_ctx *ctx, const T *w, const double *nrm2, T *v, T *z, const T *d, int64_t n);
+int scale_precond(xab_ctx *ctx, const T *w, const double *nrm2, T *v, T *z, const T *d, int64_t n,
+                  const double *nrm2_gated = nullptr, const int *gate = nullptr);
 template <class TS, class T>
 int scale_from(xab_ctx *ctx, const TS *r, double scale, T *v, T *z, const T *d, int64_t n);
 int residual(xab_ctx *ctx, const double *b, double *r, int64_t n, double *part, int nb);

@@ -95,6 +95,51 @@ __global__ __launch_bounds__(kNT) void k_update_norm(const T *__restrict__ V, in
     if (threadIdx.x == 0) part[blockIdx.x] = acc;
 }
 
+// w' = w - sum_i h[i] V_i (i < nv), stored, and in the same sweep the
+// second Gram-Schmidt pass's dots: part[b * ldp + i] = sum V_i[r] w'[r],
+// part[b * ldp + nv] = sum w'[r]^2 (w' as stored).  One read of V serves
+// the first pass's update and the second pass's projection.
+template <class T, int NV>
+__global__ __launch_bounds__(kNT) void k_update_mdot(const T *__restrict__ V, int64_t ldv, int nv,
+                                                     const double *__restrict__ h, T *__restrict__ w, int64_t n,
+                                                     double *__restrict__ part, int ldp) {
+    __shared__ double sh[kNT / kWave][NV + 1];
+    double hh[NV], acc[NV + 1];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) hh[i] = i < nv ? h[i] : 0.0;
+#pragma unroll
+    for (int i = 0; i <= NV; ++i) acc[i] = 0.0;
+    for (int64_t r = (int64_t)blockIdx.x * kNT + threadIdx.x; r < n; r += (int64_t)gridDim.x * kNT) {
+        double vr[NV];
+        double a = (double)w[r];
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            vr[i] = i < nv ? (double)V[i * ldv + r] : 0.0;
+            a -= hh[i] * vr[i];
+        }
+        const T at = (T)a;
+        w[r] = at;
+        const double ad = (double)at;
+        acc[NV] += ad * ad;
+#pragma unroll
+        for (int i = 0; i < NV; ++i) acc[i] += vr[i] * ad;
+    }
+    const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+#pragma unroll
+    for (int i = 0; i <= NV; ++i) {
+        const double t = wave_scan_dpp(acc[i], AddStep{});
+        if (lane == kWave - 1) sh[wv][i] = t;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x <= nv) {
+        const int src = (int)threadIdx.x < nv ? (int)threadIdx.x : NV;
+        double t = 0.0;
+#pragma unroll
+        for (int q = 0; q < kNT / kWave; ++q) t += sh[q][src];
+        part[(int64_t)blockIdx.x * ldp + threadIdx.x] = t;
+    }
+}
+
 // the gated launch of the second Gram-Schmidt pass
 template <class T, int NV>
 __global__ __launch_bounds__(kNT) void k_mdot_gated(const T *__restrict__ V, int64_t ldv, int nv,
@@ -134,13 +179,15 @@ __global__ void k_dgks_gate(const double *__restrict__ wnorm2, const double *__r
     if (threadIdx.x == 0) *gate = (sqrt(*wpnorm2) < eta * sqrt(*wnorm2)) ? 1 : 0;
 }
 
-// v = w / sqrt(*nrm2) (stored as T), z = v / d (Jacobi) or v
+// v = w / sqrt(nrm2) (stored as T), z = v / d (Jacobi) or v, where nrm2 is
+// *nrm2_gated when a gate is given and set, else *nrm2
 template <class T>
-__global__ void k_scale_precond(const T *__restrict__ w, const double *__restrict__ nrm2, T *__restrict__ v,
-                                T *__restrict__ z, const T *__restrict__ d, int64_t n) {
+__global__ void k_scale_precond(const T *__restrict__ w, const double *__restrict__ nrm2,
+                                const double *__restrict__ nrm2_gated, const int *__restrict__ gate,
+                                T *__restrict__ v, T *__restrict__ z, const T *__restrict__ d, int64_t n) {
     int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n) return;
-    double s = sqrt(*nrm2);
+    double s = sqrt((gate && *gate) ? *nrm2_gated : *nrm2);
     double inv = s > 0.0 ? 1.0 / s : 0.0;
     T vr = (T)((double)w[r] * inv);
     v[r] = vr;
@@ -242,6 +289,29 @@ int update_norm(xab_ctx *ctx, const T *V, int64_t ldv, int nv, const double *h, 
     return xab_fail(ctx, XAB_E_UNSUPPORTED, "more than 64 basis vectors");
 }
 
+template <class T>
+int update_mdot(xab_ctx *ctx, const T *V, int64_t ldv, int nv, const double *h, T *w, int64_t n, double *part,
+                int nb) {
+    dim3 g(nb), b(kNT);
+    const int ldp = kPartLd;
+#define XAB_UPM_CASE(NVC)                                                                                      \
+    if (nv <= NVC) {                                                                                           \
+        hipLaunchKernelGGL((k_update_mdot<T, NVC>), g, b, 0, ctx->stream, V, ldv, nv, h, w, n, part, ldp);     \
+        XAB_LAUNCH_CHECK(ctx, "k_update_mdot");                                                                \
+        return XAB_OK;                                                                                         \
+    }
+    XAB_UPM_CASE(8)
+    XAB_UPM_CASE(16)
+    XAB_UPM_CASE(32)
+    XAB_UPM_CASE(64)
+#undef XAB_UPM_CASE
+    return xab_fail(ctx, XAB_E_UNSUPPORTED, "more than 64 basis vectors");
+}
+template int update_mdot<double>(xab_ctx *, const double *, int64_t, int, const double *, double *, int64_t,
+                                 double *, int);
+template int update_mdot<float>(xab_ctx *, const float *, int64_t, int, const double *, float *, int64_t, double *,
+                                int);
+
 template int mdot<double>(xab_ctx *, const double *, int64_t, int, const double *, int64_t, double *, int, const int *);
 template int mdot<float>(xab_ctx *, const float *, int64_t, int, const float *, int64_t, double *, int, const int *);
 template int update_norm<double>(xab_ctx *, const double *, int64_t, int, const double *, double *, int64_t, double *,
@@ -263,15 +333,17 @@ int dgks_gate(xab_ctx *ctx, const double *wn2, const double *wpn2, double eta, i
 }
 
 template <class T>
-int scale_precond(xab_ctx *ctx, const T *w, const double *nrm2, T *v, T *z, const T *d, int64_t n) {
-    hipLaunchKernelGGL((k_scale_precond<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, ctx->stream, w, nrm2, v,
-                       z, d, n);
+int scale_precond(xab_ctx *ctx, const T *w, const double *nrm2, T *v, T *z, const T *d, int64_t n,
+                  const double *nrm2_gated, const int *gate) {
+    hipLaunchKernelGGL((k_scale_precond<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, ctx->stream, w, nrm2,
+                       nrm2_gated, gate, v, z, d, n);
     XAB_LAUNCH_CHECK(ctx, "k_scale_precond");
     return XAB_OK;
 }
 template int scale_precond<double>(xab_ctx *, const double *, const double *, double *, double *, const double *,
-                                   int64_t);
-template int scale_precond<float>(xab_ctx *, const float *, const double *, float *, float *, const float *, int64_t);
+                                   int64_t, const double *, const int *);
+template int scale_precond<float>(xab_ctx *, const float *, const double *, float *, float *, const float *, int64_t,
+                                  const double *, const int *);
 
 template <class TS, class T>
 int scale_from(xab_ctx *ctx, const TS *r, double scale, T *v, T *z, const T *d, int64_t n) {

@@ -75,7 +75,18 @@ struct Cycle {
     int k = 0;               // Arnoldi steps taken
     double est = 0.0;        // recurrence residual estimate |g_{k}|
     bool breakdown = false;  // h_{j+1,j} = 0
+    std::vector<double> samp;  // |g_0| = beta, then |g_{j+1}| after every step
 };
+
+// The MM ratio of eq. (1) over samples v[s-t .. s-1]: max / min.
+double mm_ratio(const std::vector<double> &v, size_t s, size_t t) {
+    double mx = v[s - t], mn = v[s - t];
+    for (size_t z = s - t; z < s; ++z) {
+        mx = std::max(mx, v[z]);
+        mn = std::min(mn, v[z]);
+    }
+    return mx / mn;
+}
 
 // One GMRES(m) cycle on A M^-1 u = rhs where rhs = r (FP64, ||r|| = beta),
 // basis in T.  Stops after m steps, at a lucky breakdown or when the
@@ -95,33 +106,34 @@ int cycle(xab_ctx *ctx, const xab_plan *pl, xab_matrix *A, Work &W, int m, doubl
     if ((s = xab::scale_from<double, T>(ctx, W.r, 1.0 / beta, V, z, d, n)) != XAB_OK) return s;
     std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), g(m + 1, 0.0);
     g[0] = beta;
+    out.samp.assign(1, beta);
     int k = 0;
     out.breakdown = false;
     for (int j = 0; j < m && j < max_steps; ++j) {
         // w = A z (FP64 accumulation in every mode)
         if ((s = xab_spmv_dispatch(ctx, pl, z, tt, w, tt, XAB_F64)) != XAB_OK) return s;
-        // pass 1: h1 = V^T w, ||w||^2 ; w' = w - V h1, ||w'||^2
+        // pass 1: h1 = V^T w, ||w||^2; then one sweep: w' = w - V h1 with
+        // the second pass's h2 = V^T w', ||w'||^2 from the same reads of V
         if ((s = xab::mdot<T>(ctx, V, W.ldv, j + 1, w, n, W.part, nb, nullptr)) != XAB_OK) return s;
         if ((s = xab::reduce_parts(ctx, W.part, nb, xab::kPartLd, j + 2, W.h1, 0, nullptr)) != XAB_OK) return s;
-        if ((s = xab::update_norm<T>(ctx, V, W.ldv, j + 1, W.h1, w, n, W.part, nb, nullptr)) != XAB_OK) return s;
-        if ((s = xab::reduce_parts(ctx, W.part, nb, 1, 1, W.sc, 0, nullptr)) != XAB_OK) return s;
-        // DGKS: second pass only when cancellation was severe
-        if ((s = xab::dgks_gate(ctx, W.h1 + j + 1, W.sc, kEta, W.gate)) != XAB_OK) return s;
-        if ((s = xab::mdot<T>(ctx, V, W.ldv, j + 1, w, n, W.part, nb, W.gate)) != XAB_OK) return s;
-        if ((s = xab::reduce_parts(ctx, W.part, nb, xab::kPartLd, j + 1, W.h2, 0, W.gate)) != XAB_OK) return s;
+        if ((s = xab::update_mdot<T>(ctx, V, W.ldv, j + 1, W.h1, w, n, W.part, nb)) != XAB_OK) return s;
+        if ((s = xab::reduce_parts(ctx, W.part, nb, xab::kPartLd, j + 2, W.h2, 0, nullptr)) != XAB_OK) return s;
+        // DGKS: the second update only when cancellation was severe
+        if ((s = xab::dgks_gate(ctx, W.h1 + j + 1, W.h2 + j + 1, kEta, W.gate)) != XAB_OK) return s;
         if ((s = xab::update_norm<T>(ctx, V, W.ldv, j + 1, W.h2, w, n, W.part, nb, W.gate)) != XAB_OK) return s;
         if ((s = xab::reduce_parts(ctx, W.part, nb, 1, 1, W.sc, 0, W.gate)) != XAB_OK) return s;
         // v_{j+1} = w / ||w||, z = M^-1 v_{j+1}
         T *vn = V + (int64_t)(j + 1) * W.ldv;
-        if ((s = xab::scale_precond<T>(ctx, w, W.sc, vn, z, d, n)) != XAB_OK) return s;
-        // one read-back of h1, h2, ||w||^2 and the DGKS gate (contiguous)
+        if ((s = xab::scale_precond<T>(ctx, w, W.h2 + j + 1, vn, z, d, n, W.sc, W.gate)) != XAB_OK) return s;
+        // one read-back of h1, h2, the norms and the DGKS gate (contiguous)
         XAB_HIP(ctx, hipMemcpyAsync(W.host, W.h1, W.small_bytes, hipMemcpyDeviceToHost, ctx->stream));
         XAB_HIP(ctx, hipStreamSynchronize(ctx->stream));
         const double *hh = W.host;
         int gate = 0;
         memcpy(&gate, (const char *)W.gate - (const char *)W.h1 + (const char *)W.host, sizeof(int));
-        for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hh[i] + (gate ? hh[(m + 2) + i] : 0.0);
-        const double hn = std::sqrt(hh[2 * (m + 2)]);
+        const size_t oh2 = (size_t)(W.h2 - W.h1), osc = (size_t)(W.sc - W.h1);  // layout of the small region
+        for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hh[i] + (gate ? hh[oh2 + i] : 0.0);
+        const double hn = std::sqrt(gate ? hh[osc] : hh[oh2 + j + 1]);
         H[(size_t)(j + 1) * m + j] = hn;
         // earlier rotations on column j, then a new one
         for (int i = 0; i < j; ++i) {
@@ -138,6 +150,7 @@ int cycle(xab_ctx *ctx, const xab_plan *pl, xab_matrix *A, Work &W, int m, doubl
         g[j + 1] = -sn[j] * g[j];
         g[j] = cs[j] * g[j];
         k = j + 1;
+        out.samp.push_back(std::fabs(g[j + 1]));
         if (hn == 0.0) {
             out.breakdown = true;
             break;
@@ -181,8 +194,13 @@ extern "C" int xab_gmres(xab_ctx *ctx, const xab_plan *pl, const double *d_b, do
     if (!ctx || !pl || !d_b || !d_x || !opts) return XAB_E_NULL;
     xab_matrix *A = const_cast<xab_matrix *>(pl->A);  // caches the Jacobi diagonal
     if (A->n != A->ncols) return xab_fail(ctx, XAB_E_SHAPE, "GMRES needs a square matrix");
-    const int m = opts->m;
-    if (m < 1 || m > 63) return xab_fail(ctx, XAB_E_SHAPE, "restart length must be in [1, 63]");
+    const int m0 = opts->m;
+    if (m0 < 1 || m0 > 63) return xab_fail(ctx, XAB_E_SHAPE, "restart length must be in [1, 63]");
+    const bool tune = opts->restart_step > 0;
+    if (tune && (opts->m_max < m0 || opts->m_max > 63))
+        return xab_fail(ctx, XAB_E_SHAPE, "m_max must be in [m, 63]");
+    const int mcap = tune ? opts->m_max : m0;  // basis capacity
+    int m = m0;                                // restart length of the next cycle
     if (opts->mode != XAB_MODE_FP64 && opts->mode != XAB_MODE_IR) return xab_fail(ctx, XAB_E_SHAPE, "mode");
     if (!A->has64) return xab_fail(ctx, XAB_E_DTYPE, "GMRES needs FP64 values for the residual");
     if (opts->mode == XAB_MODE_IR && !A->has32) return xab_fail(ctx, XAB_E_DTYPE, "IR mode needs FP32 values");
@@ -214,7 +232,7 @@ extern "C" int xab_gmres(xab_ctx *ctx, const xab_plan *pl, const double *d_b, do
     } restore{A, d64, d32};
     Work W;
     const bool ir = opts->mode == XAB_MODE_IR;
-    if ((s = alloc_work(ctx, W, n, m, ir ? sizeof(float) : sizeof(double))) != XAB_OK) return s;
+    if ((s = alloc_work(ctx, W, n, mcap, ir ? sizeof(float) : sizeof(double))) != XAB_OK) return s;
     auto t0 = std::chrono::steady_clock::now();
     auto elapsed = [&]() { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); };
     // ||b||
@@ -254,7 +272,12 @@ extern "C" int xab_gmres(xab_ctx *ctx, const xab_plan *pl, const double *d_b, do
         if (s != XAB_OK) return s;
         inf.iters += c.k;
         inf.restarts++;
+        inf.m_final = m;
         if (c.k == 0) break;
+        // restart-length judgment on this cycle's residual samples (relative
+        // to ||b||; the ratio is scale-free)
+        if (tune && m < opts->m_max && mm_ratio(c.samp, c.samp.size(), c.samp.size()) < opts->mm_ratio)
+            m = std::min(m + opts->restart_step, opts->m_max);
     }
     XAB_HIP(ctx, hipStreamSynchronize(ctx->stream));
     inf.true_relres = relres;

@@ -222,3 +222,39 @@ def test_batch_rejects_cross_system_columns(ctx):
     with pytest.raises(xab.XabError) as e:
         ctx.batch(B)
     assert e.value.status == -4
+
+
+# ------------------------------------------------- restart-length tuning
+def test_gmres_restart_tuning_vs_oracle(ctx):
+    """GMRES(4) on the 64x64 Laplacian with the MM-ratio rule (threshold 10,
+    step 4, m_max 40): the final restart length equals the oracle's, the
+    iteration count is within 20 % of it and the true residual meets 1e-10."""
+    A = gen.laplacian2d(64)
+    b = np.ones(A.n)
+    ref = oracle.gmres_at(A, b, 4, 40, 4, 10.0, tol=1e-10, maxiter=3000)
+    assert ref["status"] == 0
+    M = ctx.matrix_from_csr(A)
+    P = ctx.plan_class(M, 5)
+    x, inf, st = ctx.gmres(P, dev(b), m=4, tol=1e-10, maxiter=3000, precond=xab.PRECOND_NONE, restart_step=4,
+                           m_max=40, mm_ratio=10.0)
+    assert st == 0
+    assert inf["m_final"] == ref["m_hist"][-1]
+    assert abs(inf["iters"] - ref["iters"]) <= 0.2 * ref["iters"]
+    xs = x.cpu().numpy()
+    assert np.linalg.norm(b - oracle.spmv(A, xs)[0]) / np.linalg.norm(b) <= 1e-10
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_gmres_restart_tuning_extremes(ctx, mode):
+    """Threshold infinity grows m by the step after every cycle (capped);
+    threshold 0 never does."""
+    A = gen.laplacian2d(20)
+    b = np.ones(A.n)
+    M = ctx.matrix_from_csr(A, with_f32=True)
+    P = ctx.plan_class(M, 5)
+    for thr in (math.inf, 0.0):
+        x, inf, st = ctx.gmres(P, dev(b), m=3, tol=1e-10, maxiter=3000, mode=mode, precond=xab.PRECOND_NONE,
+                               restart_step=5, m_max=17, mm_ratio=thr)
+        assert st == 0
+        want = min(3 + 5 * (inf["restarts"] - 1), 17) if thr == math.inf else 3
+        assert inf["m_final"] == want

@@ -116,3 +116,61 @@ def test_gmres_banded_batch_system():
         A = gen.batch_system(k, int(n[k]), int(kind[k]), int(h[k]))
         r = oracle.gmres(A, np.ones(A.n), tol=1e-10, precond=1)
         assert r["status"] == 0 and r["relres"] <= 1e-10
+
+
+# ------------------------------------------------- restart-length tuning (eq. (1))
+def test_mm_ratio_closed_forms():
+    """R(s, t) of eq. (1): geometric decay q^z gives q^-(t-1); a constant
+    sequence gives 1; the window is z = s-t+1 .. s."""
+    q = 0.5
+    r = q ** np.arange(1, 21)
+    for s, t in [(20, 20), (10, 4), (5, 1), (7, 7)]:
+        assert math.isclose(oracle.mm_ratio(r, s, t), q ** -(t - 1), rel_tol=1e-15)
+    assert oracle.mm_ratio(np.full(9, 3.7), 9, 9) == 1.0
+    r = np.array([5.0, 1.0, 4.0, 2.0, 8.0])
+    assert oracle.mm_ratio(r, 4, 3) == 4.0      # [1, 4, 2]
+    assert oracle.mm_ratio(r, 5, 2) == 4.0      # [2, 8]
+    assert oracle.mm_ratio(r, 5, 5) == 8.0      # [5, 1, 4, 2, 8]
+    rng = np.random.default_rng(3)
+    for _ in range(50):
+        v = rng.uniform(0.1, 10.0, 30)
+        s = int(rng.integers(1, 31))
+        t = int(rng.integers(1, s + 1))
+        w = v[s - t:s]
+        assert oracle.mm_ratio(v, s, t) == w.max() / w.min()
+
+
+def test_gmres_at_without_tuning_is_plain_gmres():
+    A = gen.random_uniform_rows(3000, 7, 5, 30)
+    b = np.ones(A.n)
+    a = oracle.gmres(A, b, m=8, tol=1e-10, maxiter=2000)
+    t = oracle.gmres_at(A, b, 8, 8, 0, 10.0, tol=1e-10, maxiter=2000)
+    assert np.array_equal(a["x"], t["x"]) and a["iters"] == t["iters"]
+    assert t["m_hist"] == [8] * t["cycles"]
+
+
+@pytest.mark.parametrize("m0,step,mmax", [(4, 4, 40), (3, 5, 17), (10, 10, 63)])
+def test_gmres_at_rule_extremes(m0, step, mmax):
+    """Threshold 0: never stagnant, m stays; threshold infinity: every cycle
+    is stagnant, so m grows by `step` per cycle up to m_max."""
+    A = gen.laplacian2d(40)
+    b = np.ones(A.n)
+    never = oracle.gmres_at(A, b, m0, mmax, step, 0.0, tol=1e-10, maxiter=400)
+    assert never["m_hist"] == [m0] * never["cycles"]
+    always = oracle.gmres_at(A, b, m0, mmax, step, math.inf, tol=1e-10, maxiter=400)
+    want = [min(m0 + step * c, mmax) for c in range(always["cycles"])]
+    assert always["m_hist"] == want
+
+
+def test_gmres_at_cures_stagnation():
+    """GMRES(4) on the 64x64 Laplacian stalls within 3000 steps; growing m
+    when a cycle's MM ratio is below 10 converges, and reaches the true
+    residual target."""
+    A = gen.laplacian2d(64)
+    b = np.ones(A.n)
+    fixed = oracle.gmres(A, b, m=4, tol=1e-10, maxiter=3000)
+    tuned = oracle.gmres_at(A, b, 4, 40, 4, 10.0, tol=1e-10, maxiter=3000)
+    assert fixed["status"] == 1 and tuned["status"] == 0
+    assert np.linalg.norm(b - oracle.spmv(A, tuned["x"])[0]) / np.linalg.norm(b) <= 1e-10
+    mh = tuned["m_hist"]
+    assert mh[0] == 4 and all(y - x in (0, 4) for x, y in zip(mh, mh[1:])) and max(mh) <= 40
