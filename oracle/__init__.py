@@ -45,7 +45,7 @@ def lib():
             "orc_mlp_train": (None, [ci, ci, ci, P, i64, P, P, P, P, ci, ci, d, P]),
             "orc_gmres": (ci, [i64, P, P, P, P, P, ci, d, i64, ci, P, P, P, P]),
             "orc_mm_ratio": (d, [P, i64, i64]),
-            "orc_gmres_at": (ci, [i64, P, P, P, P, P, ci, ci, ci, d, d, i64, ci, P, P, P, P, P]),
+            "orc_gmres_at": (ci, [i64, P, P, P, P, P, ci, ci, ci, d, d, i64, ci, P, P, P, P, P, ci, P]),
             "orc_bicgstab": (ci, [i64, P, P, P, P, P, d, i64, ci, P, P, P]),
         }
         for name, (res, args) in sig.items():
@@ -238,19 +238,31 @@ def mm_ratio(r, s, t):
     return float(lib().orc_mm_ratio(_p(r), s, t))
 
 
-def gmres_at(A, b, m0, m_max, step, ratio, x0=None, tol=1e-10, maxiter=10000, precond=0):
-    """GMRES with the restart length tuned by the MM ratio after every cycle;
-    returns the solve summary plus the m of every cycle."""
+ORTHO_DGKS, ORTHO_CGS, ORTHO_MGS, ORTHO_BCGS, ORTHO_POLICY = 0, 1, 2, 3, 4
+
+
+def gmres_at(A, b, m0, m_max, step, ratio, x0=None, tol=1e-10, maxiter=10000, precond=0, ortho=ORTHO_MGS,
+             history=False):
+    """GMRES with the restart length tuned by the MM ratio after every cycle
+    (step > 0) and a choice of orthogonalisation; returns the solve summary,
+    the m of every cycle and [faults, final ortho]."""
     rp, ci, v = _csr(A)
     b = np.ascontiguousarray(b, dtype=np.float64)
     x = np.zeros(A.n) if x0 is None else np.array(x0, dtype=np.float64)
     info = np.zeros(3, dtype=np.int64)
     dinfo = np.zeros(1, dtype=np.float64)
     mh = np.zeros(maxiter + 1, dtype=np.int32)
+    pol = np.zeros(2, dtype=np.int32)
+    hist = np.full(maxiter + 1, np.nan) if history else None
+    aerr = np.zeros(1, dtype=np.float64) if history else None
     lib().orc_gmres_at(A.n, _p(rp), _p(ci), _p(v), _p(b), _p(x), m0, m_max, step, ratio, tol, maxiter, precond,
-                       _p(info), _p(dinfo), None, None, _p(mh))
+                       _p(info), _p(dinfo), _p(hist), _p(aerr), _p(mh), ortho, _p(pol))
     out = dict(x=x, iters=int(info[0]), cycles=int(info[1]), status=int(info[2]), relres=float(dinfo[0]))
     out["m_hist"] = mh[: out["cycles"]].tolist()
+    out["faults"], out["ortho"] = int(pol[0]), int(pol[1])
+    if history:
+        out["hist"] = hist[: out["iters"] + 1]
+        out["arnoldi_err"] = float(aerr[0])
     return out
 
 

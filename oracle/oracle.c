@@ -559,10 +559,51 @@ double orc_mm_ratio(const double *r, int64_t s, int64_t t) {
  * steps) is formed over the whole cycle, and when it is below `ratio` (the
  * residual stagnated) the next cycle's m grows by `step`, up to m_max.
  * m_hist (may be NULL) receives the m of every cycle. */
+/* Orthogonalise w against the columns V_0 .. V_j (length n) by one of the
+ * section 3.2.2 methods; h[0..j] receives the projection coefficients and
+ * the norm of w afterwards is returned.
+ *   ORC_MGS   one column at a time, each dot with the current w
+ *   ORC_CGS   all dots with the incoming w, then one combined update
+ *   ORC_DGKS  CGS, then CGS again when the norm fell below 1/sqrt(2) of
+ *             the incoming norm (coefficients of both passes summed)
+ *   ORC_BCGS  blocks of 4 columns: CGS inside a block, blocks in order */
+enum { ORC_DGKS = 0, ORC_CGS = 1, ORC_MGS = 2, ORC_BCGS = 3, ORC_POLICY = 4 };
+
+static void cgs_block(int64_t n, const double *V, int i0, int i1, double *w, double *h) {
+    for (int i = i0; i < i1; ++i) h[i] = dot(n, w, V + (int64_t)i * n);
+    for (int i = i0; i < i1; ++i)
+        for (int64_t q = 0; q < n; ++q) w[q] -= h[i] * V[(int64_t)i * n + q];
+}
+
+static double orth_step(int ortho, int64_t n, const double *V, int j, double *w, double *h, double *h2) {
+    if (ortho == ORC_MGS) {
+        for (int i = 0; i <= j; ++i) cgs_block(n, V, i, i + 1, w, h);
+    } else if (ortho == ORC_CGS) {
+        cgs_block(n, V, 0, j + 1, w, h);
+    } else if (ortho == ORC_BCGS) {
+        for (int i0 = 0; i0 <= j; i0 += 4) cgs_block(n, V, i0, i0 + 4 < j + 1 ? i0 + 4 : j + 1, w, h);
+    } else { /* DGKS */
+        double nw = sqrt(dot(n, w, w));
+        cgs_block(n, V, 0, j + 1, w, h);
+        if (sqrt(dot(n, w, w)) < nw / sqrt(2.0)) {
+            cgs_block(n, V, 0, j + 1, w, h2);
+            for (int i = 0; i <= j; ++i) h[i] += h2[i];
+        }
+    }
+    return sqrt(dot(n, w, w));
+}
+
 int orc_gmres_at(int64_t n, const int32_t *rowptr, const int32_t *colind, const double *val,
                  const double *b, double *x, int m0, int m_max, int step, double ratio, double tol,
                  int64_t maxiter, int precond, int64_t *info, double *dinfo, double *resid_hist,
-                 double *arnoldi_err, int32_t *m_hist) {
+                 double *arnoldi_err, int32_t *m_hist, int ortho_in, int32_t *policy_out) {
+    /* accuracy policy (section 3.3.2): MGS when the requirement is 1e-10 or
+     * tighter, else BCGS; after a fault convergence (the recurrence met the
+     * threshold, the true residual did not) DGKS and a threshold narrowed
+     * tenfold for the recurrence test */
+    int ortho = ortho_in == ORC_POLICY ? (tol <= 1e-10 ? ORC_MGS : ORC_BCGS) : ortho_in;
+    double tol_rec = tol;
+    int faults = 0, stopped_by_rec = 0;
     const int m = (step > 0 && m_max > m0) ? m_max : m0; /* capacity: rows of H, columns of V */
     int cm = m0;                                          /* restart length of the current cycle */
     double *samp = malloc(sizeof(double) * (m + 1));
@@ -573,6 +614,7 @@ int orc_gmres_at(int64_t n, const int32_t *rowptr, const int32_t *colind, const 
     double *g = malloc(sizeof(double) * (m + 1)), *yv = malloc(sizeof(double) * m);
     double *w = malloc(sizeof(double) * n), *z = malloc(sizeof(double) * n), *r = malloc(sizeof(double) * n);
     double *dg = malloc(sizeof(double) * n);
+    double *hc = malloc(sizeof(double) * (m + 1)), *hc2 = malloc(sizeof(double) * (m + 1));
     if (precond) diag_of(n, rowptr, colind, val, dg);
     double bn = sqrt(dot(n, b, b));
     if (bn == 0.0) bn = 1.0;
@@ -587,6 +629,13 @@ int orc_gmres_at(int64_t n, const int32_t *rowptr, const int32_t *colind, const 
         relres = beta / bn;
         if (resid_hist && it == 0) resid_hist[0] = relres;
         if (relres <= tol) { status = 0; break; }
+        if (stopped_by_rec && ortho_in == ORC_POLICY) {
+            /* fault convergence */
+            faults++;
+            ortho = ORC_DGKS;
+            tol_rec *= 0.1;
+        }
+        stopped_by_rec = 0;
         if (it >= maxiter) { status = 1; break; }
         if (m_hist) m_hist[restarts] = cm;
         restarts++; /* cycles started */
@@ -600,12 +649,8 @@ int orc_gmres_at(int64_t n, const int32_t *rowptr, const int32_t *colind, const 
             if (precond) for (int64_t i = 0; i < n; ++i) z[i] = vj[i] / dg[i];
             else memcpy(z, vj, sizeof(double) * n);
             spmv_plain(n, rowptr, colind, val, z, w);
-            for (int i = 0; i <= j; ++i) {
-                double h = dot(n, w, V + (int64_t)i * n);
-                H[i * m + j] = h;
-                for (int64_t q = 0; q < n; ++q) w[q] -= h * V[(int64_t)i * n + q];
-            }
-            double hn = sqrt(dot(n, w, w));
+            double hn = orth_step(ortho, n, V, j, w, hc, hc2);
+            for (int i = 0; i <= j; ++i) H[i * m + j] = hc[i];
             H[(j + 1) * m + j] = hn;
             for (int i = 0; i <= j + 1; ++i) H0[i * m + j] = H[i * m + j];
             if (hn != 0.0)
@@ -628,7 +673,8 @@ int orc_gmres_at(int64_t n, const int32_t *rowptr, const int32_t *colind, const 
             k = j + 1;
             if (resid_hist) resid_hist[it] = fabs(g[j + 1]) / bn;
             samp[j + 1] = fabs(g[j + 1]) / bn;
-            if (hn == 0.0 || fabs(g[j + 1]) / bn <= tol) break;
+            if (hn == 0.0) break;
+            if (fabs(g[j + 1]) / bn <= tol_rec) { stopped_by_rec = 1; break; }
         }
         /* restart-length judgment on this cycle's samples */
         if (step > 0 && cm < m_max && k > 0 && orc_mm_ratio(samp, k + 1, k + 1) < ratio)
@@ -666,7 +712,8 @@ int orc_gmres_at(int64_t n, const int32_t *rowptr, const int32_t *colind, const 
     if (dinfo) dinfo[0] = relres;
     if (arnoldi_err) *arnoldi_err = aerr;
     free(V); free(H); free(H0); free(cs); free(sn); free(g); free(yv); free(w); free(z); free(r); free(dg);
-    free(samp);
+    free(samp); free(hc); free(hc2);
+    if (policy_out) { policy_out[0] = faults; policy_out[1] = ortho; }
     return status;
 }
 
@@ -674,7 +721,7 @@ int orc_gmres(int64_t n, const int32_t *rowptr, const int32_t *colind, const dou
               const double *b, double *x, int m, double tol, int64_t maxiter, int precond,
               int64_t *info, double *dinfo, double *resid_hist, double *arnoldi_err) {
     return orc_gmres_at(n, rowptr, colind, val, b, x, m, m, 0, 0.0, tol, maxiter, precond, info, dinfo,
-                        resid_hist, arnoldi_err, NULL);
+                        resid_hist, arnoldi_err, NULL, ORC_MGS, NULL);
 }
 
 /* BiCGStab (van der Vorst 1992), right preconditioned by M = diag(A) when

@@ -90,10 +90,12 @@ int orc_gmres(int64_t n, const int32_t *rowptr, const int32_t *colind, const dou
               const double *b, double *x, int m, double tol, int64_t maxiter, int precond,
               int64_t *info, double *dinfo, double *resid_hist, double *arnoldi_err);
 double orc_mm_ratio(const double *r, int64_t s, int64_t t);
+/* ortho: 0 DGKS, 1 CGS, 2 MGS, 3 BCGS (block 4), 4 the accuracy policy;
+ * policy_out (may be NULL) receives [faults, final ortho]. */
 int orc_gmres_at(int64_t n, const int32_t *rowptr, const int32_t *colind, const double *val,
                  const double *b, double *x, int m0, int m_max, int step, double ratio, double tol,
                  int64_t maxiter, int precond, int64_t *info, double *dinfo, double *resid_hist,
-                 double *arnoldi_err, int32_t *m_hist);
+                 double *arnoldi_err, int32_t *m_hist, int ortho, int32_t *policy_out);
 int orc_bicgstab(int64_t n, const int32_t *rowptr, const int32_t *colind, const double *val,
                  const double *b, double *x, double tol, int64_t maxiter, int precond, int64_t *info,
                  double *dinfo, double *resid_hist);
