@@ -240,6 +240,21 @@ def gmres_pair(ctx, xab, torch, plan, n, reps=3):
     return res
 
 
+def ortho_menu_leg(ctx, xab, torch, plan, n):
+    """FP64 GMRES(30) with Jacobi to 1e-10 under each orthogonalisation and
+    the accuracy policy; median of 3 each."""
+    b = torch.ones(n, dtype=torch.float64, device="cuda")
+    res = {}
+    for name, o in (("dgks", xab.ORTHO_DGKS), ("cgs", xab.ORTHO_CGS), ("mgs", xab.ORTHO_MGS),
+                    ("bcgs", xab.ORTHO_BCGS), ("policy", xab.ORTHO_POLICY)):
+        runs = sorted((ctx.gmres(plan, b, m=30, tol=1e-10, precond=xab.PRECOND_JACOBI, ortho=o)[1] for _ in range(3)),
+                      key=lambda r: r["seconds"])
+        med = runs[1]
+        res[name] = {"s": round(med["seconds"], 5), "iters": med["iters"], "relres": med["true_relres"],
+                     "status": med["status"], "faults": med["faults"]}
+    return res
+
+
 def restart_tuning_leg(ctx, xab, torch, plan, n):
     """Restart-length tuning by the MM ratio: FP64 GMRES with Jacobi from
     m = 5, fixed vs grown by 5 (up to 30) after each cycle whose MM ratio is
@@ -422,6 +437,7 @@ def main():
     if not args.no_gmres:
         log("GMRES(30) FP64 vs mixed precision (power-law)")
         gm = gmres_pair(ctx, xab, torch, plan, A.n)
+        gm["ortho_menu"] = ortho_menu_leg(ctx, xab, torch, plan, A.n)
 
     c3 = None
     if not args.no_c3:

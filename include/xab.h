@@ -254,6 +254,20 @@ int xab_selector_loss_grad(xab_ctx *ctx, const float *d_feat, const float *d_y, 
 /* ------------------------------------------------------------------ Krylov */
 typedef enum { XAB_MODE_FP64 = 0, XAB_MODE_IR = 1 } xab_krylov_mode;
 typedef enum { XAB_PRECOND_NONE = 0, XAB_PRECOND_JACOBI = 1 } xab_precond;
+/* Orthogonalisation of the Arnoldi step (section 3.2.2): DGKS (classical
+ * Gram-Schmidt, repeated when the norm fell below 1/sqrt(2) of the
+ * incoming one), CGS (once), MGS (column by column), BCGS (blocks of 4
+ * columns: CGS inside a block, blocks in order); POLICY is the accuracy
+ * policy of section 3.3.2: MGS for tol <= 1e-10, else BCGS, and after a
+ * fault convergence (a cycle ended on its recurrence residual but the true
+ * residual missed tol) DGKS with a tenfold narrower recurrence threshold. */
+typedef enum {
+    XAB_ORTHO_DGKS = 0,
+    XAB_ORTHO_CGS = 1,
+    XAB_ORTHO_MGS = 2,
+    XAB_ORTHO_BCGS = 3,
+    XAB_ORTHO_POLICY = 4
+} xab_ortho;
 
 typedef struct {
     int32_t m;            /* restart length (30) */
@@ -269,6 +283,7 @@ typedef struct {
                              cycle whose residual samples have an MM ratio below mm_ratio */
     int32_t m_max;        /* GMRES restart-length tuning: upper bound on m (<= 63) */
     double mm_ratio;      /* GMRES restart-length tuning: stagnation threshold on the MM ratio */
+    int32_t ortho;        /* GMRES: xab_ortho (0 = DGKS) */
 } xab_krylov_opts;
 
 typedef struct {
@@ -279,6 +294,8 @@ typedef struct {
     double seconds;       /* wall time of the call */
     int32_t status;       /* same as the return value */
     int32_t m_final;      /* GMRES: restart length of the last cycle */
+    int32_t faults;       /* GMRES, ortho = POLICY: fault convergences seen */
+    int32_t ortho;        /* GMRES: orthogonalisation of the last cycle */
 } xab_krylov_info;
 
 /* Restarted GMRES(m) (section 2.2) on A x = b.  d_x holds x0 on entry and

@@ -25,6 +25,7 @@ NFEAT = 12
 MLP_NPARAMS = 64 * 12 + 64 + 64 * 64 + 64 + NCLASSES * 64 + NCLASSES
 MODE_FP64, MODE_IR = 0, 1
 PRECOND_NONE, PRECOND_JACOBI = 0, 1
+ORTHO_DGKS, ORTHO_CGS, ORTHO_MGS, ORTHO_BCGS, ORTHO_POLICY = 0, 1, 2, 3, 4
 
 STATUS = {0: "ok", -1: "null", -2: "shape", -3: "dtype", -4: "struct", -5: "alias", -6: "unsupported",
           -7: "nomem", -8: "device", -9: "align", 1: "not_converged", 2: "breakdown", 3: "time_limit"}
@@ -64,13 +65,14 @@ class KrylovOpts(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int32), ("tol", ctypes.c_double), ("maxiter", ctypes.c_int64),
                 ("max_time_s", ctypes.c_double), ("mode", ctypes.c_int32), ("precond", ctypes.c_int32),
                 ("inner_tol", ctypes.c_double), ("graph", ctypes.c_int32), ("check_every", ctypes.c_int32),
-                ("restart_step", ctypes.c_int32), ("m_max", ctypes.c_int32), ("mm_ratio", ctypes.c_double)]
+                ("restart_step", ctypes.c_int32), ("m_max", ctypes.c_int32), ("mm_ratio", ctypes.c_double),
+                ("ortho", ctypes.c_int32)]
 
 
 class KrylovInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int64), ("restarts", ctypes.c_int64), ("refinements", ctypes.c_int64),
                 ("true_relres", ctypes.c_double), ("seconds", ctypes.c_double), ("status", ctypes.c_int32),
-                ("m_final", ctypes.c_int32)]
+                ("m_final", ctypes.c_int32), ("faults", ctypes.c_int32), ("ortho", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -328,13 +330,13 @@ class Context:
 
     # ----------------------------------------------------------- Krylov
     def gmres(self, plan, b, x=None, m=30, tol=1e-10, maxiter=100000, mode=MODE_FP64, precond=PRECOND_JACOBI,
-              inner_tol=1e-6, max_time_s=0.0, restart_step=0, m_max=0, mm_ratio=0.0):
+              inner_tol=1e-6, max_time_s=0.0, restart_step=0, m_max=0, mm_ratio=0.0, ortho=0):
         torch = _torch()
         if x is None:
             x = torch.zeros_like(b)
         opts = KrylovOpts(m=m, tol=tol, maxiter=maxiter, max_time_s=max_time_s, mode=mode, precond=precond,
                           inner_tol=inner_tol, graph=0, check_every=0, restart_step=restart_step,
-                          m_max=m_max if m_max else m, mm_ratio=mm_ratio)
+                          m_max=m_max if m_max else m, mm_ratio=mm_ratio, ortho=ortho)
         info = KrylovInfo()
         s = self._check(lib().xab_gmres(self.h, plan.h, _ptr(b), _ptr(x), ctypes.byref(opts), ctypes.byref(info)),
                         "xab_gmres")
@@ -349,7 +351,7 @@ class Context:
         if x is None:
             x = torch.zeros_like(b)
         opts = KrylovOpts(m=0, tol=tol, maxiter=maxiter, max_time_s=0.0, mode=0, precond=precond, inner_tol=0.0,
-                          graph=int(graph), check_every=check_every, restart_step=0, m_max=0, mm_ratio=0.0)
+                          graph=int(graph), check_every=check_every, restart_step=0, m_max=0, mm_ratio=0.0, ortho=0)
         infos = (KrylovInfo * batch.nsys)()
         allinfo = KrylovInfo()
         s = self._check(lib().xab_bicgstab(self.h, batch.h, _ptr(b), _ptr(x), ctypes.byref(opts),

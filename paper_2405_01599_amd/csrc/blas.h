@@ -13,11 +13,12 @@ int mdot(xab_ctx *ctx, const T *V, int64_t ldv, int nv, const T *w, int64_t n, d
 template <class T>
 int update_norm(xab_ctx *ctx, const T *V, int64_t ldv, int nv, const double *h, T *w, int64_t n, double *part,
                 int nb, const int *gate);
-// w -= V h and, in the same sweep, partials of V^T w and ||w||^2 of the new w
-// (the first Gram-Schmidt pass's update fused with the second pass's dots)
+// w -= Vu h (nvu columns) and, in the same sweep, partials of Vd^T w (nvd
+// columns, 0 for none) and ||w||^2 of the new w, in kPartLd slots per
+// workgroup (the dots first, the norm at index nvd)
 template <class T>
-int update_mdot(xab_ctx *ctx, const T *V, int64_t ldv, int nv, const double *h, T *w, int64_t n, double *part,
-                int nb);
+int update_mdot(xab_ctx *ctx, const T *Vu, int nvu, const double *h, const T *Vd, int nvd, int64_t ldv, T *w,
+                int64_t n, double *part, int nb);
 int reduce_parts(xab_ctx *ctx, const double *part, int nb, int ldp, int m, double *out, int add, const int *gate);
 int dgks_gate(xab_ctx *ctx, const double *wn2, const double *wpn2, double eta, int *gate);
 // v = w / ||w||, z = M^-1 v; the squared norm is *nrm2_gated when gate is

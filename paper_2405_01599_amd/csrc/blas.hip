@@ -95,34 +95,44 @@ __global__ __launch_bounds__(kNT) void k_update_norm(const T *__restrict__ V, in
     if (threadIdx.x == 0) part[blockIdx.x] = acc;
 }
 
-// w' = w - sum_i h[i] V_i (i < nv), stored, and in the same sweep the
-// second Gram-Schmidt pass's dots: part[b * ldp + i] = sum V_i[r] w'[r],
-// part[b * ldp + nv] = sum w'[r]^2 (w' as stored).  One read of V serves
-// the first pass's update and the second pass's projection.
+// w' = w - sum_{i < nvu} h[i] Vu_i, stored, and in the same sweep the dots
+// of the next projection: part[b * ldp + i] = sum Vd_i[r] w'[r] (i < nvd),
+// part[b * ldp + nvd] = sum w'[r]^2 (w' as stored).  One read of the basis
+// serves an update and the following projection: DGKS passes Vd = Vu (the
+// second pass's dots), MGS one column and the next, BCGS one block of four
+// and the next.
 template <class T, int NV>
-__global__ __launch_bounds__(kNT) void k_update_mdot(const T *__restrict__ V, int64_t ldv, int nv,
-                                                     const double *__restrict__ h, T *__restrict__ w, int64_t n,
-                                                     double *__restrict__ part, int ldp) {
+__global__ __launch_bounds__(kNT) void k_update_mdot(const T *__restrict__ Vu, int nvu, const double *__restrict__ h,
+                                                     const T *__restrict__ Vd, int nvd, int64_t ldv,
+                                                     T *__restrict__ w, int64_t n, double *__restrict__ part,
+                                                     int ldp) {
     __shared__ double sh[kNT / kWave][NV + 1];
     double hh[NV], acc[NV + 1];
 #pragma unroll
-    for (int i = 0; i < NV; ++i) hh[i] = i < nv ? h[i] : 0.0;
+    for (int i = 0; i < NV; ++i) hh[i] = i < nvu ? h[i] : 0.0;
 #pragma unroll
     for (int i = 0; i <= NV; ++i) acc[i] = 0.0;
+    const bool same = Vd == Vu && nvd == nvu;
     for (int64_t r = (int64_t)blockIdx.x * kNT + threadIdx.x; r < n; r += (int64_t)gridDim.x * kNT) {
         double vr[NV];
         double a = (double)w[r];
 #pragma unroll
         for (int i = 0; i < NV; ++i) {
-            vr[i] = i < nv ? (double)V[i * ldv + r] : 0.0;
+            vr[i] = i < nvu ? (double)Vu[i * ldv + r] : 0.0;
             a -= hh[i] * vr[i];
         }
         const T at = (T)a;
         w[r] = at;
         const double ad = (double)at;
         acc[NV] += ad * ad;
+        if (same) {
 #pragma unroll
-        for (int i = 0; i < NV; ++i) acc[i] += vr[i] * ad;
+            for (int i = 0; i < NV; ++i) acc[i] += vr[i] * ad;
+        } else {
+#pragma unroll
+            for (int i = 0; i < NV; ++i)
+                if (i < nvd) acc[i] += (double)Vd[i * ldv + r] * ad;
+        }
     }
     const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
 #pragma unroll
@@ -131,8 +141,8 @@ __global__ __launch_bounds__(kNT) void k_update_mdot(const T *__restrict__ V, in
         if (lane == kWave - 1) sh[wv][i] = t;
     }
     __syncthreads();
-    if ((int)threadIdx.x <= nv) {
-        const int src = (int)threadIdx.x < nv ? (int)threadIdx.x : NV;
+    if ((int)threadIdx.x <= nvd) {
+        const int src = (int)threadIdx.x < nvd ? (int)threadIdx.x : NV;
         double t = 0.0;
 #pragma unroll
         for (int q = 0; q < kNT / kWave; ++q) t += sh[q][src];
@@ -290,16 +300,18 @@ int update_norm(xab_ctx *ctx, const T *V, int64_t ldv, int nv, const double *h, 
 }
 
 template <class T>
-int update_mdot(xab_ctx *ctx, const T *V, int64_t ldv, int nv, const double *h, T *w, int64_t n, double *part,
-                int nb) {
+int update_mdot(xab_ctx *ctx, const T *Vu, int nvu, const double *h, const T *Vd, int nvd, int64_t ldv, T *w,
+                int64_t n, double *part, int nb) {
     dim3 g(nb), b(kNT);
     const int ldp = kPartLd;
-#define XAB_UPM_CASE(NVC)                                                                                      \
-    if (nv <= NVC) {                                                                                           \
-        hipLaunchKernelGGL((k_update_mdot<T, NVC>), g, b, 0, ctx->stream, V, ldv, nv, h, w, n, part, ldp);     \
-        XAB_LAUNCH_CHECK(ctx, "k_update_mdot");                                                                \
-        return XAB_OK;                                                                                         \
+    const int nv = nvu > nvd ? nvu : nvd;
+#define XAB_UPM_CASE(NVC)                                                                                         \
+    if (nv <= NVC) {                                                                                              \
+        hipLaunchKernelGGL((k_update_mdot<T, NVC>), g, b, 0, ctx->stream, Vu, nvu, h, Vd, nvd, ldv, w, n, part, ldp); \
+        XAB_LAUNCH_CHECK(ctx, "k_update_mdot");                                                                   \
+        return XAB_OK;                                                                                            \
     }
+    XAB_UPM_CASE(4)
     XAB_UPM_CASE(8)
     XAB_UPM_CASE(16)
     XAB_UPM_CASE(32)
@@ -307,10 +319,10 @@ int update_mdot(xab_ctx *ctx, const T *V, int64_t ldv, int nv, const double *h, 
 #undef XAB_UPM_CASE
     return xab_fail(ctx, XAB_E_UNSUPPORTED, "more than 64 basis vectors");
 }
-template int update_mdot<double>(xab_ctx *, const double *, int64_t, int, const double *, double *, int64_t,
-                                 double *, int);
-template int update_mdot<float>(xab_ctx *, const float *, int64_t, int, const double *, float *, int64_t, double *,
-                                int);
+template int update_mdot<double>(xab_ctx *, const double *, int, const double *, const double *, int, int64_t,
+                                 double *, int64_t, double *, int);
+template int update_mdot<float>(xab_ctx *, const float *, int, const double *, const float *, int, int64_t, float *,
+                                int64_t, double *, int);
 
 template int mdot<double>(xab_ctx *, const double *, int64_t, int, const double *, int64_t, double *, int, const int *);
 template int mdot<float>(xab_ctx *, const float *, int64_t, int, const float *, int64_t, double *, int, const int *);

@@ -76,6 +76,7 @@ struct Cycle {
     double est = 0.0;        // recurrence residual estimate |g_{k}|
     bool breakdown = false;  // h_{j+1,j} = 0
     std::vector<double> samp;  // |g_0| = beta, then |g_{j+1}| after every step
+    bool by_recurrence = false;  // ended because the recurrence residual met the threshold
 };
 
 // The MM ratio of eq. (1) over samples v[s-t .. s-1]: max / min.
@@ -93,7 +94,7 @@ double mm_ratio(const std::vector<double> &v, size_t s, size_t t) {
 // recurrence residual falls to tol_abs.  Adds scale * M^-1 V y to x.
 template <class T>
 int cycle(xab_ctx *ctx, const xab_plan *pl, xab_matrix *A, Work &W, int m, double beta, double tol_abs,
-          int64_t max_steps, double *x, Cycle &out) {
+          int64_t max_steps, double *x, int ortho, Cycle &out) {
     const int64_t n = A->n;
     const T *d = nullptr;
     if constexpr (sizeof(T) == 8) d = (const T *)A->diag64;
@@ -112,28 +113,61 @@ int cycle(xab_ctx *ctx, const xab_plan *pl, xab_matrix *A, Work &W, int m, doubl
     for (int j = 0; j < m && j < max_steps; ++j) {
         // w = A z (FP64 accumulation in every mode)
         if ((s = xab_spmv_dispatch(ctx, pl, z, tt, w, tt, XAB_F64)) != XAB_OK) return s;
-        // pass 1: h1 = V^T w, ||w||^2; then one sweep: w' = w - V h1 with
-        // the second pass's h2 = V^T w', ||w'||^2 from the same reads of V
-        if ((s = xab::mdot<T>(ctx, V, W.ldv, j + 1, w, n, W.part, nb, nullptr)) != XAB_OK) return s;
-        if ((s = xab::reduce_parts(ctx, W.part, nb, xab::kPartLd, j + 2, W.h1, 0, nullptr)) != XAB_OK) return s;
-        if ((s = xab::update_mdot<T>(ctx, V, W.ldv, j + 1, W.h1, w, n, W.part, nb)) != XAB_OK) return s;
-        if ((s = xab::reduce_parts(ctx, W.part, nb, xab::kPartLd, j + 2, W.h2, 0, nullptr)) != XAB_OK) return s;
-        // DGKS: the second update only when cancellation was severe
-        if ((s = xab::dgks_gate(ctx, W.h1 + j + 1, W.h2 + j + 1, kEta, W.gate)) != XAB_OK) return s;
-        if ((s = xab::update_norm<T>(ctx, V, W.ldv, j + 1, W.h2, w, n, W.part, nb, W.gate)) != XAB_OK) return s;
-        if ((s = xab::reduce_parts(ctx, W.part, nb, 1, 1, W.sc, 0, W.gate)) != XAB_OK) return s;
+        const size_t oh2 = (size_t)(W.h2 - W.h1), osc = (size_t)(W.sc - W.h1);  // layout of the small region
+        bool dgks = false;
+        if (ortho == XAB_ORTHO_DGKS) {
+            // pass 1: h1 = V^T w, ||w||^2; then one sweep: w' = w - V h1 with
+            // the second pass's h2 = V^T w', ||w'||^2 from the same reads of V
+            dgks = true;
+            if ((s = xab::mdot<T>(ctx, V, W.ldv, j + 1, w, n, W.part, nb, nullptr)) != XAB_OK) return s;
+            if ((s = xab::reduce_parts(ctx, W.part, nb, xab::kPartLd, j + 2, W.h1, 0, nullptr)) != XAB_OK) return s;
+            if ((s = xab::update_mdot<T>(ctx, V, j + 1, W.h1, V, j + 1, W.ldv, w, n, W.part, nb)) != XAB_OK) return s;
+            if ((s = xab::reduce_parts(ctx, W.part, nb, xab::kPartLd, j + 2, W.h2, 0, nullptr)) != XAB_OK) return s;
+            // the second update only when cancellation was severe
+            if ((s = xab::dgks_gate(ctx, W.h1 + j + 1, W.h2 + j + 1, kEta, W.gate)) != XAB_OK) return s;
+            if ((s = xab::update_norm<T>(ctx, V, W.ldv, j + 1, W.h2, w, n, W.part, nb, W.gate)) != XAB_OK) return s;
+            if ((s = xab::reduce_parts(ctx, W.part, nb, 1, 1, W.sc, 0, W.gate)) != XAB_OK) return s;
+        } else if (ortho == XAB_ORTHO_CGS) {
+            // h1 = V^T w, then w -= V h1; ||w||^2 into h1[j+1]
+            if ((s = xab::mdot<T>(ctx, V, W.ldv, j + 1, w, n, W.part, nb, nullptr)) != XAB_OK) return s;
+            if ((s = xab::reduce_parts(ctx, W.part, nb, xab::kPartLd, j + 1, W.h1, 0, nullptr)) != XAB_OK) return s;
+            if ((s = xab::update_norm<T>(ctx, V, W.ldv, j + 1, W.h1, w, n, W.part, nb, nullptr)) != XAB_OK) return s;
+            if ((s = xab::reduce_parts(ctx, W.part, nb, 1, 1, W.h1 + j + 1, 0, nullptr)) != XAB_OK) return s;
+        } else {
+            // MGS (blocks of one column) or BCGS (blocks of four): each
+            // sweep applies one block's update and forms the next block's
+            // dots with the updated w; the last sweep leaves ||w||^2 in h1[j+1]
+            const int bs = ortho == XAB_ORTHO_MGS ? 1 : 4;
+            const int nb0 = std::min(bs, j + 1);
+            if ((s = xab::mdot<T>(ctx, V, W.ldv, nb0, w, n, W.part, nb, nullptr)) != XAB_OK) return s;
+            if ((s = xab::reduce_parts(ctx, W.part, nb, xab::kPartLd, nb0, W.h1, 0, nullptr)) != XAB_OK) return s;
+            for (int b0 = 0; b0 <= j; b0 += bs) {
+                const int b1 = std::min(b0 + bs, j + 1);
+                const int c1 = std::min(b1 + bs, j + 1);  // next block [b1, c1)
+                const T *Vn = c1 > b1 ? V + (int64_t)b1 * W.ldv : nullptr;
+                if ((s = xab::update_mdot<T>(ctx, V + (int64_t)b0 * W.ldv, b1 - b0, W.h1 + b0, Vn, c1 - b1, W.ldv, w,
+                                             n, W.part, nb)) != XAB_OK)
+                    return s;
+                if ((s = xab::reduce_parts(ctx, W.part, nb, xab::kPartLd, c1 - b1 + 1, W.h1 + b1, 0, nullptr)) !=
+                    XAB_OK)
+                    return s;
+            }
+        }
         // v_{j+1} = w / ||w||, z = M^-1 v_{j+1}
         T *vn = V + (int64_t)(j + 1) * W.ldv;
-        if ((s = xab::scale_precond<T>(ctx, w, W.h2 + j + 1, vn, z, d, n, W.sc, W.gate)) != XAB_OK) return s;
-        // one read-back of h1, h2, the norms and the DGKS gate (contiguous)
+        if (dgks) {
+            if ((s = xab::scale_precond<T>(ctx, w, W.h2 + j + 1, vn, z, d, n, W.sc, W.gate)) != XAB_OK) return s;
+        } else {
+            if ((s = xab::scale_precond<T>(ctx, w, W.h1 + j + 1, vn, z, d, n)) != XAB_OK) return s;
+        }
+        // one read-back of the coefficients, the norms and the DGKS gate (contiguous)
         XAB_HIP(ctx, hipMemcpyAsync(W.host, W.h1, W.small_bytes, hipMemcpyDeviceToHost, ctx->stream));
         XAB_HIP(ctx, hipStreamSynchronize(ctx->stream));
         const double *hh = W.host;
         int gate = 0;
-        memcpy(&gate, (const char *)W.gate - (const char *)W.h1 + (const char *)W.host, sizeof(int));
-        const size_t oh2 = (size_t)(W.h2 - W.h1), osc = (size_t)(W.sc - W.h1);  // layout of the small region
+        if (dgks) memcpy(&gate, (const char *)W.gate - (const char *)W.h1 + (const char *)W.host, sizeof(int));
         for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hh[i] + (gate ? hh[oh2 + i] : 0.0);
-        const double hn = std::sqrt(gate ? hh[osc] : hh[oh2 + j + 1]);
+        const double hn = std::sqrt(!dgks ? hh[j + 1] : (gate ? hh[osc] : hh[oh2 + j + 1]));
         H[(size_t)(j + 1) * m + j] = hn;
         // earlier rotations on column j, then a new one
         for (int i = 0; i < j; ++i) {
@@ -155,7 +189,10 @@ int cycle(xab_ctx *ctx, const xab_plan *pl, xab_matrix *A, Work &W, int m, doubl
             out.breakdown = true;
             break;
         }
-        if (std::fabs(g[j + 1]) <= tol_abs) break;
+        if (std::fabs(g[j + 1]) <= tol_abs) {
+            out.by_recurrence = true;
+            break;
+        }
     }
     // back substitution on the rotated triangle
     std::vector<double> y(k > 0 ? k : 1, 0.0);
@@ -201,6 +238,11 @@ extern "C" int xab_gmres(xab_ctx *ctx, const xab_plan *pl, const double *d_b, do
         return xab_fail(ctx, XAB_E_SHAPE, "m_max must be in [m, 63]");
     const int mcap = tune ? opts->m_max : m0;  // basis capacity
     int m = m0;                                // restart length of the next cycle
+    if (opts->ortho < XAB_ORTHO_DGKS || opts->ortho > XAB_ORTHO_POLICY) return xab_fail(ctx, XAB_E_SHAPE, "ortho");
+    const bool policy = opts->ortho == XAB_ORTHO_POLICY;
+    int ortho = policy ? (opts->tol <= 1e-10 ? XAB_ORTHO_MGS : XAB_ORTHO_BCGS) : opts->ortho;
+    double rec_scale = 1.0;  // the policy narrows the recurrence threshold after a fault
+    bool last_by_rec = false;
     if (opts->mode != XAB_MODE_FP64 && opts->mode != XAB_MODE_IR) return xab_fail(ctx, XAB_E_SHAPE, "mode");
     if (!A->has64) return xab_fail(ctx, XAB_E_DTYPE, "GMRES needs FP64 values for the residual");
     if (opts->mode == XAB_MODE_IR && !A->has32) return xab_fail(ctx, XAB_E_DTYPE, "IR mode needs FP32 values");
@@ -254,6 +296,13 @@ extern "C" int xab_gmres(xab_ctx *ctx, const xab_plan *pl, const double *d_b, do
             status = XAB_OK;
             break;
         }
+        if (last_by_rec && policy && !ir) {
+            // fault convergence: the recurrence met the threshold, the true residual did not
+            inf.faults++;
+            ortho = XAB_ORTHO_DGKS;
+            rec_scale *= 0.1;
+        }
+        last_by_rec = false;
         if (inf.iters >= maxiter) break;
         if (opts->max_time_s > 0 && elapsed() > opts->max_time_s) {
             status = XAB_TIME_LIMIT;
@@ -264,11 +313,12 @@ extern "C" int xab_gmres(xab_ctx *ctx, const xab_plan *pl, const double *d_b, do
             // inner solve of A d = r to inner_tol (or one cycle), then x += d
             double inner = opts->inner_tol > 0 ? opts->inner_tol : 1e-6;
             double tol_abs = std::max(inner * beta, 0.1 * opts->tol * bn);
-            s = cycle<float>(ctx, pl, A, W, m, beta, tol_abs, maxiter - inf.iters, d_x, c);
+            s = cycle<float>(ctx, pl, A, W, m, beta, tol_abs, maxiter - inf.iters, d_x, ortho, c);
             inf.refinements++;
         } else {
-            s = cycle<double>(ctx, pl, A, W, m, beta, opts->tol * bn, maxiter - inf.iters, d_x, c);
+            s = cycle<double>(ctx, pl, A, W, m, beta, opts->tol * bn * rec_scale, maxiter - inf.iters, d_x, ortho, c);
         }
+        last_by_rec = c.by_recurrence;
         if (s != XAB_OK) return s;
         inf.iters += c.k;
         inf.restarts++;
@@ -283,5 +333,6 @@ extern "C" int xab_gmres(xab_ctx *ctx, const xab_plan *pl, const double *d_b, do
     inf.true_relres = relres;
     inf.seconds = elapsed();
     inf.status = status;
+    inf.ortho = ortho;
     return status;
 }

@@ -258,3 +258,44 @@ def test_gmres_restart_tuning_extremes(ctx, mode):
         assert st == 0
         want = min(3 + 5 * (inf["restarts"] - 1), 17) if thr == math.inf else 3
         assert inf["m_final"] == want
+
+
+# ------------------------------------------------- orthogonalisation menu + accuracy policy
+@pytest.mark.parametrize("ortho", [0, 1, 2, 3])
+@pytest.mark.parametrize("mode", [0, 1])
+def test_gmres_ortho_menu_vs_oracle(ctx, ortho, mode):
+    """Every orthogonalisation converges to the true-residual target with an
+    iteration count within 20 % of the oracle's run of the same method."""
+    A = gen.laplacian2d(32)
+    b = np.ones(A.n)
+    ref = oracle.gmres_at(A, b, 30, 30, 0, 0.0, tol=1e-10, maxiter=1500, ortho=ortho)
+    M = ctx.matrix_from_csr(A, with_f32=True)
+    P = ctx.plan_class(M, 5)
+    x, inf, st = ctx.gmres(P, dev(b), m=30, tol=1e-10, maxiter=1500, mode=mode, precond=xab.PRECOND_NONE,
+                           ortho=ortho)
+    assert st == 0 and inf["ortho"] == ortho
+    xs = x.cpu().numpy()
+    assert np.linalg.norm(b - oracle.spmv(A, xs)[0]) / np.linalg.norm(b) <= 1e-10
+    if mode == 0:
+        assert abs(inf["iters"] - ref["iters"]) <= 0.2 * ref["iters"]
+        assert np.linalg.norm(xs - ref["x"]) <= 1e-8 * np.linalg.norm(ref["x"])
+
+
+def test_gmres_accuracy_policy(ctx):
+    """The policy picks MGS at 1e-10 and BCGS at 1e-8; at 1e-15 (below the
+    attainable true residual) the recurrence keeps meeting narrowed
+    thresholds the true residual misses: faults are counted and DGKS takes
+    over, as in the oracle."""
+    A = gen.laplacian2d(32)
+    b = np.ones(A.n)
+    M = ctx.matrix_from_csr(A)
+    P = ctx.plan_class(M, 5)
+    for tol, want in ((1e-10, xab.ORTHO_MGS), (1e-8, xab.ORTHO_BCGS)):
+        x, inf, st = ctx.gmres(P, dev(b), m=30, tol=tol, maxiter=1500, precond=xab.PRECOND_NONE,
+                               ortho=xab.ORTHO_POLICY)
+        assert st == 0 and inf["faults"] == 0 and inf["ortho"] == want
+    ref = oracle.gmres_at(A, b, 30, 30, 0, 0.0, tol=1e-15, maxiter=600, ortho=oracle.ORTHO_POLICY)
+    x, inf, st = ctx.gmres(P, dev(b), m=30, tol=1e-15, maxiter=600, precond=xab.PRECOND_NONE,
+                           ortho=xab.ORTHO_POLICY)
+    assert st == 1 and ref["status"] == 1
+    assert inf["faults"] >= 1 and ref["faults"] >= 1 and inf["ortho"] == xab.ORTHO_DGKS

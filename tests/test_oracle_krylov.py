@@ -174,3 +174,49 @@ def test_gmres_at_cures_stagnation():
     assert np.linalg.norm(b - oracle.spmv(A, tuned["x"])[0]) / np.linalg.norm(b) <= 1e-10
     mh = tuned["m_hist"]
     assert mh[0] == 4 and all(y - x in (0, 4) for x, y in zip(mh, mh[1:])) and max(mh) <= 40
+
+
+# ------------------------------------------------- orthogonalisation menu + accuracy policy
+ORTHOS = [oracle.ORTHO_DGKS, oracle.ORTHO_CGS, oracle.ORTHO_MGS, oracle.ORTHO_BCGS]
+
+
+def test_ortho_variants_agree_when_well_conditioned():
+    """DGKS, CGS, MGS and BCGS build the same Arnoldi decomposition in exact
+    arithmetic: on a well-conditioned problem they take the same steps, reach
+    the same solution and satisfy the Arnoldi relation to rounding."""
+    A = gen.laplacian2d(32)
+    b = np.ones(A.n)
+    outs = [oracle.gmres_at(A, b, 30, 30, 0, 0.0, tol=1e-10, maxiter=1500, ortho=o, history=True) for o in ORTHOS]
+    ref = outs[2]  # MGS
+    for o, r in zip(ORTHOS, outs):
+        assert r["status"] == 0 and r["iters"] == ref["iters"], o
+        assert np.linalg.norm(r["x"] - ref["x"]) <= 1e-9 * np.linalg.norm(ref["x"]), o
+        assert r["arnoldi_err"] <= 1e-14, o
+
+
+def test_bcgs_within_one_block_is_cgs():
+    """With m <= 4 every BCGS step is a single block: bit for bit CGS."""
+    A = gen.random_uniform_rows(2000, 9, 5, 30)
+    b = np.ones(A.n)
+    c = oracle.gmres_at(A, b, 4, 4, 0, 0.0, tol=1e-10, maxiter=800, ortho=oracle.ORTHO_CGS)
+    k = oracle.gmres_at(A, b, 4, 4, 0, 0.0, tol=1e-10, maxiter=800, ortho=oracle.ORTHO_BCGS)
+    assert np.array_equal(c["x"], k["x"]) and c["iters"] == k["iters"]
+
+
+def test_accuracy_policy_rule():
+    """MGS for requirements of 1e-10 or tighter, BCGS otherwise; a fault
+    convergence (recurrence met, true residual missed) switches to DGKS and
+    narrows the recurrence threshold.  On the 32x32 Laplacian the true
+    residual cannot go much below 1e-14, so 1e-14 converges after a fault
+    and 1e-15 keeps faulting until the step limit."""
+    A = gen.laplacian2d(32)
+    b = np.ones(A.n)
+    P = oracle.ORTHO_POLICY
+    r = oracle.gmres_at(A, b, 30, 30, 0, 0.0, tol=1e-10, maxiter=1500, ortho=P)
+    assert (r["status"], r["faults"], r["ortho"]) == (0, 0, oracle.ORTHO_MGS)
+    r = oracle.gmres_at(A, b, 30, 30, 0, 0.0, tol=1e-8, maxiter=1500, ortho=P)
+    assert (r["status"], r["faults"], r["ortho"]) == (0, 0, oracle.ORTHO_BCGS)
+    r = oracle.gmres_at(A, b, 30, 30, 0, 0.0, tol=1e-14, maxiter=1500, ortho=P)
+    assert r["status"] == 0 and r["faults"] >= 1 and r["ortho"] == oracle.ORTHO_DGKS
+    r = oracle.gmres_at(A, b, 30, 30, 0, 0.0, tol=1e-15, maxiter=1500, ortho=P)
+    assert r["status"] == 1 and r["faults"] >= 2 and r["ortho"] == oracle.ORTHO_DGKS
