@@ -252,6 +252,12 @@ def ortho_menu_leg(ctx, xab, torch, plan, n):
         med = runs[1]
         res[name] = {"s": round(med["seconds"], 5), "iters": med["iters"], "relres": med["true_relres"],
                      "status": med["status"], "faults": med["faults"]}
+    # mixed precision under the policy: the inner solve's requirement (1e-6) selects BCGS
+    runs = sorted((ctx.gmres(plan, b, m=30, tol=1e-10, mode=xab.MODE_IR, precond=xab.PRECOND_JACOBI,
+                             ortho=xab.ORTHO_POLICY)[1] for _ in range(3)), key=lambda r: r["seconds"])
+    med = runs[1]
+    res["ir_policy"] = {"s": round(med["seconds"], 5), "iters": med["iters"], "relres": med["true_relres"],
+                        "status": med["status"], "ortho": med["ortho"]}
     return res
 
 

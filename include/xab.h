@@ -85,14 +85,24 @@ typedef enum { XAB_TIME = 0, XAB_STABLE = 1, XAB_LEARNED = 2 } xab_policy;
  *                  block is scanned with 256 * j_per_lane entries per
  *                  workgroup and the 8 partial products are summed in
  *                  block order.  The plan owns the copy: values changed
- *                  after plan creation are not seen. */
+ *                  after plan creation are not seen.
+ *   XAB_SELL       sliced ELLPACK with a sorting window (SELL-C-sigma, a
+ *                  format the paper names as future work, section 5):
+ *                  inside windows of tile_rows rows the rows are ordered
+ *                  longest first, cut into chunks of 64 (one wave) and each
+ *                  chunk is stored column-major, padded to its longest row;
+ *                  one lane sums one row.  The plan owns the padded copy.
+ *                  XAB_E_UNSUPPORTED when a row is longer than 4096 or the
+ *                  padded size would exceed twice the entries plus one
+ *                  chunk of the longest row. */
 typedef enum {
     XAB_ROW = 0,
     XAB_NNZ = 1,
     XAB_BSS = 2,
     XAB_SYM_S3 = 3,
     XAB_SYM_ATOMIC = 4,
-    XAB_XCB = 5
+    XAB_XCB = 5,
+    XAB_SELL = 6
 } xab_variant;
 
 typedef struct {
@@ -100,7 +110,8 @@ typedef struct {
     int32_t tile_nnz;      /* NNZ, SYM_S3: target entries per tile (>= 256) */
     int32_t j_per_lane;    /* BSS: entries per lane, 1..32 */
     int32_t col_block;     /* SYM_S3: column block size C of the touch map (power of two) */
-    int32_t tile_rows;     /* SYM_S3: maximum rows per tile (<= 2048) */
+    int32_t tile_rows;     /* SYM_S3: maximum rows per tile (<= 2048); SELL: sorting window
+                              (a multiple of 64, at most 1024) */
 } xab_params;
 
 /* Matrix flags */
@@ -109,9 +120,9 @@ typedef struct {
 #define XAB_TRUST_INPUT 2u /* skip the structural validation pass */
 
 /* Selector classes: fixed (variant, params) pairs, the action space of the
- * selector.  0..8 and 12 apply to general matrices, 9..11 to
+ * selector.  0..8, 12 and 13 apply to general matrices, 9..11 to
  * XAB_SYM_LOWER. */
-#define XAB_NCLASSES 13
+#define XAB_NCLASSES 14
 int xab_class_params(int32_t k, xab_variant *variant, xab_params *params);
 
 typedef struct {
@@ -159,7 +170,9 @@ void xab_plan_destroy(xab_plan *plan);
  * 1 BSS row_lo, 2 BSS tile_row, 3 BSS carry_row, 4 tm_ptr, 5 tm_tile,
  * 6 tile_ptr, 7 tile_blk, 8 tile_slot, 9 XCB per-block row pointers
  * (8 x (nrows+1), block-major), 10 XCB column indices in block order,
- * bit 31 set on the first entry of each row within its block.
+ * bit 31 set on the first entry of each row within its block, 11 SELL
+ * row order (original row of each ordered row), 12 SELL ordered row
+ * lengths, 13 SELL chunk widths, 14 SELL padded column indices.
  * *len receives the length; h_out may be NULL to query it.  Synchronous. */
 int xab_plan_array(const xab_plan *plan, int32_t which, int32_t *h_out, int64_t *len);
 int xab_plan_info(const xab_plan *plan, xab_variant *v, xab_params *p);
@@ -258,9 +271,11 @@ typedef enum { XAB_PRECOND_NONE = 0, XAB_PRECOND_JACOBI = 1 } xab_precond;
  * Gram-Schmidt, repeated when the norm fell below 1/sqrt(2) of the
  * incoming one), CGS (once), MGS (column by column), BCGS (blocks of 4
  * columns: CGS inside a block, blocks in order); POLICY is the accuracy
- * policy of section 3.3.2: MGS for tol <= 1e-10, else BCGS, and after a
- * fault convergence (a cycle ended on its recurrence residual but the true
- * residual missed tol) DGKS with a tenfold narrower recurrence threshold. */
+ * policy of section 3.3.2: MGS when the requirement of the orthogonalised
+ * solve is <= 1e-10 (tol in FP64 mode, inner_tol in IR mode), else BCGS,
+ * and after a fault convergence (a cycle ended on its recurrence residual
+ * but the true residual missed tol; FP64 mode) DGKS with a tenfold
+ * narrower recurrence threshold. */
 typedef enum {
     XAB_ORTHO_DGKS = 0,
     XAB_ORTHO_CGS = 1,

@@ -37,6 +37,7 @@ def lib():
             "orc_plan_sym_touch": (i64, [i64, P, P, i64, P, i64, P, P, P, P, P]),
             "orc_plan_xcb": (None, [i64, i64, P, P, ci, P, P]),
             "orc_xcb_flag_heads": (None, [i64, ci, P, P]),
+            "orc_plan_sell": (i64, [i64, P, P, P, ci, ci, P, P, P, P, P, P]),
             "orc_features": (None, [i64, P, P, ci, P, P]),
             "orc_mlp_nparams": (i64, [ci, ci, ci]),
             "orc_mlp_forward": (None, [ci, ci, ci, P, i64, P, P]),
@@ -161,6 +162,22 @@ def plan_xcb(A, nb=8, flagged=False):
     if flagged:
         lib().orc_xcb_flag_heads(A.n, nb, _p(out_rp), _p(out_ci))
     return out_rp, out_ci[:A.nnz]
+
+
+def plan_sell(A, C=64, sigma=1024):
+    """SELL-C-sigma layout: dict(perm, cptr, clen, rlen, cols, vals)."""
+    rp, ci, v = _csr(A)
+    n = A.n
+    nch = (n + C - 1) // C
+    perm = np.empty(max(n, 1), dtype=np.int32)
+    rlen = np.empty(max(n, 1), dtype=np.int32)
+    cptr = np.empty(nch + 1, dtype=np.int64)
+    clen = np.empty(max(nch, 1), dtype=np.int32)
+    tot = lib().orc_plan_sell(n, _p(rp), _p(ci), _p(v), C, sigma, _p(perm), _p(cptr), _p(clen), _p(rlen), None, None)
+    cols = np.empty(max(tot, 1), dtype=np.int32)
+    vals = np.empty(max(tot, 1), dtype=np.float64)
+    lib().orc_plan_sell(n, _p(rp), _p(ci), _p(v), C, sigma, _p(perm), _p(cptr), _p(clen), _p(rlen), _p(cols), _p(vals))
+    return dict(perm=perm[:n], cptr=cptr, clen=clen[:nch], rlen=rlen[:n], cols=cols[:tot], vals=vals[:tot])
 
 
 # ------------------------------------------------------------------ features

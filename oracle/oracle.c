@@ -324,6 +324,61 @@ void orc_xcb_flag_heads(int64_t n, int nb, const int32_t *rp, int32_t *ci) {
     }
 }
 
+/* Sliced ELLPACK with sorting window (SELL-C-sigma, a format the paper
+ * lists among future SpMV candidates, section 5): inside every window of
+ * sigma rows the rows are ordered by length, longest first (ties keep the
+ * lower row first); the ordered rows are cut into chunks of C; a chunk is
+ * stored column-major and padded to its longest row: entry k of the chunk's
+ * lane l sits at cptr[chunk] + k*C + l.  perm[r] = original row of ordered
+ * row r, rlen[r] its length, clen[chunk] the chunk width.  Returns the
+ * padded size cptr[nchunks]; when cols is non-NULL also fills cols / vals
+ * (padding: column 0, value 0). */
+int64_t orc_plan_sell(int64_t n, const int32_t *rowptr, const int32_t *colind, const double *val, int C,
+                      int sigma, int32_t *perm, int64_t *cptr, int32_t *clen, int32_t *rlen, int32_t *cols,
+                      double *vals) {
+    for (int64_t w0 = 0; w0 < n; w0 += sigma) {
+        int64_t w1 = w0 + sigma < n ? w0 + sigma : n;
+        for (int64_t r = w0; r < w1; ++r) perm[r] = (int32_t)r;
+        /* insertion sort: stable, longest first */
+        for (int64_t r = w0 + 1; r < w1; ++r) {
+            int32_t row = perm[r];
+            int32_t len = rowptr[row + 1] - rowptr[row];
+            int64_t q = r - 1;
+            while (q >= w0 && rowptr[perm[q] + 1] - rowptr[perm[q]] < len) {
+                perm[q + 1] = perm[q];
+                --q;
+            }
+            perm[q + 1] = row;
+        }
+    }
+    int64_t nch = (n + C - 1) / C;
+    cptr[0] = 0;
+    for (int64_t c = 0; c < nch; ++c) {
+        int32_t wmax = 0;
+        for (int64_t r = c * C; r < (c + 1) * C && r < n; ++r) {
+            rlen[r] = rowptr[perm[r] + 1] - rowptr[perm[r]];
+            if (rlen[r] > wmax) wmax = rlen[r];
+        }
+        clen[c] = wmax;
+        cptr[c + 1] = cptr[c] + (int64_t)wmax * C;
+    }
+    if (cols) {
+        for (int64_t q = 0; q < cptr[nch]; ++q) {
+            cols[q] = 0;
+            if (vals) vals[q] = 0.0;
+        }
+        for (int64_t r = 0; r < n; ++r) {
+            int64_t c = r / C, l = r % C;
+            for (int32_t k = 0; k < rlen[r]; ++k) {
+                int64_t dst = cptr[c] + (int64_t)k * C + l, src = rowptr[perm[r]] + k;
+                cols[dst] = colind[src];
+                if (vals) vals[dst] = val[src];
+            }
+        }
+    }
+    return cptr[nch];
+}
+
 /* ------------------------------------------------------------- features */
 
 /* stats: [0] n, [1] nnz, [2] sum len^2, [3] max len, [4] max |i-j|,

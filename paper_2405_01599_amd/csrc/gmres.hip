@@ -240,7 +240,10 @@ extern "C" int xab_gmres(xab_ctx *ctx, const xab_plan *pl, const double *d_b, do
     int m = m0;                                // restart length of the next cycle
     if (opts->ortho < XAB_ORTHO_DGKS || opts->ortho > XAB_ORTHO_POLICY) return xab_fail(ctx, XAB_E_SHAPE, "ortho");
     const bool policy = opts->ortho == XAB_ORTHO_POLICY;
-    int ortho = policy ? (opts->tol <= 1e-10 ? XAB_ORTHO_MGS : XAB_ORTHO_BCGS) : opts->ortho;
+    // the policy's rule applies to the requirement of the solve being
+    // orthogonalised: the FP64 solve's tol, or in IR mode the inner tolerance
+    const double req = opts->mode == XAB_MODE_IR ? (opts->inner_tol > 0 ? opts->inner_tol : 1e-6) : opts->tol;
+    int ortho = policy ? (req <= 1e-10 ? XAB_ORTHO_MGS : XAB_ORTHO_BCGS) : opts->ortho;
     double rec_scale = 1.0;  // the policy narrows the recurrence threshold after a fault
     bool last_by_rec = false;
     if (opts->mode != XAB_MODE_FP64 && opts->mode != XAB_MODE_IR) return xab_fail(ctx, XAB_E_SHAPE, "mode");

@@ -89,6 +89,17 @@ struct xab_plan {
     void *xcb_Y = nullptr;              // compressed partial products, acc-type, ybase[kXcb] slots
     int64_t xcb_G = 0;                  // row groups of 256 (the combine's workgroups)
     int32_t *xcb_gbase = nullptr;       // kXcb * (G + 1): compressed index of group g's first row in block k
+    // SELL: chunks of kSellC ordered rows, column-major, padded to the chunk's longest row
+    static constexpr int kSellC = 64;
+    static constexpr int kSellMaxRow = 4096;
+    int64_t sell_nch = 0, sell_total = 0;  // chunks, padded entries
+    int32_t *sell_perm = nullptr;          // original row of ordered row r
+    int32_t *sell_rlen = nullptr;          // length of ordered row r (nch * C slots, 0 past n)
+    int32_t *sell_clen = nullptr;          // chunk widths
+    int64_t *sell_cptr = nullptr;          // chunk offsets [nch + 2]: offsets, then the widest chunk
+    int32_t *sell_cols = nullptr;          // padded columns (padding: 0)
+    double *sell_val64 = nullptr;          // padded values (padding: 0)
+    float *sell_val32 = nullptr;
 };
 
 struct xab_batch {

@@ -360,6 +360,112 @@ __global__ void k_xcb_scatter(const int32_t *rowptr, const int32_t *colind, cons
     }
 }
 
+__global__ void k_zero_i32(int32_t *p, int64_t m) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < m) p[i] = 0;
+}
+
+// ---- SELL-C-sigma: order rows inside each window, chunk widths, padded copy
+// One workgroup (blockDim = the window rounded up to a power of two, at
+// most 1024) per window: bitonic sort of (longest first, then lower row)
+// keys in LDS.
+__global__ void k_sell_sort(const int32_t *rowptr, int32_t n, int32_t sigma, int32_t *perm, int32_t *rlen) {
+    __shared__ unsigned long long key[1024];
+    const int P2 = blockDim.x;
+    const int64_t w0 = (int64_t)blockIdx.x * sigma;
+    const int t = threadIdx.x;
+    const int64_t r = w0 + t;
+    unsigned long long k = ~0ull;
+    if (t < sigma && r < n) {
+        const uint32_t len = (uint32_t)(rowptr[r + 1] - rowptr[r]);
+        k = ((unsigned long long)(0x7fffffffu - len) << 32) | (unsigned long long)r;
+    }
+    key[t] = k;
+    __syncthreads();
+    for (int size = 2; size <= P2; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            const int partner = t ^ stride;
+            if (partner > t) {
+                const bool up = (t & size) == 0;
+                const unsigned long long a = key[t], b = key[partner];
+                if ((a > b) == up) {
+                    key[t] = b;
+                    key[partner] = a;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    if (t < sigma && r < n) {
+        const unsigned long long q = key[t];
+        perm[r] = (int32_t)(q & 0xffffffffull);
+        rlen[r] = (int32_t)(0x7fffffffu - (uint32_t)(q >> 32));
+    }
+}
+
+// chunk widths: the first ordered row of a chunk is its longest (chunks lie
+// inside windows); lanes past n count as empty rows
+__global__ void k_sell_widths(const int32_t *rlen, int32_t n, int64_t nch, int32_t *clen) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < nch) clen[c] = rlen[c * xab_plan::kSellC];
+}
+
+// cptr[c] = C * sum of widths before chunk c (int64), cptr[nch] = padded
+// size, cptr[nch + 1] = the widest chunk (one workgroup)
+__global__ void k_sell_scan(const int32_t *clen, int64_t nch, int64_t *cptr) {
+    __shared__ int64_t part[1024];
+    __shared__ int64_t carry, widest;
+    const int t = threadIdx.x;
+    if (t == 0) {
+        carry = 0;
+        widest = 0;
+    }
+    __syncthreads();
+    for (int64_t base = 0; base < nch; base += 1024) {
+        const int64_t i = base + t;
+        const int64_t v = i < nch ? (int64_t)clen[i] * xab_plan::kSellC : 0;
+        part[t] = v;
+        __syncthreads();
+        for (int d = 1; d < 1024; d <<= 1) {
+            const int64_t u = t >= d ? part[t - d] : 0;
+            __syncthreads();
+            part[t] += u;
+            __syncthreads();
+        }
+        if (i < nch) {
+            cptr[i] = carry + part[t] - v;
+            if (clen[i] > widest) atomicMax((unsigned long long *)&widest, (unsigned long long)clen[i]);
+        }
+        __syncthreads();
+        if (t == 1023) carry += part[1023];
+        __syncthreads();
+    }
+    if (t == 0) {
+        cptr[nch] = carry;
+        cptr[nch + 1] = widest;
+    }
+}
+
+// one lane per ordered row slot (nch * C of them): copy its row into the
+// chunk's columns, zeros past the row's end
+__global__ void k_sell_fill(const int32_t *rowptr, const int32_t *colind, const double *v64, const float *v32,
+                            int32_t n, int64_t nch, const int32_t *perm, const int32_t *rlen, const int64_t *cptr,
+                            const int32_t *clen, int32_t *cols, double *o64, float *o32) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nch * xab_plan::kSellC) return;
+    const int64_t c = r / xab_plan::kSellC, l = r % xab_plan::kSellC;
+    const int32_t w = clen[c];
+    const int32_t len = r < n ? rlen[r] : 0;
+    const int64_t src = r < n ? rowptr[perm[r]] : 0;
+    for (int32_t k = 0; k < w; ++k) {
+        const int64_t dst = cptr[c] + (int64_t)k * xab_plan::kSellC + l;
+        const bool live = k < len;
+        cols[dst] = live ? colind[src + k] : 0;
+        if (o64) o64[dst] = live ? v64[src + k] : 0.0;
+        if (o32) o32[dst] = live ? v32[src + k] : 0.0f;
+    }
+}
+
 unsigned grid_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 }  // namespace
@@ -383,6 +489,13 @@ static void free_plan_arrays(xab_ctx *ctx, xab_plan *pl) {
     xab_dfree(ctx, pl->xcb_gbase);
     xab_dfree(ctx, pl->s3_ci);
     xab_dfree(ctx, pl->s3_dense);
+    xab_dfree(ctx, pl->sell_perm);
+    xab_dfree(ctx, pl->sell_rlen);
+    xab_dfree(ctx, pl->sell_clen);
+    xab_dfree(ctx, pl->sell_cptr);
+    xab_dfree(ctx, pl->sell_cols);
+    xab_dfree(ctx, pl->sell_val64);
+    xab_dfree(ctx, pl->sell_val32);
     xab_dfree(ctx, pl->xcb_mask);
     xab_dfree(ctx, pl->xcb_colind);
     xab_dfree(ctx, pl->xcb_val64);
@@ -447,6 +560,10 @@ int xab_build_plan(xab_ctx *ctx, const xab_matrix *A, xab_variant v, const xab_p
             if (p.j_per_lane < 1 || p.j_per_lane > 32 || !pow2(p.j_per_lane))
                 return xab_fail(ctx, XAB_E_UNSUPPORTED, "j_per_lane must be a power of two in [1, 32]");
             break;
+        case XAB_SELL:
+            if (p.tile_rows < xab_plan::kSellC || p.tile_rows > 1024 || p.tile_rows % xab_plan::kSellC != 0)
+                return xab_fail(ctx, XAB_E_UNSUPPORTED, "SELL window (tile_rows) must be a multiple of 64 in [64, 1024]");
+            break;
         case XAB_SYM_S3:
             if (!pow2(p.col_block) || p.col_block < 16 || p.col_block > xab::sym::kExtCap)
                 return xab_fail(ctx, XAB_E_UNSUPPORTED, "col_block must be a power of two in [16, %d]",
@@ -489,6 +606,50 @@ int xab_build_plan(xab_ctx *ctx, const xab_matrix *A, xab_variant v, const xab_p
         hipLaunchKernelGGL(k_split_bss, dim3(grid_for(pl->P + 1, 256)), dim3(256), 0, st, A->rowptr, n, T, pl->P,
                            pl->row_lo, pl->tile_row, pl->carry_row);
         CHECKED(hip_ok(ctx, hipGetLastError(), "k_split_bss"));
+    } else if (v == XAB_SELL) {
+        constexpr int C = xab_plan::kSellC;
+        const int32_t sigma = p.tile_rows;
+        const int64_t nch = std::max<int64_t>(1, ((int64_t)n + C - 1) / C);
+        pl->sell_nch = nch;
+        pl->P = nch;
+        ALLOC(pl->sell_perm, int32_t, std::max<int32_t>(1, n));
+        ALLOC(pl->sell_rlen, int32_t, nch * C);
+        ALLOC(pl->sell_clen, int32_t, nch);
+        ALLOC(pl->sell_cptr, int64_t, nch + 2);
+        hipLaunchKernelGGL(k_zero_i32, dim3(grid_for(nch * C, 256)), dim3(256), 0, st, pl->sell_rlen, nch * C);
+        if (n > 0) {
+            int P2 = 64;
+            while (P2 < sigma) P2 <<= 1;
+            hipLaunchKernelGGL(k_sell_sort, dim3(grid_for(n, sigma)), dim3(P2), 0, st, A->rowptr, n, sigma,
+                               pl->sell_perm, pl->sell_rlen);
+        }
+        hipLaunchKernelGGL(k_sell_widths, dim3(grid_for(nch, 256)), dim3(256), 0, st, pl->sell_rlen, n, nch,
+                           pl->sell_clen);
+        hipLaunchKernelGGL(k_sell_scan, dim3(1), dim3(1024), 0, st, pl->sell_clen, nch, pl->sell_cptr);
+        int64_t hdr[2] = {0, 0};
+        hipError_t e = hipGetLastError();
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(hdr, pl->sell_cptr + nch, sizeof(hdr), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        CHECKED(hip_ok(ctx, e, "SELL layout"));
+        pl->sell_total = hdr[0];
+        // limits: rows of at most 4096 entries (one lane sums a row) and
+        // padding at most the entries themselves plus one chunk of the widest row
+        if (hdr[1] > xab_plan::kSellMaxRow || hdr[0] > 2 * nnz + (int64_t)C * hdr[1]) {
+            free_plan_arrays(ctx, pl);
+            delete pl;
+            return xab_fail(ctx, XAB_E_UNSUPPORTED, "SELL: %s", hdr[1] > xab_plan::kSellMaxRow
+                                                                   ? "a row is longer than 4096"
+                                                                   : "padding would exceed the entries");
+        }
+        const int64_t tot = std::max<int64_t>(1, pl->sell_total);
+        ALLOC(pl->sell_cols, int32_t, tot);
+        if (A->has64) ALLOC(pl->sell_val64, double, tot);
+        if (A->has32) ALLOC(pl->sell_val32, float, tot);
+        hipLaunchKernelGGL(k_sell_fill, dim3(grid_for(nch * C, 256)), dim3(256), 0, st, A->rowptr, A->colind,
+                           A->val64, A->val32, n, nch, pl->sell_perm, pl->sell_rlen, pl->sell_cptr, pl->sell_clen,
+                           pl->sell_cols, pl->sell_val64, pl->sell_val32);
+        CHECKED(hip_ok(ctx, hipGetLastError(), "SELL fill"));
     } else if (v == XAB_XCB) {
         constexpr int KB = xab_plan::kXcb;
         const int64_t T = 256 * (int64_t)p.j_per_lane;
@@ -829,6 +990,10 @@ int xab_plan_array(const xab_plan *pl, int32_t which, int32_t *h_out, int64_t *l
         case 8: src = pl->tile_slot; m = pl->tile_slot ? pl->ntouch : 0; break;
         case 9: src = pl->xcb_rowptr; m = pl->xcb_rowptr ? (int64_t)xab_plan::kXcb * (pl->A->n + 1) : 0; break;
         case 10: src = pl->xcb_colind; m = pl->xcb_colind ? pl->A->nnz : 0; break;
+        case 11: src = pl->sell_perm; m = pl->sell_perm ? pl->A->n : 0; break;
+        case 12: src = pl->sell_rlen; m = pl->sell_rlen ? pl->A->n : 0; break;
+        case 13: src = pl->sell_clen; m = pl->sell_clen ? pl->sell_nch : 0; break;
+        case 14: src = pl->sell_cols; m = pl->sell_cols ? pl->sell_total : 0; break;
         default: return XAB_E_SHAPE;
     }
     *len = m;

@@ -52,7 +52,10 @@ def test_select_time_is_argmin(ctx, name):
     if A.sym_lower:
         assert set(valid) <= set(xab.SYM_CLASSES)
     else:
-        assert valid == list(xab.GENERAL_CLASSES)
+        # every general class applies, except SELL outside its limits (rows
+        # of at most 4096 entries): the trans4-shaped matrix has a longer row
+        want = [k for k in xab.GENERAL_CLASSES if not (k == 13 and int(np.max(np.diff(A.rowptr))) > 4096)]
+        assert valid == want
     t = {k: info.time_ms[k] for k in valid}
     best = min(valid, key=lambda k: (t[k], k))
     assert info.chosen == best

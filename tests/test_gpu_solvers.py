@@ -294,6 +294,11 @@ def test_gmres_accuracy_policy(ctx):
         x, inf, st = ctx.gmres(P, dev(b), m=30, tol=tol, maxiter=1500, precond=xab.PRECOND_NONE,
                                ortho=xab.ORTHO_POLICY)
         assert st == 0 and inf["faults"] == 0 and inf["ortho"] == want
+    # mixed precision: the rule reads the inner solve's requirement (1e-6)
+    M32 = ctx.matrix_from_csr(A, with_f32=True)
+    x, inf, st = ctx.gmres(ctx.plan_class(M32, 5), dev(b), m=30, tol=1e-10, maxiter=1500, mode=MODE_IR,
+                           precond=xab.PRECOND_NONE, ortho=xab.ORTHO_POLICY)
+    assert st == 0 and inf["ortho"] == xab.ORTHO_BCGS
     ref = oracle.gmres_at(A, b, 30, 30, 0, 0.0, tol=1e-15, maxiter=600, ortho=oracle.ORTHO_POLICY)
     x, inf, st = ctx.gmres(P, dev(b), m=30, tol=1e-15, maxiter=600, precond=xab.PRECOND_NONE,
                            ortho=xab.ORTHO_POLICY)

@@ -66,6 +66,24 @@ GENERAL = general_suite()
 GENERAL_CLASSES = list(xab.GENERAL_CLASSES)
 
 
+def _sell_supported(A, sigma=1024):
+    """The SELL plan's own limits, from the oracle's layout of A."""
+    p = oracle.plan_sell(A, 64, sigma)
+    longest = int(np.max(np.diff(A.rowptr))) if A.n else 0
+    return longest <= 4096 and int(p["cptr"][-1]) <= 2 * A.nnz + 64 * longest
+
+
+def _plan_class(ctx, M, A, k):
+    """Plan of class k; for SELL on a matrix outside its limits, check the
+    library refuses it (XAB_E_UNSUPPORTED) and return None."""
+    if xab.class_params(k)[0] == xab.SELL and not _sell_supported(A, xab.class_params(k)[1].tile_rows):
+        with pytest.raises(xab.XabError) as e:
+            ctx.plan_class(M, k)
+        assert e.value.status == -6
+        return None
+    return ctx.plan_class(M, k)
+
+
 def _int_version(A, seed=5):
     rng = np.random.default_rng(seed)
     B = gen.CSR(A.n, A.ncols, A.rowptr, A.colind, rng.integers(-8, 9, A.nnz).astype(np.float64),
@@ -80,7 +98,9 @@ def test_general_integer_bitexact(ctx, name, k):
     x = gen.int_vec(A.ncols, 9)
     yo, _ = oracle.spmv(A, x)
     M = ctx.matrix_from_csr(A)
-    P = ctx.plan_class(M, k)
+    P = _plan_class(ctx, M, A, k)
+    if P is None:
+        return
     y = ctx.spmv(P, dev(x))
     torch.cuda.synchronize()
     assert np.array_equal(y.cpu().numpy(), yo), f"class {k} on {name}"
@@ -93,7 +113,9 @@ def test_general_fp64_gate_and_determinism(ctx, name, k):
     x = gen.uniform_vec(A.ncols, 12)
     yo, s = oracle.spmv(A, x)
     M = ctx.matrix_from_csr(A)
-    P = ctx.plan_class(M, k)
+    P = _plan_class(ctx, M, A, k)
+    if P is None:
+        return
     xd = dev(x)
     y1 = ctx.spmv(P, xd).cpu().numpy()
     y2 = ctx.spmv(P, xd).cpu().numpy()
@@ -101,6 +123,20 @@ def test_general_fp64_gate_and_determinism(ctx, name, k):
     assert np.all(err <= 1e-12 * s), f"max rel {np.max(err / np.maximum(s, 1e-300))}"
     assert np.all(y1[s == 0] == 0.0)
     assert np.array_equal(y1, y2)
+
+
+@pytest.mark.parametrize("sigma", [64, 192, 1024])
+def test_sell_plan_bitexact(ctx, sigma):
+    for name, A in GENERAL.items():
+        if not _sell_supported(A, sigma):
+            continue
+        M = ctx.matrix_from_csr(A)
+        P = ctx.plan(M, xab.SELL, tile_rows=sigma)
+        ref = oracle.plan_sell(A, 64, sigma)
+        assert np.array_equal(P.array(11), ref["perm"]), (name, sigma)
+        assert np.array_equal(P.array(12), ref["rlen"]), (name, sigma)
+        assert np.array_equal(P.array(13), ref["clen"]), (name, sigma)
+        assert np.array_equal(P.array(14), ref["cols"]), (name, sigma)
 
 
 def test_nnz_plan_bitexact(ctx):
@@ -169,8 +205,8 @@ FP32_COMBOS = [  # (y dtype, acc) with x and values FP32
 ]
 
 
-@pytest.mark.parametrize("name", ["powerlaw", "trans4", "lap2d", "one_long_row"])
-@pytest.mark.parametrize("k", [0, 1, 3, 6, 8, 12])
+@pytest.mark.parametrize("name", ["powerlaw", "trans4", "lap2d", "one_long_row", "blockdiag"])
+@pytest.mark.parametrize("k", [0, 1, 3, 6, 8, 12, 13])
 @pytest.mark.parametrize("combo", range(3))
 def test_general_fp32(ctx, name, k, combo):
     ydt, acc = FP32_COMBOS[combo]
@@ -181,7 +217,9 @@ def test_general_fp32(ctx, name, k, combo):
     y_rounded, s_r = oracle.spmv(A32, x32.astype(np.float64))
     y_exact, s = oracle.spmv(A, x64)
     M = ctx.matrix_from_csr(A, with_f32=True)
-    P = ctx.plan_class(M, k)
+    P = _plan_class(ctx, M, A, k)
+    if P is None:
+        return
     y = ctx.spmv(P, dev(x32, torch.float32), ydtype=ydt, acc=acc).double().cpu().numpy()
     lens = np.diff(A.rowptr).astype(np.float64)
     # accumulation error alone (rounded inputs): recursive-summation bound

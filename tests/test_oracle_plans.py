@@ -338,3 +338,55 @@ def test_xcb_flag_walk_is_exact():
             y[i] += part[j]
         base += nk
     assert np.array_equal(y, oracle.spmv(A, x)[0])
+
+
+# ------------------------------------------------------------------ SELL-C-sigma
+def _sell_brute(A, C, sigma):
+    lens = np.diff(A.rowptr)
+    perm = []
+    for w0 in range(0, A.n, sigma):
+        perm += sorted(range(w0, min(w0 + sigma, A.n)), key=lambda r: (-lens[r], r))
+    rlen = [int(lens[r]) for r in perm]
+    clen = [max(rlen[c:c + C]) for c in range(0, A.n, C)]
+    cptr = [0]
+    for w in clen:
+        cptr.append(cptr[-1] + w * C)
+    cols = np.zeros(cptr[-1], dtype=np.int32)
+    vals = np.zeros(cptr[-1])
+    for r, row in enumerate(perm):
+        c, l = divmod(r, C)
+        for k in range(rlen[r]):
+            cols[cptr[c] + k * C + l] = A.colind[A.rowptr[row] + k]
+            vals[cptr[c] + k * C + l] = A.val[A.rowptr[row] + k]
+    return perm, rlen, clen, cptr, cols, vals
+
+
+@pytest.mark.parametrize("case", sorted(ADVERSARIAL))
+@pytest.mark.parametrize("C,sigma", [(4, 4), (4, 16), (64, 64), (2, 8)])
+def test_plan_sell_brute(case, C, sigma):
+    """Rows ordered longest first inside each sigma-window (ties by row),
+    chunks of C padded column-major to their longest row."""
+    A = _mat(ADVERSARIAL[case] * 3, seed=5, ncols=60)
+    p = oracle.plan_sell(A, C, sigma)
+    perm, rlen, clen, cptr, cols, vals = _sell_brute(A, C, sigma)
+    assert p["perm"].tolist() == perm and p["rlen"].tolist() == rlen
+    assert p["clen"].tolist() == clen and p["cptr"].tolist() == cptr
+    assert np.array_equal(p["cols"], cols) and np.array_equal(p["vals"], vals)
+
+
+def test_sell_walk_is_exact():
+    """Row sums over the padded chunks, written back through perm, give A x
+    exactly (integer values)."""
+    A = _mat([3, 0, 7, 1, 12, 0, 5, 9, 9, 2] * 13, seed=7, ncols=90)
+    x = gen.int_vec(A.ncols, 2)
+    C = 8
+    p = oracle.plan_sell(A, C, 32)
+    y = np.full(A.n, np.nan)
+    for r in range(A.n):
+        c, l = divmod(r, C)
+        s = 0.0
+        for k in range(p["rlen"][r]):
+            q = p["cptr"][c] + k * C + l
+            s += p["vals"][q] * x[p["cols"][q]]
+        y[p["perm"][r]] = s
+    assert np.array_equal(y, oracle.spmv(A, x)[0])
