@@ -1,0 +1,140 @@
+"""Pins of the oracle's thick-restart Lanczos against closed forms, a library
+eigensolver and invariants (no GPU)."""
+import numpy as np
+import pytest
+
+import gen
+from oracle import eig
+
+
+def lap1d(n):
+    """tridiag(-1, 2, -1): eigenvalues 2 - 2 cos(k pi / (n + 1)), all simple."""
+    rp = [0]
+    ci, v = [], []
+    for i in range(n):
+        for j, a in ((i - 1, -1.0), (i, 2.0), (i + 1, -1.0)):
+            if 0 <= j < n:
+                ci.append(j)
+                v.append(a)
+        rp.append(len(ci))
+    return gen.CSR(n, n, np.array(rp, np.int32), np.array(ci, np.int32), np.array(v), name=f"lap1d_{n}")
+
+
+def from_dense(D, lower=False):
+    n = D.shape[0]
+    rp, ci, v = [0], [], []
+    for i in range(n):
+        for j in range(n):
+            if D[i, j] != 0.0 and (not lower or j <= i):
+                ci.append(j)
+                v.append(D[i, j])
+        rp.append(len(ci))
+    return gen.CSR(n, n, np.array(rp, np.int32), np.array(ci, np.int32), np.array(v), sym_lower=lower,
+                   name="dense")
+
+
+def st27_eigs(g):
+    """Closed-form spectrum of 28 I - T (x) T (x) T, T = tridiag(1, 1, 1) of order g
+    (the 27-point stencil with 27 on the diagonal and -1 off it)."""
+    t = 1.0 + 2.0 * np.cos(np.arange(1, g + 1) * np.pi / (g + 1))
+    return np.sort((28.0 - np.einsum("i,j,k->ijk", t, t, t)).ravel())
+
+
+@pytest.mark.parametrize("which", [eig.LARGEST, eig.SMALLEST])
+def test_lap1d_closed_form(which):
+    n = 400
+    A = lap1d(n)
+    r = eig.lanczos(A, 10, 30, gen.uniform_vec(n, 1), tol=1e-8, which=which)
+    assert r["status"] == eig.OK and r["restarts"] > 5  # the restart path is exercised
+    k = np.arange(1, n + 1)
+    lam = 2.0 - 2.0 * np.cos(k * np.pi / (n + 1))
+    want = np.sort(lam)[::-1][:10] if which == eig.LARGEST else np.sort(lam)[:10]
+    assert np.max(np.abs(r["evals"] - want)) <= 1e-10 * r["anrm"]
+    # eigenvectors: sin(k j pi / (n + 1)), normalised, up to sign
+    for i in range(10):
+        kk = int(np.argmin(np.abs(lam - r["evals"][i]))) + 1
+        u = np.sin(kk * np.arange(1, n + 1) * np.pi / (n + 1))
+        u /= np.linalg.norm(u)
+        assert abs(abs(u @ r["evecs"][:, i]) - 1.0) <= 1e-8
+    assert np.max(r["resid"]) <= 1.5e-8 * r["anrm"]
+
+
+def test_diagonal_distinct():
+    d = np.linspace(1.0, 3.0, 300) ** 2
+    A = from_dense(np.diag(d))
+    r = eig.lanczos(A, 10, 24, gen.uniform_vec(300, 2), tol=1e-10)
+    assert r["status"] == eig.OK
+    assert np.max(np.abs(r["evals"] - np.sort(d)[::-1][:10])) <= 1e-12 * r["anrm"]
+    top = np.argsort(-d)[:10]
+    for i in range(10):
+        assert abs(abs(r["evecs"][top[i], i]) - 1.0) <= 1e-8
+
+
+def test_full_space_one_cycle_matches_eigh():
+    """m = n: the Krylov space is the whole space after one cycle, so every
+    Ritz value equals an eigenvalue of the dense matrix (LAPACK's)."""
+    rng = np.random.default_rng(3)
+    M = rng.standard_normal((40, 40))
+    D = M + M.T
+    r = eig.lanczos(from_dense(D), 6, 40, rng.standard_normal(40), tol=1e-12)
+    assert r["status"] == eig.OK and r["restarts"] == 0
+    ref = np.linalg.eigvalsh(D)[::-1][:6]
+    assert np.max(np.abs(r["evals"] - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def test_random_sparse_vs_eigh_and_lower_equals_full():
+    rng = np.random.default_rng(4)
+    n = 300
+    D = np.zeros((n, n))
+    for i in range(n):
+        for j in rng.choice(n, 6, replace=False):
+            D[i, j] = D[j, i] = rng.standard_normal()
+    D += np.diag(rng.uniform(-2, 2, n))
+    v0 = gen.uniform_vec(n, 9)
+    full = eig.lanczos(from_dense(D), 8, 32, v0, tol=1e-9)
+    low = eig.lanczos(from_dense(D, lower=True), 8, 32, v0, tol=1e-9)
+    ref = np.linalg.eigvalsh(D)[::-1][:8]
+    for r in (full, low):
+        assert r["status"] == eig.OK
+        assert np.max(np.abs(r["evals"] - ref)) <= 1e-9 * r["anrm"]
+        X = r["evecs"]
+        assert np.max(np.abs(X.T @ X - np.eye(8))) <= 1e-10
+        assert np.max(r["resid"]) <= 1.5e-9 * r["anrm"]
+    assert np.max(np.abs(full["evals"] - low["evals"])) <= 1e-11 * full["anrm"]
+
+
+def test_st27_values_are_eigenvalues():
+    """The lower-stored 27-point stencil on a 12^3 grid has eigenvalues of
+    multiplicity 3 and 6, so which copies a single-vector Lanczos finds is
+    rounding-dependent; what is fixed: the first value is the largest
+    eigenvalue, every value is one of the closed form's, and each Ritz pair
+    meets the residual bound."""
+    g = 12
+    A = gen.stencil27(g)
+    r = eig.lanczos(A, 10, 40, gen.uniform_vec(A.n, 5), tol=1e-8)
+    assert r["status"] == eig.OK
+    lam = st27_eigs(g)
+    assert abs(r["evals"][0] - lam[-1]) <= 1e-9 * r["anrm"]
+    for t in r["evals"]:
+        assert np.min(np.abs(lam - t)) <= 1e-9 * r["anrm"]
+    assert np.all(np.diff(r["evals"]) <= 0)
+    assert np.max(r["resid"]) <= 1.5e-8 * r["anrm"]
+
+
+def test_breakdown_small_invariant_space():
+    """A start vector inside a 3-dimensional eigenspace sum: the recurrence
+    stops at 3 vectors, fewer than nev = 4, which is a breakdown."""
+    d = np.arange(1.0, 31.0)
+    A = from_dense(np.diag(d))
+    v0 = np.zeros(30)
+    v0[[2, 7, 11]] = 1.0
+    r = eig.lanczos(A, 4, 10, v0)
+    assert r["status"] == eig.BREAKDOWN
+    r = eig.lanczos(A, 2, 10, v0)  # nev within the invariant space: exact
+    assert r["status"] == eig.OK
+    assert np.allclose(r["evals"], [12.0, 8.0], atol=1e-13)
+
+
+def test_kept_count():
+    assert eig.kept_count(10, 30) == 20
+    assert eig.kept_count(10, 11) == 10
