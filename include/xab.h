@@ -118,6 +118,7 @@ typedef struct {
 #define XAB_GENERAL 0u
 #define XAB_SYM_LOWER 1u   /* symmetric; only entries with col <= row are stored */
 #define XAB_TRUST_INPUT 2u /* skip the structural validation pass */
+#define XAB_BATCH_TILES 4u /* xab_batch_csr: segmented-scan tiles only, no sliced ELLPACK copy */
 
 /* Selector classes: fixed (variant, params) pairs, the action space of the
  * selector.  0..8, 12 and 13 apply to general matrices, 9..11 to
@@ -337,11 +338,21 @@ int xab_gmres(xab_ctx *ctx, const xab_plan *plan, const double *d_b, double *d_x
  * system k owns rows [h_row_off[k], h_row_off[k+1]) and entries
  * [h_nnz_off[k], h_nnz_off[k+1]); d_rowptr holds global offsets and
  * d_colind global column indices (inside the system's own row range).
+ * The arrays are borrowed and must outlive the batch.  Unless flags has
+ * XAB_BATCH_TILES, the batch also keeps its own sliced ELLPACK copy
+ * (SELL-C-sigma, C = 64, sigma = 1024: about 12 (FP64) or 8 (FP32) bytes per
+ * entry plus padding) and its SpMV runs on that copy; a batch outside the
+ * copy's limits (a row longer than 4096 entries, or padding beyond
+ * nnz + 64 * longest row) silently uses the segmented-scan tiles instead.
  * Synchronous (validates unless flags has XAB_TRUST_INPUT). */
 int xab_batch_csr(xab_ctx *ctx, int32_t nsys, const int64_t *h_row_off, const int64_t *h_nnz_off,
                   const int32_t *d_rowptr, const int32_t *d_colind, const void *d_val, xab_dtype vt,
                   uint32_t flags, xab_batch **batch);
 void xab_batch_destroy(xab_batch *batch);
+/* Layout the batch's SpMV runs on: 1 = its sliced ELLPACK copy, 0 = the
+ * segmented-scan tiles (XAB_BATCH_TILES, or outside the copy's limits);
+ * -1 for a null batch. */
+int xab_batch_layout(const xab_batch *batch);
 /* y = blockdiag(A_k) x over all systems in one persistent launch.
  * Asynchronous. */
 int xab_batch_spmv(xab_ctx *ctx, const xab_batch *batch, const void *d_x, void *d_y);

@@ -18,7 +18,7 @@ TIME, STABLE, LEARNED = 0, 1, 2
 ROW, NNZ, BSS, SYM_S3, SYM_ATOMIC, XCB, SELL = 0, 1, 2, 3, 4, 5, 6
 VARIANT_NAMES = {ROW: "row", NNZ: "nnz", BSS: "bss", SYM_S3: "sym_s3", SYM_ATOMIC: "sym_atomic", XCB: "xcb",
                  SELL: "sell"}
-GENERAL, SYM_LOWER, TRUST_INPUT = 0, 1, 2
+GENERAL, SYM_LOWER, TRUST_INPUT, BATCH_TILES = 0, 1, 2, 4
 NCLASSES = 14
 GENERAL_CLASSES = tuple(range(9)) + (12, 13)
 SYM_CLASSES = (9, 10, 11)
@@ -115,6 +115,7 @@ SIGNATURES = {
     "xab_gmres": (ctypes.c_int, [_P, _P, _P, _P, ctypes.POINTER(KrylovOpts), ctypes.POINTER(KrylovInfo)]),
     "xab_batch_csr": (ctypes.c_int, [_P, _I32, _P, _P, _P, _P, _P, ctypes.c_int, _U32, _PP]),
     "xab_batch_destroy": (None, [_P]),
+    "xab_batch_layout": (ctypes.c_int, [_P]),
     "xab_batch_spmv": (ctypes.c_int, [_P, _P, _P, _P]),
     "xab_bicgstab": (ctypes.c_int, [_P, _P, _P, _P, ctypes.POINTER(KrylovOpts), _P, ctypes.POINTER(KrylovInfo)]),
 }
@@ -343,8 +344,8 @@ class Context:
                         "xab_gmres")
         return x, info.as_dict(), s
 
-    def batch(self, B, dtype="f64", trust=False):
-        return Batch(self, B, dtype, trust)
+    def batch(self, B, dtype="f64", trust=False, tiles=False):
+        return Batch(self, B, dtype, trust, tiles)
 
     def bicgstab(self, batch, b, x=None, tol=1e-10, maxiter=10000, precond=PRECOND_JACOBI, graph=True,
                  check_every=8):
@@ -442,7 +443,7 @@ class Plan:
 
 
 class Batch:
-    def __init__(self, ctx, B, dtype="f64", trust=False):
+    def __init__(self, ctx, B, dtype="f64", trust=False, tiles=False):
         torch = _torch()
         dev = f"cuda:{ctx.device}"
         self.ctx = ctx
@@ -458,9 +459,15 @@ class Batch:
         h = ctypes.c_void_p()
         ctx._check(lib().xab_batch_csr(ctx.h, self.nsys, self.row_off.ctypes.data_as(_P),
                                        self.nnz_off.ctypes.data_as(_P), _ptr(self.rowptr), _ptr(self.colind),
-                                       _ptr(self.val), _dt(self.val), TRUST_INPUT if trust else 0, ctypes.byref(h)),
+                                       _ptr(self.val), _dt(self.val),
+                                       (TRUST_INPUT if trust else 0) | (BATCH_TILES if tiles else 0), ctypes.byref(h)),
                    "xab_batch_csr")
         self.h = h
+
+    @property
+    def layout(self):
+        """'sell' when the SpMV runs on the batch's sliced ELLPACK copy, else 'tiles'."""
+        return "sell" if lib().xab_batch_layout(self.h) == 1 else "tiles"
 
     def spmv(self, x, y=None):
         torch = _torch()

@@ -18,6 +18,7 @@ using xab::Seg;
 constexpr int kNT = 256;
 constexpr int kBatchJ = 4;  // entries per lane of the batched SpMV tiles
 constexpr int kBiNT = 1024; // threads of the per-system solver kernels (one workgroup per system)
+constexpr int kSellSigma = 1024; // sorting window of the sliced ELLPACK copy
 
 
 // Batched SpMV over the concatenation, in segmented-scan tiles of
@@ -49,6 +50,58 @@ __global__ __launch_bounds__(kNT) void k_batch_spmv(const int32_t *__restrict__ 
     }
     xab::bss_tile<kNT, T, T, T, double, kBatchJ>(t, rowptr, colind, val, x, y, nnz, row_lo, carry_row, carry_val,
                                                  tail_val, tail_row, head_row, wave_tot, nullptr);
+}
+
+// Batched SpMV over the sliced ELLPACK copy of the concatenation (64 ordered
+// rows per chunk, one lane per row, one wave per chunk).  A chunk none of
+// whose rows belongs to an active system is skipped (its products are never
+// read); otherwise every row of the chunk is computed.
+constexpr int kSellC = xab_plan::kSellC;
+constexpr int kSellUnroll = 4;
+
+template <class T>
+__global__ __launch_bounds__(kNT) void k_batch_sell(const int64_t *__restrict__ cptr, const int32_t *__restrict__ clen,
+                                                    const int32_t *__restrict__ rlen, const int32_t *__restrict__ perm,
+                                                    const int32_t *__restrict__ cols, const T *__restrict__ val,
+                                                    const T *__restrict__ x, T *__restrict__ y, int32_t n, int64_t nch,
+                                                    int64_t nwg, const int32_t *__restrict__ sys_of_row,
+                                                    const int *__restrict__ active) {
+    const int64_t wg = xab::xcd_remap(blockIdx.x, nwg);
+    const int64_t c = wg * (kNT / kSellC) + threadIdx.x / kSellC;
+    if (c >= nch) return;
+    const int l = threadIdx.x % kSellC;
+    const int64_t r = c * kSellC + l;
+    const int32_t row = r < n ? perm[r] : -1;
+    if (active) {
+        const bool mine = row >= 0 && active[sys_of_row[row]] != 0;
+        if (__ballot(mine) == 0) return;  // wave-uniform: the wave is the chunk
+    }
+    const int32_t len = rlen[r];
+    const int32_t w = clen[c];
+    const int64_t base = cptr[c] + l;
+    double acc = 0.0;
+    int32_t k = 0;
+    for (; k + kSellUnroll <= w; k += kSellUnroll) {
+        T v[kSellUnroll];
+        int32_t cc[kSellUnroll];
+#pragma unroll
+        for (int u = 0; u < kSellUnroll; ++u) {
+            v[u] = __builtin_nontemporal_load(val + base + (int64_t)(k + u) * kSellC);
+            cc[u] = __builtin_nontemporal_load(cols + base + (int64_t)(k + u) * kSellC);
+        }
+#pragma unroll
+        for (int u = 0; u < kSellUnroll; ++u) {
+            const double p = (double)v[u] * (double)x[cc[u]];
+            acc = k + u < len ? acc + p : acc;
+        }
+    }
+    for (; k < w; ++k) {
+        const T v = __builtin_nontemporal_load(val + base + (int64_t)k * kSellC);
+        const int32_t cc = __builtin_nontemporal_load(cols + base + (int64_t)k * kSellC);
+        const double p = (double)v * (double)x[cc];
+        acc = k < len ? acc + p : acc;
+    }
+    if (row >= 0) y[row] = (T)acc;
 }
 
 // rows cut by a tile end: start partial plus the following tiles' carries,
@@ -343,6 +396,16 @@ unsigned grid_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 template <class T>
 void launch_batch_spmv(const xab_batch *B, const T *x, T *y, const int *active, hipStream_t st) {
+    if (B->sell.cols) {
+        const xab_sell &S = B->sell;
+        const T *pv;
+        if constexpr (sizeof(T) == 8) pv = (const T *)S.val64;
+        else pv = (const T *)S.val32;
+        const int64_t nwg = (S.nch + kNT / kSellC - 1) / (kNT / kSellC);
+        hipLaunchKernelGGL((k_batch_sell<T>), dim3((unsigned)nwg), dim3(kNT), 0, st, S.cptr, S.clen, S.rlen, S.perm,
+                           S.cols, pv, x, y, (int32_t)B->n, S.nch, nwg, B->d_sys_of_row, active);
+        return;
+    }
     hipLaunchKernelGGL((k_batch_spmv<T>), dim3((unsigned)B->P), dim3(kNT), 0, st, B->rowptr, B->colind,
                        (const T *)B->val, x, y, B->nnz, B->P, B->row_lo, B->tile_row, B->carry_row, B->carry_val,
                        B->tail_val, B->tail_row, B->d_sys_of_row, (int32_t)B->n, active);
@@ -578,6 +641,17 @@ int xab_batch_csr(xab_ctx *ctx, int32_t nsys, const int64_t *h_row_off, const in
         xab_batch_destroy(B);
         return xab_fail(ctx, XAB_E_STRUCT, "a system has columns outside its own rows");
     }
+    // the sliced ELLPACK copy, unless asked for the tiles alone or outside its
+    // limits (then the tiles serve)
+    if (!(flags & XAB_BATCH_TILES) && n > 0) {
+        s = xab_sell_build(ctx, d_rowptr, d_colind, vt == XAB_F64 ? (const double *)d_val : nullptr,
+                           vt == XAB_F32 ? (const float *)d_val : nullptr, vt == XAB_F64, vt == XAB_F32, (int32_t)n,
+                           nnz, kSellSigma, &B->sell);
+        if (s != XAB_OK && s != XAB_E_UNSUPPORTED) {
+            xab_batch_destroy(B);
+            return s;
+        }
+    }
     *out = B;
     return XAB_OK;
 }
@@ -594,7 +668,13 @@ void xab_batch_destroy(xab_batch *B) {
     xab_dfree(B->ctx, B->diag);
     xab_dfree(B->ctx, B->d_sys_of_row);
     xab_dfree(B->ctx, B->d_row_off);
+    xab_sell_free(B->ctx, &B->sell);
     delete B;
+}
+
+int xab_batch_layout(const xab_batch *B) {
+    if (!B) return -1;
+    return B->sell.cols ? 1 : 0;
 }
 
 int xab_batch_spmv(xab_ctx *ctx, const xab_batch *B, const void *d_x, void *d_y) {

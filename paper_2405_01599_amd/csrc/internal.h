@@ -49,6 +49,21 @@ struct xab_matrix {
     float *diag32 = nullptr;
 };
 
+// Sliced ELLPACK copy of a CSR (SELL-C-sigma, C = 64): rows ordered longest
+// first inside windows of sigma rows, chunks of 64 ordered rows stored
+// column-major and padded to the chunk's longest row.
+struct xab_sell {
+    int64_t nch = 0, total = 0;  // chunks, padded entries
+    int32_t sigma = 0;
+    int32_t *perm = nullptr;     // original row of ordered row r
+    int32_t *rlen = nullptr;     // length of ordered row r (nch * 64 slots, 0 past n)
+    int32_t *clen = nullptr;     // chunk widths
+    int64_t *cptr = nullptr;     // [nch + 2] chunk offsets, padded size, widest chunk
+    int32_t *cols = nullptr;     // padded columns (padding: 0)
+    double *val64 = nullptr;     // padded values (padding: 0)
+    float *val32 = nullptr;
+};
+
 struct xab_plan {
     xab_ctx *ctx = nullptr;
     const xab_matrix *A = nullptr;
@@ -92,14 +107,7 @@ struct xab_plan {
     // SELL: chunks of kSellC ordered rows, column-major, padded to the chunk's longest row
     static constexpr int kSellC = 64;
     static constexpr int kSellMaxRow = 4096;
-    int64_t sell_nch = 0, sell_total = 0;  // chunks, padded entries
-    int32_t *sell_perm = nullptr;          // original row of ordered row r
-    int32_t *sell_rlen = nullptr;          // length of ordered row r (nch * C slots, 0 past n)
-    int32_t *sell_clen = nullptr;          // chunk widths
-    int64_t *sell_cptr = nullptr;          // chunk offsets [nch + 2]: offsets, then the widest chunk
-    int32_t *sell_cols = nullptr;          // padded columns (padding: 0)
-    double *sell_val64 = nullptr;          // padded values (padding: 0)
-    float *sell_val32 = nullptr;
+    xab_sell sell;
 };
 
 struct xab_batch {
@@ -117,6 +125,7 @@ struct xab_batch {
     int32_t *d_sys_of_row = nullptr; // system index of every row
     int64_t *d_row_off = nullptr;    // [nsys+1]
     void *diag = nullptr;            // Jacobi diagonal (value type; lazy, library-owned)
+    xab_sell sell;                   // sliced ELLPACK copy (when within its limits): the SpMV of choice
 };
 
 // ------------------------------------------------------------------ helpers
@@ -141,6 +150,12 @@ void *xab_scratch(xab_ctx *ctx, size_t bytes);
 
 // plan builders (plan.hip)
 int xab_build_plan(xab_ctx *ctx, const xab_matrix *A, xab_variant v, const xab_params *p, xab_plan **out);
+// SELL copy of a CSR (plan.hip): XAB_E_UNSUPPORTED when a row is longer
+// than 4096 or the padded size exceeds 2 nnz + 64 * (longest row); the
+// arrays are then freed.  Synchronous.
+int xab_sell_build(xab_ctx *ctx, const int32_t *rowptr, const int32_t *colind, const double *v64, const float *v32,
+                   bool has64, bool has32, int32_t n, int64_t nnz, int32_t sigma, xab_sell *out);
+void xab_sell_free(xab_ctx *ctx, xab_sell *s);
 // segmented-scan tile descriptors (row_lo, tile_row [P+1], carry_row [P]) of a
 // CSR with T entries per tile, queued on `st`
 void xab_launch_split_bss(hipStream_t st, const int32_t *rowptr, int32_t n, int64_t T, int64_t P, int32_t *row_lo,

@@ -489,13 +489,7 @@ static void free_plan_arrays(xab_ctx *ctx, xab_plan *pl) {
     xab_dfree(ctx, pl->xcb_gbase);
     xab_dfree(ctx, pl->s3_ci);
     xab_dfree(ctx, pl->s3_dense);
-    xab_dfree(ctx, pl->sell_perm);
-    xab_dfree(ctx, pl->sell_rlen);
-    xab_dfree(ctx, pl->sell_clen);
-    xab_dfree(ctx, pl->sell_cptr);
-    xab_dfree(ctx, pl->sell_cols);
-    xab_dfree(ctx, pl->sell_val64);
-    xab_dfree(ctx, pl->sell_val32);
+    xab_sell_free(ctx, &pl->sell);
     xab_dfree(ctx, pl->xcb_mask);
     xab_dfree(ctx, pl->xcb_colind);
     xab_dfree(ctx, pl->xcb_val64);
@@ -530,6 +524,77 @@ static void free_plan_arrays(xab_ctx *ctx, xab_plan *pl) {
     } while (0)
 
 static int hip_ok(xab_ctx *ctx, hipError_t e, const char *w) { return xab_hip_check(ctx, e, w); }
+
+void xab_sell_free(xab_ctx *ctx, xab_sell *s) {
+    xab_dfree(ctx, s->perm);
+    xab_dfree(ctx, s->rlen);
+    xab_dfree(ctx, s->clen);
+    xab_dfree(ctx, s->cptr);
+    xab_dfree(ctx, s->cols);
+    xab_dfree(ctx, s->val64);
+    xab_dfree(ctx, s->val32);
+    *s = xab_sell{};
+}
+
+int xab_sell_build(xab_ctx *ctx, const int32_t *rowptr, const int32_t *colind, const double *v64, const float *v32,
+                   bool has64, bool has32, int32_t n, int64_t nnz, int32_t sigma, xab_sell *out) {
+    constexpr int C = xab_plan::kSellC;
+    hipStream_t st = ctx->stream;
+    xab_sell &S = *out;
+    S = xab_sell{};
+    S.sigma = sigma;
+    const int64_t nch = std::max<int64_t>(1, ((int64_t)n + C - 1) / C);
+    S.nch = nch;
+    S.perm = (int32_t *)xab_dalloc(ctx, sizeof(int32_t) * (size_t)std::max<int32_t>(1, n));
+    S.rlen = (int32_t *)xab_dalloc(ctx, sizeof(int32_t) * (size_t)(nch * C));
+    S.clen = (int32_t *)xab_dalloc(ctx, sizeof(int32_t) * (size_t)nch);
+    S.cptr = (int64_t *)xab_dalloc(ctx, sizeof(int64_t) * (size_t)(nch + 2));
+    if (!S.perm || !S.rlen || !S.clen || !S.cptr) {
+        xab_sell_free(ctx, &S);
+        return xab_fail(ctx, XAB_E_NOMEM, "SELL layout");
+    }
+    hipLaunchKernelGGL(k_zero_i32, dim3(grid_for(nch * C, 256)), dim3(256), 0, st, S.rlen, nch * C);
+    if (n > 0) {
+        int P2 = 64;
+        while (P2 < sigma) P2 <<= 1;
+        hipLaunchKernelGGL(k_sell_sort, dim3(grid_for(n, sigma)), dim3(P2), 0, st, rowptr, n, sigma, S.perm, S.rlen);
+    }
+    hipLaunchKernelGGL(k_sell_widths, dim3(grid_for(nch, 256)), dim3(256), 0, st, S.rlen, n, nch, S.clen);
+    hipLaunchKernelGGL(k_sell_scan, dim3(1), dim3(1024), 0, st, S.clen, nch, S.cptr);
+    int64_t hdr[2] = {0, 0};
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(hdr, S.cptr + nch, sizeof(hdr), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        xab_sell_free(ctx, &S);
+        return xab_hip_check(ctx, e, "SELL layout");
+    }
+    S.total = hdr[0];
+    // limits: rows of at most 4096 entries (one lane sums a row) and
+    // padding at most the entries themselves plus one chunk of the widest row
+    if (hdr[1] > xab_plan::kSellMaxRow || hdr[0] > 2 * nnz + (int64_t)C * hdr[1]) {
+        xab_sell_free(ctx, &S);
+        return xab_fail(ctx, XAB_E_UNSUPPORTED, "SELL: %s",
+                        hdr[1] > xab_plan::kSellMaxRow ? "a row is longer than 4096" : "padding would exceed the entries");
+    }
+    const size_t tot = (size_t)std::max<int64_t>(1, S.total);
+    S.cols = (int32_t *)xab_dalloc(ctx, sizeof(int32_t) * tot);
+    if (has64) S.val64 = (double *)xab_dalloc(ctx, sizeof(double) * tot);
+    if (has32) S.val32 = (float *)xab_dalloc(ctx, sizeof(float) * tot);
+    if (!S.cols || (has64 && !S.val64) || (has32 && !S.val32)) {
+        xab_sell_free(ctx, &S);
+        return xab_fail(ctx, XAB_E_NOMEM, "SELL copy");
+    }
+    hipLaunchKernelGGL(k_sell_fill, dim3(grid_for(nch * C, 256)), dim3(256), 0, st, rowptr, colind, v64, v32, n, nch,
+                       S.perm, S.rlen, S.cptr, S.clen, S.cols, S.val64, S.val32);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        xab_sell_free(ctx, &S);
+        return xab_hip_check(ctx, e, "SELL fill");
+    }
+    return XAB_OK;
+}
 
 void xab_launch_split_bss(hipStream_t st, const int32_t *rowptr, int32_t n, int64_t T, int64_t P, int32_t *row_lo,
                           int32_t *tile_row, int32_t *carry_row) {
@@ -607,49 +672,14 @@ int xab_build_plan(xab_ctx *ctx, const xab_matrix *A, xab_variant v, const xab_p
                            pl->row_lo, pl->tile_row, pl->carry_row);
         CHECKED(hip_ok(ctx, hipGetLastError(), "k_split_bss"));
     } else if (v == XAB_SELL) {
-        constexpr int C = xab_plan::kSellC;
-        const int32_t sigma = p.tile_rows;
-        const int64_t nch = std::max<int64_t>(1, ((int64_t)n + C - 1) / C);
-        pl->sell_nch = nch;
-        pl->P = nch;
-        ALLOC(pl->sell_perm, int32_t, std::max<int32_t>(1, n));
-        ALLOC(pl->sell_rlen, int32_t, nch * C);
-        ALLOC(pl->sell_clen, int32_t, nch);
-        ALLOC(pl->sell_cptr, int64_t, nch + 2);
-        hipLaunchKernelGGL(k_zero_i32, dim3(grid_for(nch * C, 256)), dim3(256), 0, st, pl->sell_rlen, nch * C);
-        if (n > 0) {
-            int P2 = 64;
-            while (P2 < sigma) P2 <<= 1;
-            hipLaunchKernelGGL(k_sell_sort, dim3(grid_for(n, sigma)), dim3(P2), 0, st, A->rowptr, n, sigma,
-                               pl->sell_perm, pl->sell_rlen);
-        }
-        hipLaunchKernelGGL(k_sell_widths, dim3(grid_for(nch, 256)), dim3(256), 0, st, pl->sell_rlen, n, nch,
-                           pl->sell_clen);
-        hipLaunchKernelGGL(k_sell_scan, dim3(1), dim3(1024), 0, st, pl->sell_clen, nch, pl->sell_cptr);
-        int64_t hdr[2] = {0, 0};
-        hipError_t e = hipGetLastError();
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(hdr, pl->sell_cptr + nch, sizeof(hdr), hipMemcpyDeviceToHost, st);
-        if (e == hipSuccess) e = hipStreamSynchronize(st);
-        CHECKED(hip_ok(ctx, e, "SELL layout"));
-        pl->sell_total = hdr[0];
-        // limits: rows of at most 4096 entries (one lane sums a row) and
-        // padding at most the entries themselves plus one chunk of the widest row
-        if (hdr[1] > xab_plan::kSellMaxRow || hdr[0] > 2 * nnz + (int64_t)C * hdr[1]) {
+        pl->P = std::max<int64_t>(1, ((int64_t)n + xab_plan::kSellC - 1) / xab_plan::kSellC);
+        const int s = xab_sell_build(ctx, A->rowptr, A->colind, A->val64, A->val32, A->has64, A->has32, n, nnz,
+                                     p.tile_rows, &pl->sell);
+        if (s != XAB_OK) {
             free_plan_arrays(ctx, pl);
             delete pl;
-            return xab_fail(ctx, XAB_E_UNSUPPORTED, "SELL: %s", hdr[1] > xab_plan::kSellMaxRow
-                                                                   ? "a row is longer than 4096"
-                                                                   : "padding would exceed the entries");
+            return s;
         }
-        const int64_t tot = std::max<int64_t>(1, pl->sell_total);
-        ALLOC(pl->sell_cols, int32_t, tot);
-        if (A->has64) ALLOC(pl->sell_val64, double, tot);
-        if (A->has32) ALLOC(pl->sell_val32, float, tot);
-        hipLaunchKernelGGL(k_sell_fill, dim3(grid_for(nch * C, 256)), dim3(256), 0, st, A->rowptr, A->colind,
-                           A->val64, A->val32, n, nch, pl->sell_perm, pl->sell_rlen, pl->sell_cptr, pl->sell_clen,
-                           pl->sell_cols, pl->sell_val64, pl->sell_val32);
-        CHECKED(hip_ok(ctx, hipGetLastError(), "SELL fill"));
     } else if (v == XAB_XCB) {
         constexpr int KB = xab_plan::kXcb;
         const int64_t T = 256 * (int64_t)p.j_per_lane;
@@ -990,10 +1020,10 @@ int xab_plan_array(const xab_plan *pl, int32_t which, int32_t *h_out, int64_t *l
         case 8: src = pl->tile_slot; m = pl->tile_slot ? pl->ntouch : 0; break;
         case 9: src = pl->xcb_rowptr; m = pl->xcb_rowptr ? (int64_t)xab_plan::kXcb * (pl->A->n + 1) : 0; break;
         case 10: src = pl->xcb_colind; m = pl->xcb_colind ? pl->A->nnz : 0; break;
-        case 11: src = pl->sell_perm; m = pl->sell_perm ? pl->A->n : 0; break;
-        case 12: src = pl->sell_rlen; m = pl->sell_rlen ? pl->A->n : 0; break;
-        case 13: src = pl->sell_clen; m = pl->sell_clen ? pl->sell_nch : 0; break;
-        case 14: src = pl->sell_cols; m = pl->sell_cols ? pl->sell_total : 0; break;
+        case 11: src = pl->sell.perm; m = pl->sell.perm ? pl->A->n : 0; break;
+        case 12: src = pl->sell.rlen; m = pl->sell.rlen ? pl->A->n : 0; break;
+        case 13: src = pl->sell.clen; m = pl->sell.clen ? pl->sell.nch : 0; break;
+        case 14: src = pl->sell.cols; m = pl->sell.cols ? pl->sell.total : 0; break;
         default: return XAB_E_SHAPE;
     }
     *len = m;

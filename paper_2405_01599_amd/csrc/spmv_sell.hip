@@ -57,15 +57,15 @@ __global__ __launch_bounds__(kNT) void k_spmv_sell(const int64_t *__restrict__ c
 template <class VT, class XT, class YT, class AT>
 int launch_sell(xab_ctx *ctx, const xab_plan *pl, const VT *val, const XT *x, YT *y) {
     (void)val;  // the plan holds its own padded copy of the values
+    const xab_sell &S = pl->sell;
     const VT *pv;
-    if constexpr (sizeof(VT) == 8) pv = (const VT *)pl->sell_val64;
-    else pv = (const VT *)pl->sell_val32;
+    if constexpr (sizeof(VT) == 8) pv = (const VT *)S.val64;
+    else pv = (const VT *)S.val32;
     if (!pv) return xab_fail(ctx, XAB_E_DTYPE, "SELL plan holds no values of this precision");
     if (pl->A->n == 0) return XAB_OK;
-    const int64_t nwg = (pl->sell_nch + kNT / kC - 1) / (kNT / kC);
-    hipLaunchKernelGGL((k_spmv_sell<VT, XT, YT, AT>), dim3((unsigned)nwg), dim3(kNT), 0, ctx->stream, pl->sell_cptr,
-                       pl->sell_clen, pl->sell_rlen, pl->sell_perm, pl->sell_cols, pv, x, y, pl->A->n, pl->sell_nch,
-                       nwg);
+    const int64_t nwg = (S.nch + kNT / kC - 1) / (kNT / kC);
+    hipLaunchKernelGGL((k_spmv_sell<VT, XT, YT, AT>), dim3((unsigned)nwg), dim3(kNT), 0, ctx->stream, S.cptr, S.clen,
+                       S.rlen, S.perm, S.cols, pv, x, y, pl->A->n, S.nch, nwg);
     XAB_LAUNCH_CHECK(ctx, "k_spmv_sell");
     return XAB_OK;
 }

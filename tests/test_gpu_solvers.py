@@ -145,13 +145,23 @@ def _batch(nsys=12, nmin=300, nmax=3000):
     return gen.batch(nsys, seed=4, nmin=nmin, nmax=nmax)
 
 
-def test_batch_spmv_integer_exact(ctx):
+@pytest.mark.parametrize("tiles", [False, True])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_batch_spmv_integer_exact(ctx, tiles, dtype):
+    """Both layouts (the sliced ELLPACK copy and the segmented-scan tiles),
+    both precisions: small integers make every sum exact."""
     B = _batch()
     rng = np.random.default_rng(1)
     B.val = rng.integers(-8, 9, B.nnz).astype(np.float64)
     x = gen.int_vec(B.n, 3)
-    bt = ctx.batch(B)
-    y = bt.spmv(dev(x)).cpu().numpy()
+    bt = ctx.batch(B, dtype=dtype, tiles=tiles)
+    assert bt.layout == ("tiles" if tiles else "sell")
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    y = bt.spmv(dev(x, tdt)).double().cpu().numpy()
+    _batch_check_exact(B, x, y)
+
+
+def _batch_check_exact(B, x, y):
     for k in range(B.nsys):
         S = B.system(k)
         r0, r1 = int(B.row_off[k]), int(B.row_off[k + 1])
@@ -159,10 +169,47 @@ def test_batch_spmv_integer_exact(ctx):
         assert np.array_equal(y[r0:r1], yo)
 
 
-@pytest.mark.parametrize("graph", [True, False])
-def test_bicgstab_batch_fp64(ctx, graph):
-    B = _batch()
+def _long_row_batch():
+    """Three systems: the first has a 5000-entry row (beyond the sliced copy's
+    4096 limit) and an empty row, the second is empty, the third diagonal."""
+    n0 = 6000
+    rows = [list(range(5000))] + [[]] + [[i] for i in range(2, n0)] + [[n0 + i] for i in range(40)]
+    rp = np.zeros(len(rows) + 1, dtype=np.int32)
+    rp[1:] = np.cumsum([len(r) for r in rows])
+    ci = np.array([c for r in rows for c in r], dtype=np.int32)
+    v = np.random.default_rng(5).integers(-8, 9, ci.size).astype(np.float64)
+    row_off = np.array([0, n0, n0, n0 + 40])
+    nnz_off = np.array([0, int(rp[n0]), int(rp[n0]), int(rp[-1])])
+    return gen.Batch(3, row_off, nnz_off, rp, ci, v, np.zeros(3), np.zeros(3))
+
+
+def test_batch_long_row_uses_tiles(ctx):
+    B = _long_row_batch()
+    x = gen.int_vec(B.n, 7)
     bt = ctx.batch(B)
+    assert bt.layout == "tiles"
+    _batch_check_exact(B, x, bt.spmv(dev(x)).cpu().numpy())
+
+
+def test_batch_sell_empty_system_and_rows(ctx):
+    """Empty systems and empty rows through the sliced copy."""
+    rows = [[0, 2], [], [0, 1, 2]] + [[3 + i % 5] for i in range(5)]
+    rp = np.zeros(len(rows) + 1, dtype=np.int32)
+    rp[1:] = np.cumsum([len(r) for r in rows])
+    ci = np.array([c for r in rows for c in r], dtype=np.int32)
+    v = np.arange(1, ci.size + 1, dtype=np.float64)
+    B = gen.Batch(3, np.array([0, 3, 3, 8]), np.array([0, 5, 5, int(rp[-1])]), rp, ci, v, np.zeros(3), np.zeros(3))
+    x = gen.int_vec(B.n, 2)
+    bt = ctx.batch(B)
+    assert bt.layout == "sell"
+    _batch_check_exact(B, x, bt.spmv(dev(x)).cpu().numpy())
+
+
+@pytest.mark.parametrize("tiles", [False, True])
+@pytest.mark.parametrize("graph", [True, False])
+def test_bicgstab_batch_fp64(ctx, graph, tiles):
+    B = _batch()
+    bt = ctx.batch(B, tiles=tiles)
     b = np.ones(B.n)
     x, per, agg, st = ctx.bicgstab(bt, dev(b), tol=1e-10, graph=graph, check_every=4)
     assert st == 0
@@ -179,18 +226,20 @@ def test_bicgstab_batch_fp64(ctx, graph):
         assert abs(per[k]["iters"] - ref["iters"]) <= max(2, 0.25 * ref["iters"])
 
 
-def test_bicgstab_graph_equals_eager(ctx):
+@pytest.mark.parametrize("tiles", [False, True])
+def test_bicgstab_graph_equals_eager(ctx, tiles):
     B = _batch(8)
-    bt = ctx.batch(B)
+    bt = ctx.batch(B, tiles=tiles)
     b = dev(np.ones(B.n))
     x1, _, _, _ = ctx.bicgstab(bt, b, tol=1e-10, graph=True, check_every=4)
     x2, _, _, _ = ctx.bicgstab(bt, b, tol=1e-10, graph=False, check_every=4)
     assert torch.equal(x1, x2)
 
 
-def test_bicgstab_batch_fp32(ctx):
+@pytest.mark.parametrize("tiles", [False, True])
+def test_bicgstab_batch_fp32(ctx, tiles):
     B = _batch(10)
-    bt = ctx.batch(B, dtype="f32")
+    bt = ctx.batch(B, dtype="f32", tiles=tiles)
     b = np.ones(B.n)
     x, per, agg, st = ctx.bicgstab(bt, dev(b, torch.float32), tol=1e-5, graph=True)
     assert st == 0
@@ -296,7 +345,7 @@ def test_gmres_accuracy_policy(ctx):
         assert st == 0 and inf["faults"] == 0 and inf["ortho"] == want
     # mixed precision: the rule reads the inner solve's requirement (1e-6)
     M32 = ctx.matrix_from_csr(A, with_f32=True)
-    x, inf, st = ctx.gmres(ctx.plan_class(M32, 5), dev(b), m=30, tol=1e-10, maxiter=1500, mode=MODE_IR,
+    x, inf, st = ctx.gmres(ctx.plan_class(M32, 5), dev(b), m=30, tol=1e-10, maxiter=1500, mode=xab.MODE_IR,
                            precond=xab.PRECOND_NONE, ortho=xab.ORTHO_POLICY)
     assert st == 0 and inf["ortho"] == xab.ORTHO_BCGS
     ref = oracle.gmres_at(A, b, 30, 30, 0, 0.0, tol=1e-15, maxiter=600, ortho=oracle.ORTHO_POLICY)
