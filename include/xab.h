@@ -334,6 +334,48 @@ typedef struct {
 int xab_gmres(xab_ctx *ctx, const xab_plan *plan, const double *d_b, double *d_x, const xab_krylov_opts *opts,
               xab_krylov_info *info);
 
+/* Restarted Lanczos (section 2.2 solver list, section 4.3 setting). */
+#define XAB_EIG_LARGEST 0  /* largest algebraic eigenvalues */
+#define XAB_EIG_SMALLEST 1 /* smallest algebraic eigenvalues */
+
+typedef struct {
+    int32_t nev;        /* wanted eigenpairs, >= 1 */
+    int32_t m;          /* basis vectors per cycle, nev < m <= min(63, n) */
+    double tol;         /* residual requirement relative to the ||A|| estimate (section 4.3: 1e-8) */
+    int64_t maxiter;    /* products with A in the recurrence; <= 0: unlimited */
+    double max_time_s;  /* wall-clock limit (the policy's MAXTIME); <= 0: none */
+    int32_t which;      /* XAB_EIG_LARGEST or XAB_EIG_SMALLEST */
+} xab_eig_opts;
+
+typedef struct {
+    int64_t iters;      /* products with A in the recurrence */
+    int64_t restarts;   /* thick restarts */
+    int32_t nconv;      /* wanted pairs whose residual estimate met tol at exit */
+    double anrm;        /* largest |Ritz value| seen: the ||A|| estimate */
+    double max_resid;   /* max_i ||A x_i - theta_i x_i|| / anrm over the returned pairs, in FP64 */
+    double seconds;     /* wall time of the call */
+    int32_t status;     /* same as the return value */
+} xab_eig_info;
+
+/* Thick-restart Lanczos (Wu and Simon's restart; the paper names a
+ * restarted Lanczos for symmetric matrices, section 2.2) for the nev
+ * eigenpairs of a symmetric A at the chosen end of the spectrum.  The plan
+ * may be general (A is then assumed symmetric, not checked) or
+ * XAB_SYM_LOWER; every product with A uses the plan's variant in FP64.
+ * d_v0 (FP64[n], non-zero) starts the recurrence.  Each new basis vector is
+ * orthogonalised against the whole basis (classical Gram-Schmidt with the
+ * DGKS second pass); after m vectors the Ritz pairs of T = Q^T A Q are
+ * formed, and the solve stops when the residual estimates
+ * |beta_m y_{m,i}| of the nev wanted ones are <= tol * anrm; otherwise
+ * nev + (m - nev) / 2 Ritz vectors are kept and the recurrence continues.
+ * Out: h_evals[nev] (host, wanted end first), d_evecs (device FP64,
+ * column-major n x nev, ld = n, orthonormal columns).  XAB_BREAKDOWN when
+ * the Krylov space of d_v0 is invariant with dimension below nev;
+ * XAB_NOT_CONVERGED / XAB_TIME_LIMIT return the current Ritz pairs.
+ * Synchronous. */
+int xab_lanczos(xab_ctx *ctx, const xab_plan *plan, const double *d_v0, const xab_eig_opts *opts,
+                double *h_evals, double *d_evecs, xab_eig_info *info);
+
 /* Batch of independent CSR systems concatenated block-diagonally:
  * system k owns rows [h_row_off[k], h_row_off[k+1]) and entries
  * [h_nnz_off[k], h_nnz_off[k+1]); d_rowptr holds global offsets and

@@ -27,6 +27,7 @@ MLP_NPARAMS = 64 * 12 + 64 + 64 * 64 + 64 + NCLASSES * 64 + NCLASSES
 MODE_FP64, MODE_IR = 0, 1
 PRECOND_NONE, PRECOND_JACOBI = 0, 1
 ORTHO_DGKS, ORTHO_CGS, ORTHO_MGS, ORTHO_BCGS, ORTHO_POLICY = 0, 1, 2, 3, 4
+EIG_LARGEST, EIG_SMALLEST = 0, 1
 
 STATUS = {0: "ok", -1: "null", -2: "shape", -3: "dtype", -4: "struct", -5: "alias", -6: "unsupported",
           -7: "nomem", -8: "device", -9: "align", 1: "not_converged", 2: "breakdown", 3: "time_limit"}
@@ -79,6 +80,20 @@ class KrylovInfo(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class EigOpts(ctypes.Structure):
+    _fields_ = [("nev", ctypes.c_int32), ("m", ctypes.c_int32), ("tol", ctypes.c_double),
+                ("maxiter", ctypes.c_int64), ("max_time_s", ctypes.c_double), ("which", ctypes.c_int32)]
+
+
+class EigInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int64), ("restarts", ctypes.c_int64), ("nconv", ctypes.c_int32),
+                ("anrm", ctypes.c_double), ("max_resid", ctypes.c_double), ("seconds", ctypes.c_double),
+                ("status", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _P = ctypes.c_void_p
 _I32, _I64, _U32, _F, _D = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_float, ctypes.c_double
 _PP = ctypes.POINTER(ctypes.c_void_p)
@@ -113,6 +128,7 @@ SIGNATURES = {
     "xab_selector_forward": (ctypes.c_int, [_P, _P, _I32, _I32, _P]),
     "xab_selector_loss_grad": (ctypes.c_int, [_P, _P, _P, _P, _I32, _P, ctypes.POINTER(_F)]),
     "xab_gmres": (ctypes.c_int, [_P, _P, _P, _P, ctypes.POINTER(KrylovOpts), ctypes.POINTER(KrylovInfo)]),
+    "xab_lanczos": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(EigOpts), _P, _P, ctypes.POINTER(EigInfo)]),
     "xab_batch_csr": (ctypes.c_int, [_P, _I32, _P, _P, _P, _P, _P, ctypes.c_int, _U32, _PP]),
     "xab_batch_destroy": (None, [_P]),
     "xab_batch_layout": (ctypes.c_int, [_P]),
@@ -343,6 +359,18 @@ class Context:
         s = self._check(lib().xab_gmres(self.h, plan.h, _ptr(b), _ptr(x), ctypes.byref(opts), ctypes.byref(info)),
                         "xab_gmres")
         return x, info.as_dict(), s
+
+    def lanczos(self, plan, v0, nev=10, m=30, tol=1e-8, maxiter=0, which=EIG_LARGEST, max_time_s=0.0):
+        """Thick-restart Lanczos: (evals numpy[nev], evecs tensor [n, nev], info dict, status)."""
+        torch = _torch()
+        n = v0.numel()
+        ev = np.zeros(nev, dtype=np.float64)
+        X = torch.empty((nev, n), dtype=torch.float64, device=v0.device)  # column-major n x nev
+        opts = EigOpts(nev=nev, m=m, tol=tol, maxiter=maxiter, max_time_s=max_time_s, which=which)
+        info = EigInfo()
+        s = self._check(lib().xab_lanczos(self.h, plan.h, _ptr(v0), ctypes.byref(opts), ev.ctypes.data_as(_P),
+                                          _ptr(X), ctypes.byref(info)), "xab_lanczos")
+        return ev, X.t(), info.as_dict(), s
 
     def batch(self, B, dtype="f64", trust=False, tiles=False):
         return Batch(self, B, dtype, trust, tiles)

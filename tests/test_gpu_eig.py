@@ -1,0 +1,169 @@
+"""GPU thick-restart Lanczos against the oracle, closed forms and LAPACK.
+
+No bitwise parity (the GPU orthogonalises with CGS + the DGKS test, the
+oracle always applies two CGS passes, and the small eigenproblem is solved
+by cyclic Jacobi on one side and LAPACK on the other): eigenvalues agree to
+1e-9 of the ||A|| estimate, eigenvectors to an angle of 1e-6, the true
+residuals meet the requirement, and the restart counts are close.
+"""
+import numpy as np
+import pytest
+
+import gen
+from oracle import eig
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+xab = pytest.importorskip("paper_2405_01599_amd")
+
+GENERAL = (3, 6, 12, 13)   # NNZ 2048, BSS J=8, XCB, SELL
+SYMMETRIC = (9, 10)        # SYM_ATOMIC, SYM_S3 C=64
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return xab.Context(0)
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def lap1d(n):
+    rp, ci, v = [0], [], []
+    for i in range(n):
+        for j, a in ((i - 1, -1.0), (i, 2.0), (i + 1, -1.0)):
+            if 0 <= j < n:
+                ci.append(j)
+                v.append(a)
+        rp.append(len(ci))
+    return gen.CSR(n, n, np.array(rp, np.int32), np.array(ci, np.int32), np.array(v), name=f"lap1d_{n}")
+
+
+def random_sym(n, per_row, seed, lower=False):
+    """Random sparse symmetric matrix (both triangles, or the lower one)."""
+    rng = np.random.default_rng(seed)
+    rows = [dict() for _ in range(n)]
+    for i in range(n):
+        rows[i][i] = rng.uniform(-2, 2)
+        for j in rng.choice(n, per_row, replace=False):
+            a = rng.standard_normal()
+            rows[i][int(j)] = rows[i].get(int(j), 0.0) + a
+            if j != i:
+                rows[int(j)][i] = rows[int(j)].get(i, 0.0) + a
+    rp, ci, v = [0], [], []
+    for i in range(n):
+        for j in sorted(rows[i]):
+            if not lower or j <= i:
+                ci.append(j)
+                v.append(rows[i][j])
+        rp.append(len(ci))
+    return gen.CSR(n, n, np.array(rp, np.int32), np.array(ci, np.int32), np.array(v), sym_lower=lower,
+                   name=f"rsym_{n}")
+
+
+def dense_of(A):
+    D = np.zeros((A.n, A.n))
+    for i in range(A.n):
+        for k in range(A.rowptr[i], A.rowptr[i + 1]):
+            D[i, A.colind[k]] += A.val[k]
+            if A.sym_lower and A.colind[k] != i:
+                D[A.colind[k], i] += A.val[k]
+    return D
+
+
+def run(ctx, A, k, nev, m, v0, **kw):
+    M = ctx.matrix_from_csr(A)
+    P = ctx.plan_class(M, k)
+    ev, X, info, st = ctx.lanczos(P, dev(v0), nev=nev, m=m, **kw)
+    return ev, X.cpu().numpy(), info, st
+
+
+def check_vs_oracle(ev, X, info, ref, nev, tol):
+    anrm = ref["anrm"]
+    assert abs(info["anrm"] - anrm) <= 1e-9 * anrm
+    assert np.max(np.abs(ev - ref["evals"])) <= 1e-9 * anrm
+    for i in range(nev):
+        assert abs(abs(X[:, i] @ ref["evecs"][:, i]) - 1.0) <= 1e-6
+    assert np.max(np.abs(X.T @ X - np.eye(nev))) <= 1e-10
+    assert info["max_resid"] <= 1.5 * tol
+    assert abs(info["restarts"] - ref["restarts"]) <= max(2, 0.2 * ref["restarts"])
+
+
+@pytest.mark.parametrize("k", GENERAL)
+@pytest.mark.parametrize("which", [xab.EIG_LARGEST, xab.EIG_SMALLEST])
+def test_lap1d_vs_oracle_and_closed_form(ctx, k, which):
+    n = 400
+    A = lap1d(n)
+    v0 = gen.uniform_vec(n, 1)
+    ref = eig.lanczos(A, 10, 30, v0, tol=1e-8, which=which)
+    ev, X, info, st = run(ctx, A, k, 10, 30, v0, tol=1e-8, which=which)
+    assert st == 0 and info["status"] == 0 and info["nconv"] == 10
+    check_vs_oracle(ev, X, info, ref, 10, 1e-8)
+    lam = np.sort(2.0 - 2.0 * np.cos(np.arange(1, n + 1) * np.pi / (n + 1)))
+    want = lam[::-1][:10] if which == xab.EIG_LARGEST else lam[:10]
+    assert np.max(np.abs(ev - want)) <= 1e-10 * info["anrm"]
+
+
+@pytest.mark.parametrize("lower,k", [(False, 3), (False, 13), (True, 9), (True, 10)])
+def test_random_symmetric_vs_oracle_and_lapack(ctx, lower, k):
+    n = 1500
+    A = random_sym(n, 5, 11, lower=lower)
+    v0 = gen.uniform_vec(n, 2)
+    ref = eig.lanczos(A, 10, 40, v0, tol=1e-9)
+    ev, X, info, st = run(ctx, A, k, 10, 40, v0, tol=1e-9)
+    assert st == 0
+    check_vs_oracle(ev, X, info, ref, 10, 1e-9)
+    lap = np.linalg.eigvalsh(dense_of(A))[::-1][:10]
+    assert np.max(np.abs(ev - lap)) <= 1e-9 * info["anrm"]
+
+
+def test_st27_lower_values_are_eigenvalues(ctx):
+    """Lower-stored 27-point stencil (16^3): eigenvalues of multiplicity 3
+    and 6, so only properties are fixed (see the oracle's pin)."""
+    g = 16
+    A = gen.stencil27(g)
+    ev, X, info, st = run(ctx, A, 10, 10, 40, gen.uniform_vec(A.n, 5), tol=1e-8)
+    assert st == 0
+    t = 1.0 + 2.0 * np.cos(np.arange(1, g + 1) * np.pi / (g + 1))
+    lam = np.sort((28.0 - np.einsum("i,j,k->ijk", t, t, t)).ravel())
+    assert abs(ev[0] - lam[-1]) <= 1e-9 * info["anrm"]
+    for v in ev:
+        assert np.min(np.abs(lam - v)) <= 1e-9 * info["anrm"]
+    assert np.all(np.diff(ev) <= 0)
+    assert info["max_resid"] <= 1.5e-8
+
+
+def test_breakdown_and_exact_invariant_space(ctx):
+    n = 64
+    A = gen.CSR(n, n, np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), np.arange(1.0, n + 1))
+    v0 = np.zeros(n)
+    v0[[2, 7, 11]] = 1.0
+    ev, X, info, st = run(ctx, A, 3, 4, 10, v0)
+    assert st == 2 and info["status"] == 2
+    ev, X, info, st = run(ctx, A, 3, 2, 10, v0)
+    assert st == 0
+    assert np.allclose(ev, [12.0, 8.0], atol=1e-13, rtol=0)
+    assert abs(abs(X[11, 0]) - 1.0) <= 1e-12 and abs(abs(X[7, 1]) - 1.0) <= 1e-12
+
+
+def test_iteration_limit_returns_current_pairs(ctx):
+    n = 400
+    A = lap1d(n)
+    ev, X, info, st = run(ctx, A, 3, 10, 30, gen.uniform_vec(n, 1), tol=1e-8, maxiter=60)
+    assert st == 1 and info["nconv"] < 10 and info["iters"] >= 60
+    assert np.all(np.diff(ev) <= 0) and np.all(ev > 0)
+
+
+def test_argument_errors(ctx):
+    A = lap1d(100)
+    M = ctx.matrix_from_csr(A)
+    P = ctx.plan_class(M, 3)
+    v0 = dev(np.ones(100))
+    for kw in ({"nev": 10, "m": 10}, {"nev": 10, "m": 64}, {"nev": 0, "m": 20}, {"which": 2}):
+        with pytest.raises(xab.XabError) as e:
+            ctx.lanczos(P, v0, **kw)
+        assert e.value.status == -2
+    with pytest.raises(xab.XabError) as e:
+        ctx.lanczos(P, dev(np.zeros(100)))
+    assert e.value.status == -2
