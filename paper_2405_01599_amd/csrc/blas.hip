@@ -41,11 +41,14 @@ __device__ __forceinline__ void mdot_body(const T *__restrict__ V, int64_t ldv, 
 #pragma unroll
     for (int i = 0; i <= NV; ++i) acc[i] = 0.0;
     for (int64_t r = (int64_t)blockIdx.x * kNT + threadIdx.x; r < n; r += (int64_t)gridDim.x * kNT) {
+        // every load of the row first (selects, no branches), then the products
+        double vr[NV];
+#pragma unroll
+        for (int i = 0; i < NV; ++i) vr[i] = i < nv ? (double)V[i * ldv + r] : 0.0;
         const double wr = (double)w[r];
         acc[NV] += wr * wr;
 #pragma unroll
-        for (int i = 0; i < NV; ++i)
-            if (i < nv) acc[i] += (double)V[i * ldv + r] * wr;
+        for (int i = 0; i < NV; ++i) acc[i] += vr[i] * wr;
     }
     const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
 #pragma unroll
@@ -83,10 +86,12 @@ __global__ __launch_bounds__(kNT) void k_update_norm(const T *__restrict__ V, in
     for (int i = 0; i < NV; ++i) hh[i] = i < nv ? h[i] : 0.0;
     double acc = 0.0;
     for (int64_t r = (int64_t)blockIdx.x * kNT + threadIdx.x; r < n; r += (int64_t)gridDim.x * kNT) {
+        double vr[NV];
+#pragma unroll
+        for (int i = 0; i < NV; ++i) vr[i] = i < nv ? (double)V[i * ldv + r] : 0.0;
         double a = (double)w[r];
 #pragma unroll
-        for (int i = 0; i < NV; ++i)
-            if (i < nv) a -= hh[i] * (double)V[i * ldv + r];
+        for (int i = 0; i < NV; ++i) a -= hh[i] * vr[i];
         const T at = (T)a;
         w[r] = at;
         acc += (double)at * (double)at;

@@ -28,25 +28,28 @@ constexpr double kEta = 0.70710678118654752440;  // DGKS threshold 1/sqrt(2)
 constexpr int kMaxM = 63;                         // basis vectors per cycle (slots of the fused dots)
 constexpr int kRotNT = 256;
 
-// out[:, c] = sum_{j < mm} V[:, j] * Y[j + c * mm] for c < k (column-major Y,
-// kept in LDS); each thread holds one row of V in registers.
+// out[:, c] = sum_{j < mm} V[:, j] * Y[j + c * mm] for c < k (column-major
+// Y).  A workgroup takes 64 rows: it stages their mm basis entries in LDS
+// (one coalesced 512-byte run per vector), then wave q forms the outputs
+// c = q, q + 4, ... for those rows, lane = row, so every basis entry is read
+// from HBM once and every output written once.
+constexpr int kRotRows = 64;
 __global__ __launch_bounds__(kRotNT) void k_rotate(const double *__restrict__ V, int64_t ldv, int mm,
                                                    const double *__restrict__ Y, int k, double *__restrict__ out,
                                                    int64_t ldo, int64_t n) {
-    __shared__ double ys[(kMaxM + 1) * kMaxM];
+    extern __shared__ double lds[];  // [mm][kRotRows] basis rows, then Y (mm * k)
+    double *vs = lds, *ys = lds + mm * kRotRows;
+    const int64_t r0 = (int64_t)blockIdx.x * kRotRows;
+    const int lane = threadIdx.x % kRotRows, q = threadIdx.x / kRotRows;
+    const int64_t r = r0 + lane;
     for (int i = threadIdx.x; i < mm * k; i += kRotNT) ys[i] = Y[i];
+    for (int j = q; j < mm; j += kRotNT / kRotRows) vs[j * kRotRows + lane] = r < n ? V[(int64_t)j * ldv + r] : 0.0;
     __syncthreads();
-    const int64_t r = (int64_t)blockIdx.x * kRotNT + threadIdx.x;
     if (r >= n) return;
-    double v[kMaxM + 1];
-#pragma unroll
-    for (int j = 0; j <= kMaxM; ++j) v[j] = j < mm ? V[(int64_t)j * ldv + r] : 0.0;
-    for (int c = 0; c < k; ++c) {
+    for (int c = q; c < k; c += kRotNT / kRotRows) {
         const double *y = ys + c * mm;
         double a = 0.0;
-#pragma unroll
-        for (int j = 0; j <= kMaxM; ++j)
-            if (j < mm) a = fma(v[j], y[j], a);
+        for (int j = 0; j < mm; ++j) a = fma(vs[j * kRotRows + lane], y[j], a);
         out[(int64_t)c * ldo + r] = a;
     }
 }
@@ -169,7 +172,8 @@ int rotate(xab_ctx *ctx, const Work &W, int mm, const std::vector<double> &Ycm, 
            int64_t n) {
     memcpy(W.host, Ycm.data(), sizeof(double) * (size_t)mm * k);
     XAB_HIP(ctx, hipMemcpyAsync(W.Y, W.host, sizeof(double) * (size_t)mm * k, hipMemcpyHostToDevice, ctx->stream));
-    hipLaunchKernelGGL(k_rotate, dim3((unsigned)((n + kRotNT - 1) / kRotNT)), dim3(kRotNT), 0, ctx->stream, W.V,
+    const size_t lds = sizeof(double) * (size_t)mm * (kRotRows + k);  // <= 64 KB (mm, k <= 63)
+    hipLaunchKernelGGL(k_rotate, dim3((unsigned)((n + kRotRows - 1) / kRotRows)), dim3(kRotNT), lds, ctx->stream, W.V,
                        W.ldv, mm, W.Y, k, out, ldo, n);
     XAB_LAUNCH_CHECK(ctx, "k_rotate");
     // the pinned buffer is reused by the next read-back: finish the copy first
