@@ -25,6 +25,13 @@ uses; this is the thick restart of Wu and Simon (2000):
   anrm is the largest |theta| seen so far (an estimate of ||A||_2).
 * Otherwise keep k = nev + (m - nev) // 2 Ritz vectors Q Y[:, :k], append
   q_m as q_k, set s_i = beta_{m-1} * Y[m-1, i] and continue from step k.
+* Restart-length tuning (the MM ratio of eq. (1) in the manner of
+  section 3.2.1, with the section 4.3 growth rule), when step > 0: after
+  every cycle the worst residual estimate of the nev wanted pairs relative
+  to anrm is sampled; once `window` samples exist since the last change of
+  m, and their MM ratio (max / min over the last `window`) is below
+  `ratio`, convergence is judged stagnant and m grows by `step` up to m_max
+  (the samples then start afresh).
 * beta_j <= 1e-14 * (the largest |alpha|, beta or |theta| met so far) is
   taken as an invariant subspace: the cycle ends at j + 1 vectors with
   exact Ritz pairs; if fewer than nev exist then, the solve reports a
@@ -32,7 +39,7 @@ uses; this is the thick restart of Wu and Simon (2000):
 """
 import numpy as np
 
-from . import spmv
+from . import mm_ratio, spmv
 
 OK, NOT_CONVERGED, BREAKDOWN = 0, 1, 2
 LARGEST, SMALLEST = 0, 1
@@ -58,19 +65,23 @@ def _cgs2(Q, j, w):
     return h + h2, w
 
 
-def lanczos(A, nev, m, v0, tol=1e-8, maxiter=100000, which=LARGEST, matvec=None):
+def lanczos(A, nev, m, v0, tol=1e-8, maxiter=100000, which=LARGEST, matvec=None, step=0, m_max=0,
+            ratio=0.0, window=5):
     """Thick-restart Lanczos for a symmetric A (CSR, general or lower-stored).
 
     Returns dict(evals[nev], evecs[n, nev], status, matvecs, restarts, anrm,
-    est[nev] (residual estimates), resid[nev] (true ||A x - theta x||))."""
+    est[nev] (residual estimates), resid[nev] (true ||A x - theta x||),
+    m_hist (m of every cycle), m_final)."""
     n = A.n
     if matvec is None:
         def matvec(x):
             return spmv(A, x)[0]
-    if not 1 <= nev < m <= n:
-        raise ValueError("need 1 <= nev < m <= n")
-    Q = np.zeros((n, m + 1))
-    T = np.zeros((m, m))
+    m_max = max(m, m_max) if step > 0 else m
+    if not 1 <= nev < m <= m_max <= n:
+        raise ValueError("need 1 <= nev < m <= m_max <= n")
+    Q = np.zeros((n, m_max + 1))
+    T = np.zeros((m_max, m_max))
+    m_hist, samples = [], []
     Q[:, 0] = v0 / np.linalg.norm(v0)
     k = 0                 # kept Ritz vectors at the start of the cycle
     anrm = 0.0
@@ -94,12 +105,14 @@ def lanczos(A, nev, m, v0, tol=1e-8, maxiter=100000, which=LARGEST, matvec=None)
             if j + 1 < m:
                 T[j + 1, j] = T[j, j + 1] = beta
             Q[:, j + 1] = w / beta
+        m_hist.append(m)
         theta, Y = np.linalg.eigh(T[:mm, :mm])
         order = _order(theta, which)
         theta, Y = theta[order], Y[:, order]
         anrm = max(anrm, float(np.max(np.abs(theta))))
         tscale = max(tscale, anrm)
         est = np.abs(beta * Y[mm - 1, :])
+        samples.append(float(np.max(est[:nev])) / anrm if mm >= nev else 0.0)
         if mm < nev:
             status = BREAKDOWN
             break
@@ -108,7 +121,7 @@ def lanczos(A, nev, m, v0, tol=1e-8, maxiter=100000, which=LARGEST, matvec=None)
             break
         if matvecs >= maxiter:
             break
-        # thick restart
+        # thick restart (kept count from the length of the cycle just ended)
         k = kept_count(nev, m)
         Qk = Q[:, :mm] @ Y[:, :k]
         qn = Q[:, mm].copy()
@@ -118,8 +131,14 @@ def lanczos(A, nev, m, v0, tol=1e-8, maxiter=100000, which=LARGEST, matvec=None)
         T[np.arange(k), np.arange(k)] = theta[:k]
         T[k, :k] = T[:k, k] = beta * Y[mm - 1, :k]
         restarts += 1
+        # restart-length judgment on the samples since the last change of m
+        if step > 0 and m < m_max and len(samples) >= window and \
+                mm_ratio(samples, len(samples), window) < ratio:
+            m = min(m + step, m_max)
+            samples = []
     nret = min(nev, mm)
     X = Q[:, :mm] @ Y[:, :nret]
     resid = np.array([np.linalg.norm(matvec(X[:, i]) - theta[i] * X[:, i]) for i in range(nret)])
     return {"evals": theta[:nret].copy(), "evecs": X, "status": status, "matvecs": matvecs,
-            "restarts": restarts, "anrm": anrm, "est": est[:nret].copy(), "resid": resid}
+            "restarts": restarts, "anrm": anrm, "est": est[:nret].copy(), "resid": resid, "m_hist": m_hist,
+            "m_final": m}

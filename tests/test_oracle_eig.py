@@ -138,3 +138,40 @@ def test_breakdown_small_invariant_space():
 def test_kept_count():
     assert eig.kept_count(10, 30) == 20
     assert eig.kept_count(10, 11) == 10
+
+
+def test_restart_tuning_off_is_plain():
+    A = lap1d(300)
+    v0 = gen.uniform_vec(300, 3)
+    a = eig.lanczos(A, 6, 16, v0)
+    b = eig.lanczos(A, 6, 16, v0, step=0, m_max=40, ratio=100.0)
+    assert a["matvecs"] == b["matvecs"] and np.array_equal(a["evals"], b["evals"])
+    assert set(b["m_hist"]) == {16}
+
+
+def test_restart_tuning_rule_extremes():
+    """ratio = inf: every window of samples is 'stagnant', so m grows by step
+    after each `window` cycles until m_max; ratio = 0: never (eq. (1) is >= 1)."""
+    A = lap1d(400)
+    v0 = gen.uniform_vec(400, 1)
+    r = eig.lanczos(A, 10, 12, v0, step=5, m_max=30, ratio=np.inf, window=3)
+    h = r["m_hist"]
+    want = [12] * 3 + [17] * 3 + [22] * 3 + [27] * 3
+    assert h[:12] == want and all(m == 30 for m in h[12:]) and r["m_final"] == 30
+    assert r["status"] == eig.OK
+    r0 = eig.lanczos(A, 10, 12, v0, step=5, m_max=30, ratio=0.0, window=3, maxiter=400)
+    assert set(r0["m_hist"]) == {12}
+
+
+def test_restart_tuning_cures_slow_convergence():
+    """Basis of 12 for 10 wanted pairs restarts with little room; the MM-ratio
+    rule grows it and the solve needs fewer products, same eigenvalues."""
+    n = 400
+    A = lap1d(n)
+    v0 = gen.uniform_vec(n, 1)
+    fixed = eig.lanczos(A, 10, 12, v0, maxiter=20000)
+    tuned = eig.lanczos(A, 10, 12, v0, step=5, m_max=40, ratio=2.0, window=5, maxiter=20000)
+    assert tuned["status"] == eig.OK and tuned["m_final"] > 12
+    assert tuned["matvecs"] < fixed["matvecs"]
+    lam = np.sort(2.0 - 2.0 * np.cos(np.arange(1, n + 1) * np.pi / (n + 1)))[::-1][:10]
+    assert np.max(np.abs(tuned["evals"] - lam)) <= 1e-10 * tuned["anrm"]
