@@ -36,6 +36,7 @@ import collections
 import csv
 import glob
 import hashlib
+import itertools
 import json
 import os
 import sys
@@ -276,10 +277,40 @@ def restart_tuning_leg(ctx, xab, torch, plan, n):
     return res
 
 
-def sym_stencil_leg(ctx, xab, torch, gen, gmres=True):
+def lanczos_leg(ctx, xab, torch, gen, plan, g):
+    """Thick-restart Lanczos on the 27-point stencil (section 4.3 setting: 10
+    eigenpairs to 1e-8), both ends of the spectrum: a fixed basis of 30
+    vectors, and restart-length tuning from 20 (m += 5 up to 60 when the MM
+    ratio of 5 per-cycle samples is below 2); wall time of the call and the
+    distance of every eigenvalue to the stencil's closed-form spectrum."""
+    import numpy as np
+    t = 1.0 + 2.0 * np.cos(np.arange(1, g + 1) * np.pi / (g + 1))
+    lam = np.sort((28.0 - np.einsum("i,j,k->ijk", t, t, t)).ravel())
+    v0 = torch.from_numpy(gen.uniform_vec(g ** 3, 5)).cuda()
+    out = {}
+    runs = (("fixed_m30", dict(m=30)),
+            ("tuned_m20_to_60", dict(m=20, restart_step=5, m_max=60, mm_ratio=2.0, window=5)))
+    ends = ((xab.EIG_LARGEST, "largest"), (xab.EIG_SMALLEST, "smallest"))
+    for (which, name), (tag, kw) in itertools.product(ends, runs):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev, X, info, st = ctx.lanczos(plan, v0, nev=10, tol=1e-8, which=which, max_time_s=60.0, **kw)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        err = max(float(np.min(np.abs(lam - v))) for v in ev) / info["anrm"]
+        out[f"{name}_{tag}"] = {
+            "s": round(wall, 4), "status": st, "matvecs": info["iters"], "restarts": info["restarts"],
+            "m_final": info["m_final"], "ms_per_matvec": round(wall / max(1, info["iters"]) * 1e3, 4),
+            "max_resid_rel": info["max_resid"], "closed_form_err_rel": err,
+            "evals": [round(float(v), 12) for v in (ev[0], ev[-1])]}
+        del X
+    return out
+
+
+def sym_stencil_leg(ctx, xab, torch, gen, gmres=True, eig=True):
     """Symmetric SpMV from lower storage on the 128^3 27-point stencil:
     TIME-selected implementation, FP64 and FP32 values (FP64 accumulation),
-    then GMRES(30) FP64 vs mixed precision on it."""
+    then GMRES(30) FP64 vs mixed precision on it, and the Lanczos leg."""
     L = gen.stencil27(128, lower=True)
     M = ctx.matrix_from_csr(L, with_f32=True)
     plan, info = ctx.select(M, xab.TIME)
@@ -301,6 +332,8 @@ def sym_stencil_leg(ctx, xab, torch, gen, gmres=True):
     if gmres:
         out["gmres"] = gmres_pair(ctx, xab, torch, plan, L.n)
         out["gmres_restart_tuning"] = restart_tuning_leg(ctx, xab, torch, plan, L.n)
+    if eig:
+        out["lanczos"] = lanczos_leg(ctx, xab, torch, gen, plan, 128)
     plan.close()
     M.close()
     return out
@@ -315,6 +348,17 @@ def batch_leg(ctx, xab, torch, gen):
     B = gen.batch()
     out = {"workload": f"512 systems, n={B.n} nnz={B.nnz}, block-diagonal CSR"}
     for dt, tol, vb in (("f64", 1e-10, 8), ("f32", 1e-5, 4)):
+        # the segmented-scan tiles first, for comparison (graph-captured BiCGStab only)
+        bt = ctx.batch(B, dtype=dt, tiles=True)
+        b = torch.ones(B.n, dtype=bt.dtype, device="cuda")
+        ctx.bicgstab(bt, b, tol=tol)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.bicgstab(bt, b, tol=tol)
+        torch.cuda.synchronize()
+        tiles_s = round(time.perf_counter() - t0, 5)
+        bt.close()
+        del b
         bt = ctx.batch(B, dtype=dt)
         x = torch.ones(B.n, dtype=bt.dtype, device="cuda")
         y = torch.empty_like(x)
@@ -328,8 +372,8 @@ def batch_leg(ctx, xab, torch, gen):
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / 50
         by = alg_bytes(B.n, B.nnz, vb, vb, vb)
-        leg = {"spmv_us": round(ms * 1e3, 2), "spmv_gbs": round(by / (ms * 1e-3) / 1e9, 1),
-               "spmv_frac": round(by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        leg = {"layout": bt.layout, "spmv_us": round(ms * 1e3, 2), "spmv_gbs": round(by / (ms * 1e-3) / 1e9, 1),
+               "spmv_frac": round(by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "bicgstab_graph_tiles_s": tiles_s}
         b = torch.ones(B.n, dtype=bt.dtype, device="cuda")
         for graph in (True, False):
             ctx.bicgstab(bt, b, tol=tol, graph=graph)  # warm (graph instantiation, code paths)
@@ -357,6 +401,7 @@ def main():
     ap.add_argument("--no-gmres", action="store_true")
     ap.add_argument("--no-c3", action="store_true", help="skip the symmetric 27-point stencil leg")
     ap.add_argument("--no-batch", action="store_true", help="skip the 512-system batch leg")
+    ap.add_argument("--no-eig", action="store_true", help="skip the Lanczos leg")
     ap.add_argument("--n", type=int, default=2_000_000)
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     ap.add_argument("--variant", default="XCB")
@@ -448,7 +493,7 @@ def main():
     c3 = None
     if not args.no_c3:
         log("symmetric 27-point stencil 128^3 (lower storage)")
-        c3 = sym_stencil_leg(ctx, xab, torch, gen, gmres=not args.no_gmres)
+        c3 = sym_stencil_leg(ctx, xab, torch, gen, gmres=not args.no_gmres, eig=not args.no_eig)
     c4 = None
     if not args.no_batch:
         log("batch of 512 systems: batched SpMV and BiCGStab")

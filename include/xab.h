@@ -345,6 +345,10 @@ typedef struct {
     int64_t maxiter;    /* products with A in the recurrence; <= 0: unlimited */
     double max_time_s;  /* wall-clock limit (the policy's MAXTIME); <= 0: none */
     int32_t which;      /* XAB_EIG_LARGEST or XAB_EIG_SMALLEST */
+    int32_t restart_step; /* restart-length tuning: growth of m (0 = off; section 4.3 uses 5) */
+    int32_t m_max;      /* tuning: largest m, in [m, min(63, n)] */
+    double mm_ratio;    /* tuning: stagnation threshold on the MM ratio of eq. (1) */
+    int32_t window;     /* tuning: cycles per MM-ratio sample window (<= 0: 5) */
 } xab_eig_opts;
 
 typedef struct {
@@ -355,6 +359,7 @@ typedef struct {
     double max_resid;   /* max_i ||A x_i - theta_i x_i|| / anrm over the returned pairs, in FP64 */
     double seconds;     /* wall time of the call */
     int32_t status;     /* same as the return value */
+    int32_t m_final;    /* m of the last cycle */
 } xab_eig_info;
 
 /* Thick-restart Lanczos (Wu and Simon's restart; the paper names a
@@ -368,6 +373,12 @@ typedef struct {
  * formed, and the solve stops when the residual estimates
  * |beta_m y_{m,i}| of the nev wanted ones are <= tol * anrm; otherwise
  * nev + (m - nev) / 2 Ritz vectors are kept and the recurrence continues.
+ * Restart-length tuning (eq. (1) in the manner of section 3.2.1, the
+ * section 4.3 growth rule), when restart_step > 0: after every cycle the
+ * worst residual estimate of the wanted pairs relative to anrm is sampled;
+ * once `window` samples exist since m last changed and their MM ratio is
+ * below mm_ratio, m grows by restart_step up to m_max and the samples
+ * start afresh.
  * Out: h_evals[nev] (host, wanted end first), d_evecs (device FP64,
  * column-major n x nev, ld = n, orthonormal columns).  XAB_BREAKDOWN when
  * the Krylov space of d_v0 is invariant with dimension below nev;

@@ -82,13 +82,15 @@ class KrylovInfo(ctypes.Structure):
 
 class EigOpts(ctypes.Structure):
     _fields_ = [("nev", ctypes.c_int32), ("m", ctypes.c_int32), ("tol", ctypes.c_double),
-                ("maxiter", ctypes.c_int64), ("max_time_s", ctypes.c_double), ("which", ctypes.c_int32)]
+                ("maxiter", ctypes.c_int64), ("max_time_s", ctypes.c_double), ("which", ctypes.c_int32),
+                ("restart_step", ctypes.c_int32), ("m_max", ctypes.c_int32), ("mm_ratio", ctypes.c_double),
+                ("window", ctypes.c_int32)]
 
 
 class EigInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int64), ("restarts", ctypes.c_int64), ("nconv", ctypes.c_int32),
                 ("anrm", ctypes.c_double), ("max_resid", ctypes.c_double), ("seconds", ctypes.c_double),
-                ("status", ctypes.c_int32)]
+                ("status", ctypes.c_int32), ("m_final", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -360,13 +362,15 @@ class Context:
                         "xab_gmres")
         return x, info.as_dict(), s
 
-    def lanczos(self, plan, v0, nev=10, m=30, tol=1e-8, maxiter=0, which=EIG_LARGEST, max_time_s=0.0):
+    def lanczos(self, plan, v0, nev=10, m=30, tol=1e-8, maxiter=0, which=EIG_LARGEST, max_time_s=0.0,
+                restart_step=0, m_max=0, mm_ratio=0.0, window=5):
         """Thick-restart Lanczos: (evals numpy[nev], evecs tensor [n, nev], info dict, status)."""
         torch = _torch()
         n = v0.numel()
         ev = np.zeros(nev, dtype=np.float64)
         X = torch.empty((nev, n), dtype=torch.float64, device=v0.device)  # column-major n x nev
-        opts = EigOpts(nev=nev, m=m, tol=tol, maxiter=maxiter, max_time_s=max_time_s, which=which)
+        opts = EigOpts(nev=nev, m=m, tol=tol, maxiter=maxiter, max_time_s=max_time_s, which=which,
+                       restart_step=restart_step, m_max=m_max if m_max else m, mm_ratio=mm_ratio, window=window)
         info = EigInfo()
         s = self._check(lib().xab_lanczos(self.h, plan.h, _ptr(v0), ctypes.byref(opts), ev.ctypes.data_as(_P),
                                           _ptr(X), ctypes.byref(info)), "xab_lanczos")

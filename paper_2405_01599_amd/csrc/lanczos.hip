@@ -168,6 +168,16 @@ int alloc_work(xab_ctx *ctx, Work &W, int64_t n, int m) {
     return XAB_OK;
 }
 
+// The MM ratio of eq. (1) over samples v[s-t .. s-1]: max / min.
+double mm_ratio(const std::vector<double> &v, size_t s, size_t t) {
+    double mx = v[s - t], mn = v[s - t];
+    for (size_t z = s - t; z < s; ++z) {
+        mx = std::max(mx, v[z]);
+        mn = std::min(mn, v[z]);
+    }
+    return mx / mn;
+}
+
 int rotate(xab_ctx *ctx, const Work &W, int mm, const std::vector<double> &Ycm, int k, double *out, int64_t ldo,
            int64_t n) {
     memcpy(W.host, Ycm.data(), sizeof(double) * (size_t)mm * k);
@@ -188,11 +198,17 @@ extern "C" int xab_lanczos(xab_ctx *ctx, const xab_plan *pl, const double *d_v0,
     if (!ctx || !pl || !d_v0 || !opts) return XAB_E_NULL;
     const xab_matrix *A = pl->A;
     const int64_t n = A->n;
-    const int nev = opts->nev, m = opts->m;
+    const int nev = opts->nev;
+    int m = opts->m;  // length of the next cycle
+    const bool tune = opts->restart_step > 0;
+    const int mc = tune ? opts->m_max : m;  // basis capacity
+    const int window = opts->window > 0 ? opts->window : 5;
     if (A->n != A->ncols) return xab_fail(ctx, XAB_E_SHAPE, "Lanczos needs a square matrix");
     if (nev < 1 || m <= nev || m > kMaxM || m > n)
         return xab_fail(ctx, XAB_E_SHAPE, "need 1 <= nev < m <= min(63, n) (nev %d, m %d, n %lld)", nev, m,
                         (long long)n);
+    if (tune && (mc < m || mc > kMaxM || mc > n))
+        return xab_fail(ctx, XAB_E_SHAPE, "m_max must be in [m, min(63, n)] (m_max %d)", mc);
     if (opts->which != XAB_EIG_LARGEST && opts->which != XAB_EIG_SMALLEST)
         return xab_fail(ctx, XAB_E_SHAPE, "which");
     if (!h_evals || !d_evecs) return XAB_E_NULL;
@@ -203,7 +219,7 @@ extern "C" int xab_lanczos(xab_ctx *ctx, const xab_plan *pl, const double *d_v0,
     XAB_HIP(ctx, hipSetDevice(ctx->device));
     Work W;
     int s;
-    if ((s = alloc_work(ctx, W, n, m)) != XAB_OK) return s;
+    if ((s = alloc_work(ctx, W, n, mc)) != XAB_OK) return s;
     const int nb = xab::kRedBlocks;
     hipStream_t st = ctx->stream;
     auto t0 = std::chrono::steady_clock::now();
@@ -220,9 +236,9 @@ extern "C" int xab_lanczos(xab_ctx *ctx, const xab_plan *pl, const double *d_v0,
 
     const int64_t maxiter = opts->maxiter > 0 ? opts->maxiter : INT64_MAX;
     const int which = opts->which;
-    std::vector<double> T((size_t)m * m, 0.0);  // row-major projected matrix
-    std::vector<double> theta, Z, Yc;
-    std::vector<int> order(m);
+    std::vector<double> T((size_t)mc * mc, 0.0);  // row-major projected matrix, stride mc
+    std::vector<double> theta, Z, Yc, samples;  // samples: worst wanted estimate / anrm per cycle
+    std::vector<int> order(mc);
     int k = 0;  // kept Ritz vectors
     double anrm = 0.0, tscale = 0.0, beta = 0.0;
     int mm = m, status = XAB_NOT_CONVERGED;
@@ -230,7 +246,7 @@ extern "C" int xab_lanczos(xab_ctx *ctx, const xab_plan *pl, const double *d_v0,
         // ---- m - k Lanczos steps, no host round trip
         for (int j = k; j < m; ++j) {
             double *V = W.V, *vj = V + (int64_t)j * W.ldv;
-            double *h1 = W.coef + (size_t)j * W.ld, *h2 = h1 + (m + 2), *sc = h2 + (m + 2);
+            double *h1 = W.coef + (size_t)j * W.ld, *h2 = h1 + (mc + 2), *sc = h2 + (mc + 2);
             int *gate = W.gate + j;
             if ((s = xab_spmv_dispatch(ctx, pl, vj, XAB_F64, W.w, XAB_F64, XAB_F64)) != XAB_OK) return s;
             if ((s = xab::mdot<double>(ctx, V, W.ldv, j + 1, W.w, n, W.part, nb, nullptr)) != XAB_OK) return s;
@@ -250,27 +266,27 @@ extern "C" int xab_lanczos(xab_ctx *ctx, const xab_plan *pl, const double *d_v0,
         // ---- one read-back of every step's coefficients
         XAB_HIP(ctx, hipMemcpyAsync(W.host, W.coef, W.host_bytes, hipMemcpyDeviceToHost, st));
         XAB_HIP(ctx, hipStreamSynchronize(st));
-        const int *gates = (const int *)((const char *)W.host + sizeof(double) * (size_t)W.ld * m);
+        const int *gates = (const int *)((const char *)W.host + sizeof(double) * (size_t)W.ld * mc);
         mm = m;
         beta = 0.0;
         for (int j = k; j < m; ++j) {
-            const double *h1 = W.host + (size_t)j * W.ld, *h2 = h1 + (m + 2), *sc = h2 + (m + 2);
+            const double *h1 = W.host + (size_t)j * W.ld, *h2 = h1 + (mc + 2), *sc = h2 + (mc + 2);
             const bool g = gates[j] != 0;
             const double alpha = h1[j] + (g ? h2[j] : 0.0);
             beta = std::sqrt(g ? sc[0] : h2[j + 1]);
-            T[(size_t)j * m + j] = alpha;
+            T[(size_t)j * mc + j] = alpha;
             tscale = std::max({tscale, std::fabs(alpha), beta});
             if (beta <= 1e-14 * tscale) {  // invariant subspace: the cycle ends here
                 beta = 0.0;
                 mm = j + 1;
                 break;
             }
-            if (j + 1 < m) T[(size_t)(j + 1) * m + j] = T[(size_t)j * m + j + 1] = beta;
+            if (j + 1 < m) T[(size_t)(j + 1) * mc + j] = T[(size_t)j * mc + j + 1] = beta;
         }
         // ---- Ritz pairs of T[:mm, :mm], wanted end first
         std::vector<double> a((size_t)mm * mm);
         for (int i = 0; i < mm; ++i)
-            for (int j = 0; j < mm; ++j) a[(size_t)i * mm + j] = T[(size_t)i * m + j];
+            for (int j = 0; j < mm; ++j) a[(size_t)i * mm + j] = T[(size_t)i * mc + j];
         jacobi_eig(mm, a, theta, Z);
         order.resize(mm);
         std::iota(order.begin(), order.end(), 0);
@@ -284,6 +300,12 @@ extern "C" int xab_lanczos(xab_ctx *ctx, const xab_plan *pl, const double *d_v0,
             anrm = std::max(anrm, std::fabs(th[i]));
         }
         tscale = std::max(tscale, anrm);
+        inf.m_final = m;
+        {
+            double worst = 0.0;
+            for (int i = 0; i < std::min(nev, mm); ++i) worst = std::max(worst, std::fabs(beta * last[i]));
+            samples.push_back(anrm > 0.0 ? worst / anrm : 0.0);
+        }
         int nconv = 0;
         for (int i = 0; i < std::min(nev, mm); ++i)
             if (std::fabs(beta * last[i]) <= opts->tol * anrm) ++nconv;
@@ -331,7 +353,8 @@ extern "C" int xab_lanczos(xab_ctx *ctx, const xab_plan *pl, const double *d_v0,
             inf.status = status;
             return status;
         }
-        // ---- thick restart: keep k Ritz vectors, then q_mm as vector k
+        // ---- thick restart: keep k Ritz vectors (count from the cycle just
+        // ended), then q_mm as vector k
         k = nev + (m - nev) / 2;
         ritz(k);
         if ((s = rotate(ctx, W, mm, Yc, k, W.V2, W.ldv, n)) != XAB_OK) return s;
@@ -340,9 +363,15 @@ extern "C" int xab_lanczos(xab_ctx *ctx, const xab_plan *pl, const double *d_v0,
         std::swap(W.V, W.V2);
         std::fill(T.begin(), T.end(), 0.0);
         for (int i = 0; i < k; ++i) {
-            T[(size_t)i * m + i] = th[i];
-            T[(size_t)k * m + i] = T[(size_t)i * m + k] = beta * last[i];
+            T[(size_t)i * mc + i] = th[i];
+            T[(size_t)k * mc + i] = T[(size_t)i * mc + k] = beta * last[i];
         }
         inf.restarts++;
+        // restart-length judgment (eq. (1)) on the samples since m last changed
+        if (tune && m < mc && (int)samples.size() >= window &&
+            mm_ratio(samples, samples.size(), window) < opts->mm_ratio) {
+            m = std::min(m + opts->restart_step, mc);
+            samples.clear();
+        }
     }
 }

@@ -167,3 +167,33 @@ def test_argument_errors(ctx):
     with pytest.raises(xab.XabError) as e:
         ctx.lanczos(P, dev(np.zeros(100)))
     assert e.value.status == -2
+
+
+def test_restart_tuning_vs_oracle(ctx):
+    """Basis of 12 for 10 pairs, m += 5 up to 40 when the MM ratio of 5
+    per-cycle samples is below 2: final m equal to the oracle's, product
+    count within 20 %, eigenvalues from the closed form."""
+    n = 400
+    A = lap1d(n)
+    v0 = gen.uniform_vec(n, 1)
+    ref = eig.lanczos(A, 10, 12, v0, step=5, m_max=40, ratio=2.0, window=5, maxiter=20000)
+    ev, X, info, st = run(ctx, A, 3, 10, 12, v0, restart_step=5, m_max=40, mm_ratio=2.0, window=5, maxiter=20000)
+    assert st == 0 and ref["status"] == 0
+    assert info["m_final"] == ref["m_final"] > 12
+    assert abs(info["iters"] - ref["matvecs"]) <= 0.2 * ref["matvecs"]
+    lam = np.sort(2.0 - 2.0 * np.cos(np.arange(1, n + 1) * np.pi / (n + 1)))[::-1][:10]
+    assert np.max(np.abs(ev - lam)) <= 1e-10 * info["anrm"]
+    assert info["max_resid"] <= 1.5e-8
+
+
+def test_restart_tuning_extremes(ctx):
+    n = 400
+    A = lap1d(n)
+    v0 = gen.uniform_vec(n, 1)
+    ev, X, info, st = run(ctx, A, 3, 10, 12, v0, restart_step=5, m_max=30, mm_ratio=np.inf, window=3)
+    assert st == 0 and info["m_final"] == 30
+    ev, X, info, st = run(ctx, A, 3, 10, 12, v0, restart_step=5, m_max=30, mm_ratio=0.0, window=3, maxiter=400)
+    assert info["m_final"] == 12
+    with pytest.raises(xab.XabError) as e:
+        run(ctx, A, 3, 10, 12, v0, restart_step=5, m_max=64)
+    assert e.value.status == -2
