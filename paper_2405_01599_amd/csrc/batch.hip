@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "segchunk.h"
+#include "sell_body.h"
 
 namespace {
 
@@ -76,31 +77,7 @@ __global__ __launch_bounds__(kNT) void k_batch_sell(const int64_t *__restrict__ 
         const bool mine = row >= 0 && active[sys_of_row[row]] != 0;
         if (__ballot(mine) == 0) return;  // wave-uniform: the wave is the chunk
     }
-    const int32_t len = rlen[r];
-    const int32_t w = clen[c];
-    const int64_t base = cptr[c] + l;
-    double acc = 0.0;
-    int32_t k = 0;
-    for (; k + kSellUnroll <= w; k += kSellUnroll) {
-        T v[kSellUnroll];
-        int32_t cc[kSellUnroll];
-#pragma unroll
-        for (int u = 0; u < kSellUnroll; ++u) {
-            v[u] = __builtin_nontemporal_load(val + base + (int64_t)(k + u) * kSellC);
-            cc[u] = __builtin_nontemporal_load(cols + base + (int64_t)(k + u) * kSellC);
-        }
-#pragma unroll
-        for (int u = 0; u < kSellUnroll; ++u) {
-            const double p = (double)v[u] * (double)x[cc[u]];
-            acc = k + u < len ? acc + p : acc;
-        }
-    }
-    for (; k < w; ++k) {
-        const T v = __builtin_nontemporal_load(val + base + (int64_t)k * kSellC);
-        const int32_t cc = __builtin_nontemporal_load(cols + base + (int64_t)k * kSellC);
-        const double p = (double)v * (double)x[cc];
-        acc = k < len ? acc + p : acc;
-    }
+    const double acc = xab::sell_lane_sum<T, T, double, kSellUnroll>(val, cols, x, cptr[c] + l, clen[c], rlen[r]);
     if (row >= 0) y[row] = (T)acc;
 }
 

@@ -3,7 +3,9 @@
 // k = 0 .. width - 1, reading entry k of all 64 rows as one contiguous run
 // (column-major chunk), and writes y[perm[row]].  Entries past a row's
 // length are padding and are skipped by a select, so a non-finite x entry
-// never reaches another row.  Rows are summed in order, one lane each.
+// never reaches another row.  Rows are summed in order, one lane each
+// (sell_body.h).
+#include "sell_body.h"
 #include "spmv_launch.h"
 
 namespace xab {
@@ -25,30 +27,7 @@ __global__ __launch_bounds__(kNT) void k_spmv_sell(const int64_t *__restrict__ c
     const int l = threadIdx.x % kC;
     const int64_t r = c * kC + l;
     const int32_t len = rlen[r];  // 0 for the slots past n
-    const int32_t w = clen[c];
-    const int64_t base = cptr[c] + l;
-    AT acc = AT(0);
-    int32_t k = 0;
-    for (; k + kUnroll <= w; k += kUnroll) {
-        VT v[kUnroll];
-        int32_t cc[kUnroll];
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-            v[u] = __builtin_nontemporal_load(val + base + (int64_t)(k + u) * kC);
-            cc[u] = __builtin_nontemporal_load(cols + base + (int64_t)(k + u) * kC);
-        }
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-            const AT p = (AT)v[u] * (AT)x[cc[u]];
-            acc = k + u < len ? acc + p : acc;
-        }
-    }
-    for (; k < w; ++k) {
-        const VT v = __builtin_nontemporal_load(val + base + (int64_t)k * kC);
-        const int32_t cc = __builtin_nontemporal_load(cols + base + (int64_t)k * kC);
-        const AT p = (AT)v * (AT)x[cc];
-        acc = k < len ? acc + p : acc;
-    }
+    const AT acc = sell_lane_sum<VT, XT, AT, kUnroll>(val, cols, x, cptr[c] + l, clen[c], len);
     if (r < n) y[perm[r]] = (YT)acc;
 }
 
