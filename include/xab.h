@@ -396,7 +396,8 @@ int xab_lanczos(xab_ctx *ctx, const xab_plan *plan, const double *d_v0, const xa
  * (SELL-C-sigma, C = 64, sigma = 1024: about 12 (FP64) or 8 (FP32) bytes per
  * entry plus padding) and its SpMV runs on that copy; a batch outside the
  * copy's limits (a row longer than 4096 entries, or padding beyond
- * nnz + 64 * longest row) silently uses the segmented-scan tiles instead.
+ * nnz + 64 * longest row), or one whose copy does not fit in device
+ * memory, silently uses the segmented-scan tiles instead.
  * Synchronous (validates unless flags has XAB_TRUST_INPUT). */
 int xab_batch_csr(xab_ctx *ctx, int32_t nsys, const int64_t *h_row_off, const int64_t *h_nnz_off,
                   const int32_t *d_rowptr, const int32_t *d_colind, const void *d_val, xab_dtype vt,

@@ -618,13 +618,13 @@ int xab_batch_csr(xab_ctx *ctx, int32_t nsys, const int64_t *h_row_off, const in
         xab_batch_destroy(B);
         return xab_fail(ctx, XAB_E_STRUCT, "a system has columns outside its own rows");
     }
-    // the sliced ELLPACK copy, unless asked for the tiles alone or outside its
-    // limits (then the tiles serve)
+    // the sliced ELLPACK copy, unless asked for the tiles alone; outside its
+    // limits, or without the memory for it, the tiles serve
     if (!(flags & XAB_BATCH_TILES) && n > 0) {
         s = xab_sell_build(ctx, d_rowptr, d_colind, vt == XAB_F64 ? (const double *)d_val : nullptr,
                            vt == XAB_F32 ? (const float *)d_val : nullptr, vt == XAB_F64, vt == XAB_F32, (int32_t)n,
                            nnz, kSellSigma, &B->sell);
-        if (s != XAB_OK && s != XAB_E_UNSUPPORTED) {
+        if (s != XAB_OK && s != XAB_E_UNSUPPORTED && s != XAB_E_NOMEM) {
             xab_batch_destroy(B);
             return s;
         }
