@@ -307,6 +307,72 @@ def lanczos_leg(ctx, xab, torch, gen, plan, g):
     return out
 
 
+def _csr_from_coo(gen, rows, cols, vals, nr, nc, lower=False, name=""):
+    """CSR from entries already ordered by (row, column)."""
+    import numpy as np
+    rp = np.zeros(nr + 1, dtype=np.int32)
+    rp[1:] = np.cumsum(np.bincount(rows, minlength=nr))
+    return gen.CSR(nr, nc, rp, np.ascontiguousarray(cols, dtype=np.int32), np.ascontiguousarray(vals),
+                   sym_lower=lower, name=name)
+
+
+def _time_selected(ctx, xab, torch, gen, S, seed):
+    """TIME-select an implementation for S and time its FP64 SpMV (HIP
+    events, 100 launches); returns (us, class, variant)."""
+    M = ctx.matrix_from_csr(S)
+    plan, info = ctx.select(M, xab.TIME)
+    x = torch.from_numpy(gen.uniform_vec(S.ncols, seed)).cuda()
+    y = torch.empty(S.n, dtype=torch.float64, device="cuda")
+    ms = ctx.time_spmv(plan, x, y, warmup=5, reps=100)
+    out = (round(ms * 1e3, 2), int(info.chosen), plan.describe()["variant"])
+    plan.close()
+    M.close()
+    return out
+
+
+def shard_leg(ctx, xab, torch, gen, A):
+    """One GPU's share of an 8-GPU row decomposition, at its real shape.
+    Power-law: rows [0, n/8) against the whole x (what each GPU multiplies
+    after the all-gather of x).  27-point 128^3, lower storage, 16 planes
+    [56, 72): the diagonal block (symmetric, lower) plus the coupling block
+    C to the previous shard's last 16,513 rows and its transpose (the
+    partial y sent back), each with its own TIME-selected implementation."""
+    import numpy as np
+    out = {}
+    ns = A.n // 8
+    nz = int(A.rowptr[ns])
+    S = gen.CSR(ns, A.ncols, A.rowptr[:ns + 1].copy(), A.colind[:nz], A.val[:nz], name="powerlaw_shard")
+    us, k, var = _time_selected(ctx, xab, torch, gen, S, 12)
+    by = 12 * nz + 4 * (ns + 1) + 8 * A.ncols + 8 * ns
+    out["powerlaw_rows_div8"] = {"rows": ns, "nnz": nz, "us": us, "class": k, "variant": var,
+                                 "gbs": round(by / (us * 1e-6) / 1e9, 1),
+                                 "allgather_bytes_per_gpu": 8 * (A.ncols - ns)}
+    g = 128
+    L = gen.stencil27(g, lower=True)
+    r0, r1, H = 56 * g * g, 72 * g * g, g * g + g + 1
+    n_s = r1 - r0
+    z0, z1 = int(L.rowptr[r0]), int(L.rowptr[r1])
+    rows = np.repeat(np.arange(n_s), np.diff(L.rowptr[r0:r1 + 1]))
+    cols, vals = L.colind[z0:z1].astype(np.int64), L.val[z0:z1]
+    own = cols >= r0
+    D = _csr_from_coo(gen, rows[own], cols[own] - r0, vals[own], n_s, n_s, lower=True, name="st27_shard_diag")
+    C = _csr_from_coo(gen, rows[~own], cols[~own] - (r0 - H), vals[~own], n_s, H, name="st27_shard_coupling")
+    order = np.lexsort((rows[~own], cols[~own]))
+    CT = _csr_from_coo(gen, (cols[~own] - (r0 - H))[order], rows[~own][order], vals[~own][order], H, n_s,
+                       name="st27_shard_coupling_T")
+    parts, tot_us, tot_by = {}, 0.0, 0
+    for name, S, by in (("diag_sym", D, 12 * D.nnz + 4 * (n_s + 1) + 16 * n_s),
+                        ("coupling", C, 12 * C.nnz + 4 * (n_s + 1) + 8 * H + 8 * n_s),
+                        ("coupling_T", CT, 12 * CT.nnz + 4 * (H + 1) + 8 * n_s + 8 * H)):
+        us, k, var = _time_selected(ctx, xab, torch, gen, S, 13)
+        parts[name] = {"rows": S.n, "cols": S.ncols, "nnz": S.nnz, "us": us, "class": k, "variant": var}
+        tot_us += us
+        tot_by += by
+    out["st27_planes_16"] = {"rows": n_s, "halo_rows": H, "halo_bytes_per_side": 8 * H, **parts,
+                             "us_total": round(tot_us, 2), "gbs": round(tot_by / (tot_us * 1e-6) / 1e9, 1)}
+    return out
+
+
 def sym_stencil_leg(ctx, xab, torch, gen, gmres=True, eig=True):
     """Symmetric SpMV from lower storage on the 128^3 27-point stencil:
     TIME-selected implementation, FP64 and FP32 values (FP64 accumulation),
@@ -402,6 +468,7 @@ def main():
     ap.add_argument("--no-c3", action="store_true", help="skip the symmetric 27-point stencil leg")
     ap.add_argument("--no-batch", action="store_true", help="skip the 512-system batch leg")
     ap.add_argument("--no-eig", action="store_true", help="skip the Lanczos leg")
+    ap.add_argument("--no-shard", action="store_true", help="skip the one-GPU-share leg")
     ap.add_argument("--n", type=int, default=2_000_000)
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     ap.add_argument("--variant", default="XCB")
@@ -494,6 +561,10 @@ def main():
     if not args.no_c3:
         log("symmetric 27-point stencil 128^3 (lower storage)")
         c3 = sym_stencil_leg(ctx, xab, torch, gen, gmres=not args.no_gmres, eig=not args.no_eig)
+    shard = None
+    if not args.no_shard:
+        log("one GPU's share of an 8-way row decomposition")
+        shard = shard_leg(ctx, xab, torch, gen, A)
     c4 = None
     if not args.no_batch:
         log("batch of 512 systems: batched SpMV and BiCGStab")
@@ -530,6 +601,7 @@ def main():
         "gmres": gm,
         "sym27": c3,
         "batch512": c4,
+        "shard_of_8": shard,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
