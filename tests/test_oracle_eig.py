@@ -175,3 +175,104 @@ def test_restart_tuning_cures_slow_convergence():
     assert tuned["matvecs"] < fixed["matvecs"]
     lam = np.sort(2.0 - 2.0 * np.cos(np.arange(1, n + 1) * np.pi / (n + 1)))[::-1][:10]
     assert np.max(np.abs(tuned["evals"] - lam)) <= 1e-10 * tuned["anrm"]
+
+
+# ------------------------------------------------------------- Arnoldi
+def triangular_permuted(n, seed):
+    """P (D + U) P^T: D diagonal with distinct entries, U sparse strictly
+    upper triangular; the eigenvalues are exactly the diagonal entries."""
+    rng = np.random.default_rng(seed)
+    d = np.linspace(0.0, 10.0, n) ** 1.5
+    U = np.triu(rng.standard_normal((n, n)) * (rng.random((n, n)) < 0.01), 1) * 0.3
+    P = np.eye(n)[rng.permutation(n)]
+    return from_dense(P @ (np.diag(d) + U) @ P.T), d
+
+
+def rotation_blocks(nb, seed):
+    """Block-diagonal 2x2 rotation-scalings [[r, -s], [s, r]], permuted: a
+    normal matrix with eigenvalues r_i +- i s_i."""
+    rng = np.random.default_rng(seed)
+    rs, ss = np.linspace(0.1, 3.0, nb), np.linspace(0.5, 1.0, nb)
+    D = np.zeros((2 * nb, 2 * nb))
+    for i in range(nb):
+        D[2 * i:2 * i + 2, 2 * i:2 * i + 2] = [[rs[i], -ss[i]], [ss[i], rs[i]]]
+    P = np.eye(2 * nb)[rng.permutation(2 * nb)]
+    return from_dense(P @ D @ P.T), rs, ss
+
+
+def dense_of_csr(A):
+    D = np.zeros((A.n, A.ncols))
+    for i in range(A.n):
+        D[i, A.colind[A.rowptr[i]:A.rowptr[i + 1]]] += A.val[A.rowptr[i]:A.rowptr[i + 1]]
+    return D
+
+
+@pytest.mark.parametrize("which", [eig.LR, eig.SR, eig.LM])
+def test_arnoldi_triangular_closed_form(which):
+    A, d = triangular_permuted(500, 7)
+    r = eig.arnoldi(A, 8, 30, gen.uniform_vec(500, 1), tol=1e-9, which=which)
+    assert r["status"] == eig.OK and r["restarts"] > 5
+    want = np.sort(d)[::-1][:8] if which != eig.SR else np.sort(d)[:8]
+    assert np.max(np.abs(r["evals"] - want)) <= 1e-9 * r["anrm"]
+    assert np.max(r["resid"]) <= 1.5e-9 * r["anrm"]
+
+
+def test_arnoldi_complex_pairs():
+    """nev = 5 cuts a complex pair, so both members are returned; the pair's
+    vector comes back as real and imaginary parts (dgeev's convention)."""
+    A, rs, ss = rotation_blocks(150, 3)
+    r = eig.arnoldi(A, 5, 30, gen.uniform_vec(300, 2), tol=1e-10, which=eig.LR)
+    assert r["status"] == eig.OK and r["evals"].size == 6
+    want = np.array([rs[-1 - i // 2] + (1j if i % 2 == 0 else -1j) * ss[-1 - i // 2] for i in range(6)])
+    got = np.sort_complex(r["evals"])
+    assert np.max(np.abs(got - np.sort_complex(want))) <= 1e-10 * r["anrm"]
+    D = dense_of_csr(A)
+    for i in (0, 2, 4):
+        lam = r["evals"][i]
+        x = r["evecs"][:, i] + 1j * r["evecs"][:, i + 1]
+        assert np.linalg.norm(D @ x - lam * x) / np.linalg.norm(x) <= 1e-9 * r["anrm"]
+
+
+def test_arnoldi_mild_toeplitz_closed_form():
+    """tridiag(a, b, c) with a c > 0 has the eigenvalues b + 2 sqrt(ac) cos(k pi / (n + 1));
+    a / c close to 1 keeps them well conditioned at n = 60."""
+    n, a, b, c = 60, -1.025, 2.0, -0.975
+    T = np.diag(np.full(n, b)) + np.diag(np.full(n - 1, a), -1) + np.diag(np.full(n - 1, c), 1)
+    lam = b + 2.0 * np.sqrt(a * c) * np.cos(np.arange(1, n + 1) * np.pi / (n + 1))
+    r = eig.arnoldi(from_dense(T), 4, 20, gen.uniform_vec(n, 3), tol=1e-10, which=eig.LR)
+    assert r["status"] == eig.OK
+    assert np.max(np.abs(r["evals"] - np.sort(lam)[::-1][:4])) <= 1e-11
+
+
+def test_arnoldi_full_space_matches_lapack():
+    rng = np.random.default_rng(3)
+    M = rng.standard_normal((40, 40))
+    r = eig.arnoldi(from_dense(M), 5, 40, rng.standard_normal(40), tol=1e-12, which=eig.LM)
+    assert r["status"] == eig.OK and r["restarts"] == 0
+    ref = np.linalg.eigvals(M)
+    ref = ref[np.argsort(-np.abs(ref), kind="stable")][:r["evals"].size]
+    assert np.max(np.abs(np.sort_complex(r["evals"]) - np.sort_complex(ref))) <= 1e-11 * np.abs(ref[0])
+
+
+def test_arnoldi_symmetric_is_lanczos_closed_form():
+    n = 400
+    A = lap1d(n)
+    r = eig.arnoldi(A, 6, 30, gen.uniform_vec(n, 1), tol=1e-9, which=eig.LR)
+    lam = np.sort(2.0 - 2.0 * np.cos(np.arange(1, n + 1) * np.pi / (n + 1)))[::-1][:6]
+    assert r["status"] == eig.OK
+    assert np.max(np.abs(r["evals"] - lam)) <= 1e-10 * r["anrm"]
+
+
+def test_arnoldi_breakdown_and_tuning():
+    A = from_dense(np.diag(np.arange(1.0, 31.0)))
+    v0 = np.zeros(30)
+    v0[[2, 7, 11]] = 1.0
+    assert eig.arnoldi(A, 4, 10, v0)["status"] == eig.BREAKDOWN
+    r = eig.arnoldi(A, 2, 10, v0, which=eig.LR)
+    assert r["status"] == eig.OK and np.allclose(r["evals"], [12.0, 8.0], atol=1e-12)
+    T, d = triangular_permuted(500, 7)
+    r = eig.arnoldi(T, 8, 12, gen.uniform_vec(500, 1), tol=1e-9, step=5, m_max=30, ratio=np.inf, window=3)
+    assert r["m_hist"][:9] == [12] * 3 + [17] * 3 + [22] * 3
+    r0 = eig.arnoldi(T, 8, 12, gen.uniform_vec(500, 1), tol=1e-9, step=5, m_max=30, ratio=0.0, window=3,
+                     maxiter=300)
+    assert set(r0["m_hist"]) == {12}
