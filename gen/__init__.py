@@ -134,6 +134,21 @@ def laplacian2d(g=64, lower=False):
     return stencil(2, 5, g, lower=lower, diag=4.0, off=-1.0, name=f"lap2d_{g}")
 
 
+def convdiff3d(g, beta):
+    """3D 7-point convection-diffusion on a g^3 grid (Dirichlet), central
+    differences with convection along x: 6 on the diagonal, -1 - beta / -1 +
+    beta to the x neighbours below / above, -1 to the others.  Unsymmetric
+    for beta != 0; its eigenvalues are real for abs(beta) < 1:
+    2 + 2 sqrt(1 - beta^2) cos(i pi / (g + 1)) + sum over y, z of
+    2 - 2 cos(j pi / (g + 1))."""
+    A = stencil(3, 7, g, diag=6.0, off=-1.0, name=f"convdiff3d_{g}_{beta}")
+    rows = np.repeat(np.arange(A.n, dtype=np.int64), np.diff(A.rowptr))
+    c = A.colind.astype(np.int64)
+    A.val[c == rows - 1] = -1.0 - beta
+    A.val[c == rows + 1] = -1.0 + beta
+    return A
+
+
 def stencil27(g=128, lower=True):
     """3D 27-point stencil, 27 on the diagonal, -1 off it (Dirichlet)."""
     return stencil(3, 27, g, lower=lower, diag=27.0, off=-1.0, name=f"st27_{g}")

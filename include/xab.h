@@ -334,9 +334,11 @@ typedef struct {
 int xab_gmres(xab_ctx *ctx, const xab_plan *plan, const double *d_b, double *d_x, const xab_krylov_opts *opts,
               xab_krylov_info *info);
 
-/* Restarted Lanczos (section 2.2 solver list, section 4.3 setting). */
-#define XAB_EIG_LARGEST 0  /* largest algebraic eigenvalues */
-#define XAB_EIG_SMALLEST 1 /* smallest algebraic eigenvalues */
+/* Restarted Lanczos and Arnoldi (section 2.2 solver list, section 4.3
+ * setting). */
+#define XAB_EIG_LARGEST 0   /* largest algebraic (Arnoldi: largest real part) */
+#define XAB_EIG_SMALLEST 1  /* smallest algebraic (Arnoldi: smallest real part) */
+#define XAB_EIG_MAGNITUDE 2 /* Arnoldi only: largest magnitude */
 
 typedef struct {
     int32_t nev;        /* wanted eigenpairs, >= 1 */
@@ -360,6 +362,7 @@ typedef struct {
     double seconds;     /* wall time of the call */
     int32_t status;     /* same as the return value */
     int32_t m_final;    /* m of the last cycle */
+    int32_t nret;       /* eigenvalues returned: nev, or nev + 1 when Arnoldi's nev-th is one of a complex pair */
 } xab_eig_info;
 
 /* Thick-restart Lanczos (Wu and Simon's restart; the paper names a
@@ -386,6 +389,27 @@ typedef struct {
  * Synchronous. */
 int xab_lanczos(xab_ctx *ctx, const xab_plan *plan, const double *d_v0, const xab_eig_opts *opts,
                 double *h_evals, double *d_evecs, xab_eig_info *info);
+
+/* Implicitly restarted Arnoldi (the paper's restarted Arnoldi for
+ * unsymmetric matrices, section 2.2; its restart frequency is what
+ * section 4.4.2 tunes) for the nev eigenvalues of a general square A with
+ * the largest or smallest real part or the largest magnitude (opts->which).
+ * Restart: Sorensen's implicit restart with exact shifts (the m - k
+ * unwanted Ritz values as implicit QR shifts, a complex pair as one
+ * double-shift step), k = nev + (m - nev) / 2, moved by one so that no
+ * complex pair is split.  Recurrence, orthogonalisation, convergence test
+ * (residual estimates <= tol * anrm), restart-length tuning and the
+ * statuses as for xab_lanczos; nev + 2 <= m <= min(63, n).  When the nev-th
+ * wanted value is one of a complex pair its partner is returned too
+ * (info->nret = nev + 1).  Out: h_re[nev + 1], h_im[nev + 1] (host, wanted
+ * first, a pair as +im then -im); d_evecs (device FP64, column-major
+ * n x (nev + 1), ld = n): column i the real eigenvector of a real value, a
+ * pair's columns the real and imaginary parts of the eigenvector of its
+ * +im member (LAPACK dgeev's layout), each eigenvector of unit norm.
+ * info->max_resid = max ||A x - lam x|| / anrm over the returned
+ * eigenvectors (complex x for a pair).  Synchronous. */
+int xab_arnoldi(xab_ctx *ctx, const xab_plan *plan, const double *d_v0, const xab_eig_opts *opts, double *h_re,
+                double *h_im, double *d_evecs, xab_eig_info *info);
 
 /* Batch of independent CSR systems concatenated block-diagonally:
  * system k owns rows [h_row_off[k], h_row_off[k+1]) and entries

@@ -27,7 +27,7 @@ MLP_NPARAMS = 64 * 12 + 64 + 64 * 64 + 64 + NCLASSES * 64 + NCLASSES
 MODE_FP64, MODE_IR = 0, 1
 PRECOND_NONE, PRECOND_JACOBI = 0, 1
 ORTHO_DGKS, ORTHO_CGS, ORTHO_MGS, ORTHO_BCGS, ORTHO_POLICY = 0, 1, 2, 3, 4
-EIG_LARGEST, EIG_SMALLEST = 0, 1
+EIG_LARGEST, EIG_SMALLEST, EIG_MAGNITUDE = 0, 1, 2
 
 STATUS = {0: "ok", -1: "null", -2: "shape", -3: "dtype", -4: "struct", -5: "alias", -6: "unsupported",
           -7: "nomem", -8: "device", -9: "align", 1: "not_converged", 2: "breakdown", 3: "time_limit"}
@@ -90,7 +90,7 @@ class EigOpts(ctypes.Structure):
 class EigInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int64), ("restarts", ctypes.c_int64), ("nconv", ctypes.c_int32),
                 ("anrm", ctypes.c_double), ("max_resid", ctypes.c_double), ("seconds", ctypes.c_double),
-                ("status", ctypes.c_int32), ("m_final", ctypes.c_int32)]
+                ("status", ctypes.c_int32), ("m_final", ctypes.c_int32), ("nret", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -131,6 +131,7 @@ SIGNATURES = {
     "xab_selector_loss_grad": (ctypes.c_int, [_P, _P, _P, _P, _I32, _P, ctypes.POINTER(_F)]),
     "xab_gmres": (ctypes.c_int, [_P, _P, _P, _P, ctypes.POINTER(KrylovOpts), ctypes.POINTER(KrylovInfo)]),
     "xab_lanczos": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(EigOpts), _P, _P, ctypes.POINTER(EigInfo)]),
+    "xab_arnoldi": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(EigOpts), _P, _P, _P, ctypes.POINTER(EigInfo)]),
     "xab_batch_csr": (ctypes.c_int, [_P, _I32, _P, _P, _P, _P, _P, ctypes.c_int, _U32, _PP]),
     "xab_batch_destroy": (None, [_P]),
     "xab_batch_layout": (ctypes.c_int, [_P]),
@@ -375,6 +376,23 @@ class Context:
         s = self._check(lib().xab_lanczos(self.h, plan.h, _ptr(v0), ctypes.byref(opts), ev.ctypes.data_as(_P),
                                           _ptr(X), ctypes.byref(info)), "xab_lanczos")
         return ev, X.t(), info.as_dict(), s
+
+    def arnoldi(self, plan, v0, nev=10, m=30, tol=1e-8, maxiter=0, which=EIG_MAGNITUDE, max_time_s=0.0,
+                restart_step=0, m_max=0, mm_ratio=0.0, window=5):
+        """Implicitly restarted Arnoldi: (evals complex numpy[nret], evecs tensor
+        [n, nret] (a complex pair as real and imaginary parts), info dict, status)."""
+        torch = _torch()
+        n = v0.numel()
+        re = np.zeros(nev + 1, dtype=np.float64)
+        im = np.zeros(nev + 1, dtype=np.float64)
+        X = torch.empty((nev + 1, n), dtype=torch.float64, device=v0.device)  # column-major n x (nev + 1)
+        opts = EigOpts(nev=nev, m=m, tol=tol, maxiter=maxiter, max_time_s=max_time_s, which=which,
+                       restart_step=restart_step, m_max=m_max if m_max else m, mm_ratio=mm_ratio, window=window)
+        info = EigInfo()
+        s = self._check(lib().xab_arnoldi(self.h, plan.h, _ptr(v0), ctypes.byref(opts), re.ctypes.data_as(_P),
+                                          im.ctypes.data_as(_P), _ptr(X), ctypes.byref(info)), "xab_arnoldi")
+        k = info.nret
+        return (re + 1j * im)[:k], X[:k].t(), info.as_dict(), s
 
     def batch(self, B, dtype="f64", trust=False, tiles=False):
         return Batch(self, B, dtype, trust, tiles)

@@ -197,3 +197,157 @@ def test_restart_tuning_extremes(ctx):
     with pytest.raises(xab.XabError) as e:
         run(ctx, A, 3, 10, 12, v0, restart_step=5, m_max=64)
     assert e.value.status == -2
+
+
+# --------------------------------------------------------------- Arnoldi
+def from_dense(D):
+    n = D.shape[0]
+    rp, ci, v = [0], [], []
+    for i in range(n):
+        nz = np.nonzero(D[i])[0]
+        ci += list(nz)
+        v += list(D[i, nz])
+        rp.append(len(ci))
+    return gen.CSR(n, n, np.array(rp, np.int32), np.array(ci, np.int32), np.array(v, dtype=np.float64))
+
+
+def triangular_permuted(n, seed):
+    rng = np.random.default_rng(seed)
+    d = np.linspace(0.0, 10.0, n) ** 1.5
+    U = np.triu(rng.standard_normal((n, n)) * (rng.random((n, n)) < 0.01), 1) * 0.3
+    P = np.eye(n)[rng.permutation(n)]
+    D = P @ (np.diag(d) + U) @ P.T
+    return from_dense(D), d, D
+
+
+def rotation_blocks(nb, seed):
+    rng = np.random.default_rng(seed)
+    rs, ss = np.linspace(0.1, 3.0, nb), np.linspace(0.5, 1.0, nb)
+    D = np.zeros((2 * nb, 2 * nb))
+    for i in range(nb):
+        D[2 * i:2 * i + 2, 2 * i:2 * i + 2] = [[rs[i], -ss[i]], [ss[i], rs[i]]]
+    P = np.eye(2 * nb)[rng.permutation(2 * nb)]
+    D = P @ D @ P.T
+    return from_dense(D), rs, ss, D
+
+
+def arun(ctx, A, k, nev, m, v0, **kw):
+    M = ctx.matrix_from_csr(A)
+    P = ctx.plan_class(M, k)
+    ev, X, info, st = ctx.arnoldi(P, dev(v0), nev=nev, m=m, **kw)
+    return ev, X.cpu().numpy(), info, st
+
+
+def check_pairs(D, ev, X, tol_abs):
+    """Every returned eigenpair against the dense matrix (a pair's columns
+    hold the real and imaginary parts of the +im member's vector)."""
+    i = 0
+    while i < ev.size:
+        if ev[i].imag != 0.0:
+            x = X[:, i] + 1j * X[:, i + 1]
+            assert abs(np.linalg.norm(x) - 1.0) <= 1e-10
+            assert np.linalg.norm(D @ x - ev[i] * x) <= tol_abs
+            assert ev[i + 1] == np.conj(ev[i])
+            i += 2
+        else:
+            x = X[:, i]
+            assert abs(np.linalg.norm(x) - 1.0) <= 1e-10
+            assert np.linalg.norm(D @ x - ev[i].real * x) <= tol_abs
+            i += 1
+
+
+@pytest.mark.parametrize("k", (3, 13))
+@pytest.mark.parametrize("which", [xab.EIG_LARGEST, xab.EIG_SMALLEST, xab.EIG_MAGNITUDE])
+def test_arnoldi_triangular_closed_form_vs_oracle(ctx, k, which):
+    n = 500
+    A, d, D = triangular_permuted(n, 7)
+    v0 = gen.uniform_vec(n, 1)
+    owhich = {xab.EIG_LARGEST: eig.LR, xab.EIG_SMALLEST: eig.SR, xab.EIG_MAGNITUDE: eig.LM}[which]
+    ref = eig.arnoldi(A, 8, 30, v0, tol=1e-9, which=owhich)
+    ev, X, info, st = arun(ctx, A, k, 8, 30, v0, tol=1e-9, which=which)
+    assert st == 0 and info["nret"] == 8 and info["nconv"] == 8
+    want = np.sort(d)[::-1][:8] if which != xab.EIG_SMALLEST else np.sort(d)[:8]
+    assert np.max(np.abs(ev - want)) <= 1e-9 * info["anrm"]
+    assert np.max(np.abs(ev - ref["evals"])) <= 1e-9 * info["anrm"]
+    assert info["max_resid"] <= 1.5e-9
+    check_pairs(D, ev, X, 1.5e-9 * info["anrm"])
+    assert abs(info["iters"] - ref["matvecs"]) <= max(10, 0.3 * ref["matvecs"])
+
+
+def test_arnoldi_complex_pairs(ctx):
+    A, rs, ss, D = rotation_blocks(150, 3)
+    v0 = gen.uniform_vec(300, 2)
+    ev, X, info, st = arun(ctx, A, 3, 5, 30, v0, tol=1e-10, which=xab.EIG_LARGEST)
+    assert st == 0 and info["nret"] == 6 and ev.size == 6
+    want = np.array([rs[-1 - i // 2] + (1j if i % 2 == 0 else -1j) * ss[-1 - i // 2] for i in range(6)])
+    assert np.max(np.abs(ev - want)) <= 1e-10 * info["anrm"]
+    check_pairs(D, ev, X, 1.5e-10 * info["anrm"])
+    ref = eig.arnoldi(A, 5, 30, v0, tol=1e-10, which=eig.LR)
+    assert np.max(np.abs(np.sort_complex(ev) - np.sort_complex(ref["evals"]))) <= 1e-10 * info["anrm"]
+
+
+def test_arnoldi_mild_toeplitz_and_symmetric(ctx):
+    n, a, b, c = 60, -1.025, 2.0, -0.975
+    T = np.diag(np.full(n, b)) + np.diag(np.full(n - 1, a), -1) + np.diag(np.full(n - 1, c), 1)
+    lam = b + 2.0 * np.sqrt(a * c) * np.cos(np.arange(1, n + 1) * np.pi / (n + 1))
+    ev, X, info, st = arun(ctx, from_dense(T), 3, 4, 20, gen.uniform_vec(n, 3), tol=1e-10)
+    assert st == 0 and np.max(np.abs(ev - np.sort(lam)[::-1][:4])) <= 1e-11
+    L = lap1d(400)
+    ev, X, info, st = arun(ctx, L, 13, 6, 30, gen.uniform_vec(400, 1), tol=1e-9, which=xab.EIG_LARGEST)
+    want = np.sort(2.0 - 2.0 * np.cos(np.arange(1, 401) * np.pi / 401))[::-1][:6]
+    assert st == 0 and np.max(np.abs(ev - want)) <= 1e-10 * info["anrm"]
+
+
+def test_arnoldi_powerlaw_vs_oracle(ctx):
+    """The power-law family (random columns, dominant diagonal) at n = 20,000:
+    the 10 eigenvalues of largest magnitude against the oracle's."""
+    A = gen.powerlaw(20000, seed=2)
+    v0 = gen.uniform_vec(A.n, 5)
+    ref = eig.arnoldi(A, 10, 30, v0, tol=1e-8, which=eig.LM)
+    ev, X, info, st = arun(ctx, A, 12, 10, 30, v0, tol=1e-8, which=xab.EIG_MAGNITUDE)
+    assert st == 0 and ref["status"] == 0
+    n_ = min(ev.size, ref["evals"].size)
+    assert np.max(np.abs(ev[:n_] - ref["evals"][:n_])) <= 1e-8 * info["anrm"]
+    assert info["max_resid"] <= 1.5e-8
+
+
+def test_arnoldi_breakdown_tuning_and_errors(ctx):
+    n = 64
+    A = gen.CSR(n, n, np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), np.arange(1.0, n + 1))
+    v0 = np.zeros(n)
+    v0[[2, 7, 11]] = 1.0
+    ev, X, info, st = arun(ctx, A, 3, 4, 10, v0)
+    assert st == 2
+    ev, X, info, st = arun(ctx, A, 3, 2, 10, v0, which=xab.EIG_LARGEST)
+    assert st == 0 and np.allclose(ev, [12.0, 8.0], atol=1e-12, rtol=0)
+    T, d, D = triangular_permuted(500, 7)
+    v0 = gen.uniform_vec(500, 1)
+    ev, X, info, st = arun(ctx, T, 3, 8, 12, v0, tol=1e-9, restart_step=5, m_max=30, mm_ratio=np.inf, window=3)
+    assert st == 0 and info["m_final"] == 30
+    ev, X, info, st = arun(ctx, T, 3, 8, 12, v0, tol=1e-9, restart_step=5, m_max=30, mm_ratio=0.0, window=3,
+                           maxiter=300)
+    assert info["m_final"] == 12
+    M = ctx.matrix_from_csr(T)
+    P = ctx.plan_class(M, 3)
+    for kw in ({"nev": 10, "m": 11}, {"nev": 10, "m": 64}, {"which": 3}):
+        with pytest.raises(xab.XabError) as e:
+            ctx.arnoldi(P, dev(v0), **kw)
+        assert e.value.status == -2
+
+
+def test_arnoldi_convdiff_values_in_closed_form(ctx):
+    """Unsymmetric 7-point convection-diffusion (20^3, beta = 0.02): real
+    closed-form spectrum with multiplicities, so the returned values must be
+    eigenvalues of the closed form, the first the largest."""
+    g, beta = 20, 0.02
+    A = gen.convdiff3d(g, beta)
+    ev, X, info, st = arun(ctx, A, 13, 10, 30, gen.uniform_vec(A.n, 5), tol=1e-8, which=xab.EIG_LARGEST)
+    k = np.arange(1, g + 1)
+    lx = 2.0 + 2.0 * np.sqrt(1.0 - beta * beta) * np.cos(k * np.pi / (g + 1))
+    ly = 2.0 - 2.0 * np.cos(k * np.pi / (g + 1))
+    lam = np.sort((lx[:, None, None] + ly[None, :, None] + ly[None, None, :]).ravel())
+    assert st == 0
+    assert abs(ev[0].real - lam[-1]) <= 1e-9 * info["anrm"]
+    for v in ev:
+        assert abs(v.imag) <= 1e-9 * info["anrm"] and np.min(np.abs(lam - v.real)) <= 1e-9 * info["anrm"]
+    assert info["max_resid"] <= 1.5e-8

@@ -276,3 +276,30 @@ def test_arnoldi_breakdown_and_tuning():
     r0 = eig.arnoldi(T, 8, 12, gen.uniform_vec(500, 1), tol=1e-9, step=5, m_max=30, ratio=0.0, window=3,
                      maxiter=300)
     assert set(r0["m_hist"]) == {12}
+
+
+def convdiff_eigs(g, beta):
+    k = np.arange(1, g + 1)
+    lx = 2.0 + 2.0 * np.sqrt(1.0 - beta * beta) * np.cos(k * np.pi / (g + 1))
+    ly = 2.0 - 2.0 * np.cos(k * np.pi / (g + 1))
+    return np.sort((lx[:, None, None] + ly[None, :, None] + ly[None, None, :]).ravel())
+
+
+def test_convdiff_generator_spectrum():
+    """The generator's convection-diffusion matrix has the stated closed-form
+    (real) spectrum: checked against LAPACK on an 8^3 grid."""
+    A = gen.convdiff3d(8, 0.3)
+    ev = np.linalg.eigvals(dense_of_csr(A))
+    assert np.max(np.abs(ev.imag)) <= 1e-10
+    assert np.max(np.abs(np.sort(ev.real) - convdiff_eigs(8, 0.3))) <= 1e-11
+
+
+def test_arnoldi_convdiff_values_in_closed_form():
+    g, beta = 12, 0.02
+    A = gen.convdiff3d(g, beta)
+    r = eig.arnoldi(A, 6, 30, gen.uniform_vec(A.n, 5), tol=1e-8, which=eig.LR)
+    lam = convdiff_eigs(g, beta)
+    assert r["status"] == eig.OK
+    assert abs(r["evals"][0].real - lam[-1]) <= 1e-9 * r["anrm"]
+    for v in r["evals"]:
+        assert abs(v.imag) <= 1e-9 * r["anrm"] and np.min(np.abs(lam - v.real)) <= 1e-9 * r["anrm"]
