@@ -307,6 +307,55 @@ def lanczos_leg(ctx, xab, torch, gen, plan, g):
     return out
 
 
+def arnoldi_leg(ctx, xab, torch, gen, plan_c2, n_c2):
+    """Implicitly restarted Arnoldi (10 eigenvalues to 1e-8): the power-law
+    matrix's largest-magnitude ones (fixed m = 30), and the 128^3
+    convection-diffusion operator's largest-real-part ones, fixed m = 30
+    against restart-length tuning from 20 (m += 5 up to 60 when the MM
+    ratio of 5 per-cycle samples is below 2), with the distance of every
+    value to that operator's closed-form spectrum."""
+    import numpy as np
+    out = {}
+    v0 = torch.from_numpy(gen.uniform_vec(n_c2, 5)).cuda()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev, X, info, st = ctx.arnoldi(plan_c2, v0, nev=10, m=30, tol=1e-8, which=xab.EIG_MAGNITUDE, max_time_s=60.0)
+    torch.cuda.synchronize()
+    out["powerlaw_largest_magnitude_m30"] = {
+        "s": round(time.perf_counter() - t0, 4), "status": st, "matvecs": info["iters"],
+        "restarts": info["restarts"], "max_resid_rel": info["max_resid"],
+        "evals": [str(complex(round(v.real, 9), round(v.imag, 9))) for v in (ev[0], ev[-1])]}
+    del X
+    g, beta = 128, 0.02
+    A = gen.convdiff3d(g, beta)
+    k = np.arange(1, g + 1)
+    lx = 2.0 + 2.0 * np.sqrt(1.0 - beta * beta) * np.cos(k * np.pi / (g + 1))
+    ly = 2.0 - 2.0 * np.cos(k * np.pi / (g + 1))
+    lam = np.sort((lx[:, None, None] + ly[None, :, None] + ly[None, None, :]).ravel())
+    M = ctx.matrix_from_csr(A)
+    plan, sinfo = ctx.select(M, xab.TIME)
+    v0 = torch.from_numpy(gen.uniform_vec(A.n, 5)).cuda()
+    out["convdiff_workload"] = f"7-point convection-diffusion {g}^3, beta = {beta}: n={A.n} nnz={A.nnz}"
+    out["convdiff_selected"] = plan.describe()["variant"]
+    for tag, kw in (("fixed_m30", dict(m=30)),
+                    ("tuned_m20_to_60", dict(m=20, restart_step=5, m_max=60, mm_ratio=2.0, window=5))):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev, X, info, st = ctx.arnoldi(plan, v0, nev=10, tol=1e-8, which=xab.EIG_LARGEST, max_time_s=60.0, **kw)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        out[f"convdiff_largest_real_{tag}"] = {
+            "s": round(wall, 4), "status": st, "matvecs": info["iters"], "restarts": info["restarts"],
+            "m_final": info["m_final"], "ms_per_matvec": round(wall / max(1, info["iters"]) * 1e3, 4),
+            "max_resid_rel": info["max_resid"],
+            "closed_form_err_rel": max(float(np.min(np.abs(lam - v.real))) for v in ev) / info["anrm"],
+            "max_abs_imag": float(np.max(np.abs(ev.imag)))}
+        del X
+    plan.close()
+    M.close()
+    return out
+
+
 def _csr_from_coo(gen, rows, cols, vals, nr, nc, lower=False, name=""):
     """CSR from entries already ordered by (row, column)."""
     import numpy as np
@@ -467,7 +516,7 @@ def main():
     ap.add_argument("--no-gmres", action="store_true")
     ap.add_argument("--no-c3", action="store_true", help="skip the symmetric 27-point stencil leg")
     ap.add_argument("--no-batch", action="store_true", help="skip the 512-system batch leg")
-    ap.add_argument("--no-eig", action="store_true", help="skip the Lanczos leg")
+    ap.add_argument("--no-eig", action="store_true", help="skip the Lanczos and Arnoldi legs")
     ap.add_argument("--no-shard", action="store_true", help="skip the one-GPU-share leg")
     ap.add_argument("--n", type=int, default=2_000_000)
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
@@ -557,6 +606,11 @@ def main():
         gm = gmres_pair(ctx, xab, torch, plan, A.n)
         gm["ortho_menu"] = ortho_menu_leg(ctx, xab, torch, plan, A.n)
 
+    arn = None
+    if not args.no_eig:
+        log("Arnoldi (power-law, convection-diffusion)")
+        arn = arnoldi_leg(ctx, xab, torch, gen, plan, A.n)
+
     c3 = None
     if not args.no_c3:
         log("symmetric 27-point stencil 128^3 (lower storage)")
@@ -602,6 +656,7 @@ def main():
         "sym27": c3,
         "batch512": c4,
         "shard_of_8": shard,
+        "arnoldi": arn,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
