@@ -38,6 +38,7 @@ def lib():
             "orc_plan_xcb": (None, [i64, i64, P, P, ci, P, P]),
             "orc_xcb_flag_heads": (None, [i64, ci, P, P]),
             "orc_plan_sell": (i64, [i64, P, P, P, ci, ci, P, P, P, P, P, P]),
+            "orc_plan_bcsr": (i64, [i64, P, P, P, ci, P, P, P, P]),
             "orc_features": (None, [i64, P, P, ci, P, P]),
             "orc_mlp_nparams": (i64, [ci, ci, ci]),
             "orc_mlp_forward": (None, [ci, ci, ci, P, i64, P, P]),
@@ -178,6 +179,21 @@ def plan_sell(A, C=64, sigma=1024):
     vals = np.empty(max(tot, 1), dtype=np.float64)
     lib().orc_plan_sell(n, _p(rp), _p(ci), _p(v), C, sigma, _p(perm), _p(cptr), _p(clen), _p(rlen), _p(cols), _p(vals))
     return dict(perm=perm[:n], cptr=cptr, clen=clen[:nch], rlen=rlen[:n], cols=cols[:tot], vals=vals[:tot])
+
+
+def plan_bcsr(A, b=4):
+    """Block CSR layout: dict(brp int64[nbr+1], bci int32[nb], bmask uint32[nb],
+    bval float64[nb, b*b])."""
+    rp, ci, v = _csr(A)
+    n = A.n
+    nbr = (n + b - 1) // b
+    brp = np.empty(nbr + 1, dtype=np.int64)
+    nb = lib().orc_plan_bcsr(n, _p(rp), _p(ci), _p(v), b, _p(brp), None, None, None)
+    bci = np.empty(max(nb, 1), dtype=np.int32)
+    bmask = np.empty(max(nb, 1), dtype=np.uint32)
+    bval = np.empty((max(nb, 1), b * b), dtype=np.float64)
+    lib().orc_plan_bcsr(n, _p(rp), _p(ci), _p(v), b, _p(brp), _p(bci), _p(bmask), _p(bval))
+    return dict(brp=brp, bci=bci[:nb], bmask=bmask[:nb], bval=bval[:nb])
 
 
 # ------------------------------------------------------------------ features

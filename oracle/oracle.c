@@ -324,6 +324,60 @@ void orc_xcb_flag_heads(int64_t n, int nb, const int32_t *rp, int32_t *ci) {
     }
 }
 
+/* Block CSR (orc_plan_bcsr in oracle.h): per block row, the block columns
+ * of its entries are collected, sorted and made unique; each entry then
+ * finds its block by binary search and adds its value to its position. */
+static int cmp_i32(const void *a, const void *b) {
+    const int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+    return x < y ? -1 : x > y;
+}
+
+int64_t orc_plan_bcsr(int64_t n, const int32_t *rowptr, const int32_t *colind, const double *val, int b,
+                      int64_t *brp, int32_t *bci, uint32_t *bmask, double *bval) {
+    const int64_t nbr = (n + b - 1) / b;
+    int64_t total = 0;
+    int64_t cap = 16;
+    int32_t *tmp = (int32_t *)malloc(sizeof(int32_t) * cap);
+    if (brp) brp[0] = 0;
+    for (int64_t R = 0; R < nbr; ++R) {
+        const int64_t r0 = R * b, r1 = r0 + b < n ? r0 + b : n;
+        const int64_t k0 = rowptr[r0], k1 = rowptr[r1];
+        if (k1 - k0 > cap) {
+            cap = k1 - k0;
+            tmp = (int32_t *)realloc(tmp, sizeof(int32_t) * cap);
+        }
+        for (int64_t k = k0; k < k1; ++k) tmp[k - k0] = colind[k] / b;
+        qsort(tmp, (size_t)(k1 - k0), sizeof(int32_t), cmp_i32);
+        int64_t u = 0;
+        for (int64_t k = 0; k < k1 - k0; ++k)
+            if (k == 0 || tmp[k] != tmp[k - 1]) tmp[u++] = tmp[k];
+        if (bci) {
+            for (int64_t q = 0; q < u; ++q) {
+                bci[total + q] = tmp[q];
+                bmask[total + q] = 0;
+                for (int e = 0; e < b * b; ++e) bval[(total + q) * b * b + e] = 0.0;
+            }
+            for (int64_t r = r0; r < r1; ++r)
+                for (int64_t k = rowptr[r]; k < rowptr[r + 1]; ++k) {
+                    const int32_t cb = colind[k] / b;
+                    int64_t lo = 0, hi = u;  /* first position with tmp[pos] >= cb */
+                    while (lo < hi) {
+                        const int64_t mid = (lo + hi) / 2;
+                        if (tmp[mid] < cb) lo = mid + 1;
+                        else hi = mid;
+                    }
+                    const int e = (int)(r - r0) * b + colind[k] % b;
+                    bmask[total + lo] |= 1u << e;
+                    bval[(total + lo) * b * b + e] += val[k];
+                }
+        }
+        total += u;
+        if (brp) brp[R + 1] = total;
+    }
+    free(tmp);
+    return total;
+}
+
 /* Sliced ELLPACK with sorting window (SELL-C-sigma, a format the paper
  * lists among future SpMV candidates, section 5): inside every window of
  * sigma rows the rows are ordered by length, longest first (ties keep the

@@ -67,6 +67,14 @@ void orc_xcb_flag_heads(int64_t n, int nb, const int32_t *rp, int32_t *ci);
 int64_t orc_plan_sell(int64_t n, const int32_t *rowptr, const int32_t *colind, const double *val, int C,
                       int sigma, int32_t *perm, int64_t *cptr, int32_t *clen, int32_t *rlen, int32_t *cols,
                       double *vals);
+/* Block CSR with b x b blocks (section 5 leaves BCSR to future work): block
+ * row R holds rows [bR, min(bR + b, n)); its blocks are the distinct c / b of
+ * its entries, ascending; a block stores b*b values row-major (0 where the
+ * matrix has no entry, duplicates summed in CSR order) and a mask with bit
+ * (r % b) * b + c % b set for every stored position.  Returns the number of
+ * blocks; brp[nbr + 1], bci, bmask and bval may be NULL (count only). */
+int64_t orc_plan_bcsr(int64_t n, const int32_t *rowptr, const int32_t *colind, const double *val, int b,
+                      int64_t *brp, int32_t *bci, uint32_t *bmask, double *bval);
 
 /* Selector features: integer statistics then the 12 features. */
 void orc_features(int64_t n, const int32_t *rowptr, const int32_t *colind, int sym_lower,

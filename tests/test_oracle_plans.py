@@ -390,3 +390,74 @@ def test_sell_walk_is_exact():
             s += p["vals"][q] * x[p["cols"][q]]
         y[p["perm"][r]] = s
     assert np.array_equal(y, oracle.spmv(A, x)[0])
+
+
+# ------------------------------------------------------------------ BCSR
+def _bcsr_brute(A, b):
+    """Block CSR from its definition, by dictionaries."""
+    nbr = (A.n + b - 1) // b
+    brp, bci, bmask, bval = [0], [], [], []
+    for R in range(nbr):
+        blocks = {}
+        for r in range(R * b, min(R * b + b, A.n)):
+            for k in range(A.rowptr[r], A.rowptr[r + 1]):
+                c = int(A.colind[k])
+                blk = blocks.setdefault(c // b, [0, np.zeros(b * b)])
+                e = (r - R * b) * b + c % b
+                blk[0] |= 1 << e
+                blk[1][e] += A.val[k]
+        for cb in sorted(blocks):
+            bci.append(cb)
+            bmask.append(blocks[cb][0])
+            bval.append(blocks[cb][1])
+        brp.append(len(bci))
+    return np.array(brp), np.array(bci), np.array(bmask), np.array(bval).reshape(-1, b * b)
+
+
+@pytest.mark.parametrize("lengths,ncols,b", [
+    ([3, 0, 7, 1, 12, 0, 5, 9, 9, 2] * 7, 90, 4),
+    ([0] * 9, 9, 4),                       # all empty
+    ([1] * 13, 13, 4),                     # ragged last block row
+    ([30, 0, 0, 30, 5], 31, 4),            # columns near the end, empty rows inside a block row
+    ([3, 3, 3], 7, 2),
+])
+def test_bcsr_brute(lengths, ncols, b):
+    A = _mat(lengths, seed=11, ncols=ncols)
+    p = oracle.plan_bcsr(A, b)
+    brp, bci, bmask, bval = _bcsr_brute(A, b)
+    assert np.array_equal(p["brp"], brp)
+    assert np.array_equal(p["bci"], bci.astype(np.int32).reshape(-1))
+    assert np.array_equal(p["bmask"], bmask.astype(np.uint32).reshape(-1))
+    assert np.array_equal(p["bval"], bval.reshape(-1, b * b) if bval.size else p["bval"])
+
+
+def test_bcsr_duplicates_summed_and_dense_reconstruction():
+    rp = np.array([0, 3, 3, 5], dtype=np.int32)
+    ci = np.array([2, 2, 5, 0, 5], dtype=np.int32)   # (0, 2) twice
+    v = np.array([1.0, 2.0, 3.0, 4.0, 5.0])
+    A = gen.CSR(3, 6, rp, ci, v)
+    p = oracle.plan_bcsr(A, 4)
+    D = np.zeros((4, 8))
+    for q, cb in enumerate(p["bci"]):
+        D[:, cb * 4:cb * 4 + 4] += p["bval"][q].reshape(4, 4)
+    want = np.zeros((4, 8))
+    want[0, 2], want[0, 5], want[2, 0], want[2, 5] = 3.0, 3.0, 4.0, 5.0
+    assert np.array_equal(D, want)
+    assert list(p["bmask"]) == [(1 << 2) | (1 << 8), 1 << 1 | 1 << 9]
+
+
+def test_bcsr_walk_is_exact():
+    """Block-row sums over the masked block entries reproduce A x exactly
+    (integer values)."""
+    A = _mat([3, 0, 7, 1, 12, 0, 5, 9, 9, 2] * 13, seed=7, ncols=90)
+    x = gen.int_vec(A.ncols, 2)
+    b = 4
+    p = oracle.plan_bcsr(A, b)
+    y = np.zeros(A.n)
+    for R in range(len(p["brp"]) - 1):
+        for q in range(p["brp"][R], p["brp"][R + 1]):
+            for e in range(b * b):
+                if p["bmask"][q] >> e & 1:
+                    r, c = R * b + e // b, p["bci"][q] * b + e % b
+                    y[r] += p["bval"][q][e] * x[c]
+    assert np.array_equal(y, oracle.spmv(A, x)[0])
