@@ -94,7 +94,16 @@ typedef enum { XAB_TIME = 0, XAB_STABLE = 1, XAB_LEARNED = 2 } xab_policy;
  *                  one lane sums one row.  The plan owns the padded copy.
  *                  XAB_E_UNSUPPORTED when a row is longer than 4096 or the
  *                  padded size would exceed twice the entries plus one
- *                  chunk of the longest row. */
+ *                  chunk of the longest row.
+ *   XAB_BCSR       block CSR with 4 x 4 blocks (another future-work format
+ *                  of section 5): block row R covers rows 4R .. 4R+3, its
+ *                  blocks are the distinct column blocks c / 4 of its
+ *                  entries, each stored as 16 values (row-major, zeros
+ *                  where no entry, duplicates summed) plus a mask of the
+ *                  stored positions; one lane sums one block row.  The plan
+ *                  owns the copy.  XAB_E_UNSUPPORTED when a block row has
+ *                  more than 4096 entries or the blocks would hold more
+ *                  than twice the entries. */
 typedef enum {
     XAB_ROW = 0,
     XAB_NNZ = 1,
@@ -102,7 +111,8 @@ typedef enum {
     XAB_SYM_S3 = 3,
     XAB_SYM_ATOMIC = 4,
     XAB_XCB = 5,
-    XAB_SELL = 6
+    XAB_SELL = 6,
+    XAB_BCSR = 7
 } xab_variant;
 
 typedef struct {
@@ -121,9 +131,9 @@ typedef struct {
 #define XAB_BATCH_TILES 4u /* xab_batch_csr: segmented-scan tiles only, no sliced ELLPACK copy */
 
 /* Selector classes: fixed (variant, params) pairs, the action space of the
- * selector.  0..8, 12 and 13 apply to general matrices, 9..11 to
+ * selector.  0..8 and 12..14 apply to general matrices, 9..11 to
  * XAB_SYM_LOWER. */
-#define XAB_NCLASSES 14
+#define XAB_NCLASSES 15
 int xab_class_params(int32_t k, xab_variant *variant, xab_params *params);
 
 typedef struct {
@@ -173,7 +183,8 @@ void xab_plan_destroy(xab_plan *plan);
  * (8 x (nrows+1), block-major), 10 XCB column indices in block order,
  * bit 31 set on the first entry of each row within its block, 11 SELL
  * row order (original row of each ordered row), 12 SELL ordered row
- * lengths, 13 SELL chunk widths, 14 SELL padded column indices.
+ * lengths, 13 SELL chunk widths, 14 SELL padded column indices, 15 BCSR
+ * block row pointers, 16 BCSR block columns, 17 BCSR position masks.
  * *len receives the length; h_out may be NULL to query it.  Synchronous. */
 int xab_plan_array(const xab_plan *plan, int32_t which, int32_t *h_out, int64_t *len);
 int xab_plan_info(const xab_plan *plan, xab_variant *v, xab_params *p);

@@ -15,12 +15,12 @@ LIB_PATH = os.path.join(HERE, "libxab.so")
 
 F64, F32 = 0, 1
 TIME, STABLE, LEARNED = 0, 1, 2
-ROW, NNZ, BSS, SYM_S3, SYM_ATOMIC, XCB, SELL = 0, 1, 2, 3, 4, 5, 6
+ROW, NNZ, BSS, SYM_S3, SYM_ATOMIC, XCB, SELL, BCSR = 0, 1, 2, 3, 4, 5, 6, 7
 VARIANT_NAMES = {ROW: "row", NNZ: "nnz", BSS: "bss", SYM_S3: "sym_s3", SYM_ATOMIC: "sym_atomic", XCB: "xcb",
-                 SELL: "sell"}
+                 SELL: "sell", BCSR: "bcsr"}
 GENERAL, SYM_LOWER, TRUST_INPUT, BATCH_TILES = 0, 1, 2, 4
-NCLASSES = 14
-GENERAL_CLASSES = tuple(range(9)) + (12, 13)
+NCLASSES = 15
+GENERAL_CLASSES = tuple(range(9)) + (12, 13, 14)
 SYM_CLASSES = (9, 10, 11)
 NFEAT = 12
 MLP_NPARAMS = 64 * 12 + 64 + 64 * 64 + 64 + NCLASSES * 64 + NCLASSES

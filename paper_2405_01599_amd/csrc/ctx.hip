@@ -159,6 +159,7 @@ int xab_class_params(int32_t k, xab_variant *v, xab_params *p) {
         case 11: *v = XAB_SYM_S3; q.col_block = 256; q.tile_nnz = 8192; q.tile_rows = 1024; break;
         case 12: *v = XAB_XCB; q.j_per_lane = 4; break;
         case 13: *v = XAB_SELL; q.tile_rows = 1024; break;
+        case 14: *v = XAB_BCSR; break;
         default: return XAB_E_SHAPE;
     }
     *p = q;

@@ -108,6 +108,15 @@ struct xab_plan {
     static constexpr int kSellC = 64;
     static constexpr int kSellMaxRow = 4096;
     xab_sell sell;
+    // BCSR: 4 x 4 blocks, 16 values row-major per block
+    static constexpr int kBcsrB = 4;
+    static constexpr int kBcsrMaxRow = 4096;  // entries of one block row (set-up sorts them in LDS)
+    int64_t bcsr_nbr = 0, bcsr_nb = 0;
+    int32_t *bcsr_brp = nullptr;   // [nbr + 1] block row pointers
+    int32_t *bcsr_bci = nullptr;   // block columns, ascending within a block row
+    int32_t *bcsr_mask = nullptr;  // bit (r % 4) * 4 + c % 4 for every stored position
+    double *bcsr_val64 = nullptr;
+    float *bcsr_val32 = nullptr;
 };
 
 struct xab_batch {

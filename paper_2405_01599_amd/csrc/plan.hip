@@ -446,6 +446,119 @@ __global__ void k_sell_scan(const int32_t *clen, int64_t nch, int64_t *cptr) {
     }
 }
 
+// ------------------------------------------------------------------ BCSR
+// One workgroup per block row R: the block columns c / 4 of the entries of
+// rows 4R .. 4R+3 are loaded into LDS and sorted (bitonic, padded with
+// INT_MAX to a power of two).  Returns the entry count, or -1 when it is
+// above kBcsrMaxRow (nothing loaded).
+constexpr int kBcsrNT = 256;
+
+__device__ int bcsr_sorted_cols(const int32_t *rowptr, const int32_t *colind, int32_t n, int64_t R, int32_t *key) {
+    constexpr int B = xab_plan::kBcsrB;
+    const int64_t r0 = R * B, r1 = r0 + B < n ? r0 + B : n;
+    const int32_t k0 = rowptr[r0];
+    const int L = rowptr[r1] - k0;
+    if (L > xab_plan::kBcsrMaxRow) return -1;
+    int P2 = 1;
+    while (P2 < L) P2 <<= 1;
+    for (int i = threadIdx.x; i < P2; i += kBcsrNT) key[i] = i < L ? colind[k0 + i] / B : INT32_MAX;
+    __syncthreads();
+    for (int size = 2; size <= P2; size <<= 1)
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int i = threadIdx.x; i < P2; i += kBcsrNT) {
+                const int partner = i ^ stride;
+                if (partner > i) {
+                    const bool up = (i & size) == 0;
+                    const int32_t a = key[i], b = key[partner];
+                    if ((a > b) == up) {
+                        key[i] = b;
+                        key[partner] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    return L;
+}
+
+// cnt[R] = distinct block columns of block row R; *bad = 1 when a block row is too long
+__global__ __launch_bounds__(kBcsrNT) void k_bcsr_count(const int32_t *rowptr, const int32_t *colind, int32_t n,
+                                                        int32_t *cnt, int *bad) {
+    __shared__ int32_t key[xab_plan::kBcsrMaxRow];
+    __shared__ int32_t red[kBcsrNT];
+    const int64_t R = blockIdx.x;
+    const int L = bcsr_sorted_cols(rowptr, colind, n, R, key);
+    if (L < 0) {
+        if (threadIdx.x == 0) {
+            cnt[R] = 0;
+            atomicOr(bad, 1);
+        }
+        return;
+    }
+    int c = 0;
+    for (int i = threadIdx.x; i < L; i += kBcsrNT) c += (i == 0 || key[i] != key[i - 1]) ? 1 : 0;
+    red[threadIdx.x] = c;
+    __syncthreads();
+    for (int d = kBcsrNT / 2; d > 0; d >>= 1) {
+        if (threadIdx.x < d) red[threadIdx.x] += red[threadIdx.x + d];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) cnt[R] = red[0];
+}
+
+// block columns of block row R at bci[brp[R] ..], then every entry added to
+// its position (values and masks zeroed beforehand; duplicates summed)
+__global__ __launch_bounds__(kBcsrNT) void k_bcsr_fill(const int32_t *rowptr, const int32_t *colind, const double *v64,
+                                                       const float *v32, int32_t n, const int32_t *brp, int32_t *bci,
+                                                       int32_t *mask, double *b64, float *b32) {
+    constexpr int B = xab_plan::kBcsrB;
+    __shared__ int32_t key[xab_plan::kBcsrMaxRow];
+    __shared__ int32_t uniq[xab_plan::kBcsrMaxRow];
+    __shared__ int32_t part[kBcsrNT];
+    const int64_t R = blockIdx.x;
+    const int L = bcsr_sorted_cols(rowptr, colind, n, R, key);
+    if (L <= 0) return;
+    // compaction of the distinct values: contiguous slices per thread, then a block scan
+    const int per = (L + kBcsrNT - 1) / kBcsrNT;
+    const int i0 = threadIdx.x * per, i1 = i0 + per < L ? i0 + per : L;
+    int c = 0;
+    for (int i = i0; i < i1; ++i) c += (i == 0 || key[i] != key[i - 1]) ? 1 : 0;
+    part[threadIdx.x] = c;
+    __syncthreads();
+    for (int d = 1; d < kBcsrNT; d <<= 1) {
+        const int32_t u = threadIdx.x >= d ? part[threadIdx.x - d] : 0;
+        __syncthreads();
+        part[threadIdx.x] += u;
+        __syncthreads();
+    }
+    int o = part[threadIdx.x] - c;
+    const int U = part[kBcsrNT - 1];
+    const int32_t base = brp[R];
+    for (int i = i0; i < i1; ++i)
+        if (i == 0 || key[i] != key[i - 1]) {
+            uniq[o] = key[i];
+            bci[base + o] = key[i];
+            ++o;
+        }
+    __syncthreads();
+    const int64_t r0 = R * B, r1 = r0 + B < n ? r0 + B : n;
+    for (int64_t r = r0; r < r1; ++r)
+        for (int32_t k = rowptr[r] + threadIdx.x; k < rowptr[r + 1]; k += kBcsrNT) {
+            const int32_t col = colind[k], cb = col / B;
+            int lo = 0, hi = U;  // first position with uniq[pos] >= cb
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (uniq[mid] < cb) lo = mid + 1;
+                else hi = mid;
+            }
+            const int64_t blk = base + lo;
+            const int e = (int)(r - r0) * B + col % B;
+            atomicOr(&mask[blk], 1 << e);
+            if (b64) atomicAdd(&b64[blk * B * B + e], v64[k]);
+            if (b32) atomicAdd(&b32[blk * B * B + e], v32[k]);
+        }
+}
+
 // one lane per ordered row slot (nch * C of them): copy its row into the
 // chunk's columns, zeros past the row's end
 __global__ void k_sell_fill(const int32_t *rowptr, const int32_t *colind, const double *v64, const float *v32,
@@ -490,6 +603,11 @@ static void free_plan_arrays(xab_ctx *ctx, xab_plan *pl) {
     xab_dfree(ctx, pl->s3_ci);
     xab_dfree(ctx, pl->s3_dense);
     xab_sell_free(ctx, &pl->sell);
+    xab_dfree(ctx, pl->bcsr_brp);
+    xab_dfree(ctx, pl->bcsr_bci);
+    xab_dfree(ctx, pl->bcsr_mask);
+    xab_dfree(ctx, pl->bcsr_val64);
+    xab_dfree(ctx, pl->bcsr_val32);
     xab_dfree(ctx, pl->xcb_mask);
     xab_dfree(ctx, pl->xcb_colind);
     xab_dfree(ctx, pl->xcb_val64);
@@ -629,6 +747,8 @@ int xab_build_plan(xab_ctx *ctx, const xab_matrix *A, xab_variant v, const xab_p
             if (p.tile_rows < xab_plan::kSellC || p.tile_rows > 1024 || p.tile_rows % xab_plan::kSellC != 0)
                 return xab_fail(ctx, XAB_E_UNSUPPORTED, "SELL window (tile_rows) must be a multiple of 64 in [64, 1024]");
             break;
+        case XAB_BCSR:
+            break;
         case XAB_SYM_S3:
             if (!pow2(p.col_block) || p.col_block < 16 || p.col_block > xab::sym::kExtCap)
                 return xab_fail(ctx, XAB_E_UNSUPPORTED, "col_block must be a power of two in [16, %d]",
@@ -679,6 +799,72 @@ int xab_build_plan(xab_ctx *ctx, const xab_matrix *A, xab_variant v, const xab_p
             free_plan_arrays(ctx, pl);
             delete pl;
             return s;
+        }
+    } else if (v == XAB_BCSR) {
+        constexpr int B = xab_plan::kBcsrB;
+        const int64_t nbr = ((int64_t)n + B - 1) / B;
+        pl->bcsr_nbr = nbr;
+        pl->P = std::max<int64_t>(1, nbr);
+        ALLOC(pl->bcsr_brp, int32_t, nbr + 1);
+        int32_t *cnt = (int32_t *)xab_dalloc(ctx, sizeof(int32_t) * (size_t)std::max<int64_t>(1, nbr));
+        const int64_t ntile = (nbr + kScanTile - 1) / kScanTile;
+        int32_t *sums = (int32_t *)xab_dalloc(ctx, sizeof(int32_t) * (ntile + 2));
+        int32_t *offs = (int32_t *)xab_dalloc(ctx, sizeof(int32_t) * (ntile + 2));
+        auto cleanup = [&]() {
+            xab_dfree(ctx, cnt);
+            xab_dfree(ctx, sums);
+            xab_dfree(ctx, offs);
+        };
+        if (!cnt || !sums || !offs) {
+            cleanup();
+            free_plan_arrays(ctx, pl);
+            delete pl;
+            return xab_fail(ctx, XAB_E_NOMEM, "BCSR plan");
+        }
+        hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, st, (int32_t *)ctx->d_flag, (int64_t)1);
+        if (nbr > 0)
+            hipLaunchKernelGGL(k_bcsr_count, dim3((unsigned)nbr), dim3(kBcsrNT), 0, st, A->rowptr, A->colind, n, cnt,
+                               ctx->d_flag);
+        const unsigned g = (unsigned)std::max<int64_t>(1, ntile);
+        hipLaunchKernelGGL(k_scan_tile_sums, dim3(g), dim3(256), 0, st, cnt, nbr, sums);
+        hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, st, sums, (int64_t)g, offs);
+        hipLaunchKernelGGL(k_scan_tile_apply, dim3(g), dim3(256), 0, st, cnt, nbr, offs, pl->bcsr_brp);
+        int32_t hdr[2] = {0, 0};
+        hipError_t e = hipGetLastError();
+        if (e == hipSuccess) e = hipMemcpyAsync(&hdr[0], pl->bcsr_brp + nbr, sizeof(int32_t), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(&hdr[1], ctx->d_flag, sizeof(int32_t), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        cleanup();
+        if (e != hipSuccess) {
+            free_plan_arrays(ctx, pl);
+            delete pl;
+            return xab_hip_check(ctx, e, "BCSR layout");
+        }
+        const int64_t nb = hdr[0];
+        pl->bcsr_nb = nb;
+        if (hdr[1] || nb * B * B > 2 * nnz) {
+            free_plan_arrays(ctx, pl);
+            delete pl;
+            return xab_fail(ctx, XAB_E_UNSUPPORTED, "BCSR: %s",
+                            hdr[1] ? "a block row has more than 4096 entries" : "the blocks would hold more than twice the entries");
+        }
+        const int64_t nbx = std::max<int64_t>(1, nb);
+        ALLOC(pl->bcsr_bci, int32_t, nbx);
+        ALLOC(pl->bcsr_mask, int32_t, nbx);
+        if (A->has64) ALLOC(pl->bcsr_val64, double, nbx * B * B);
+        if (A->has32) ALLOC(pl->bcsr_val32, float, nbx * B * B);
+        e = hipMemsetAsync(pl->bcsr_mask, 0, sizeof(int32_t) * nbx, st);
+        if (e == hipSuccess && pl->bcsr_val64) e = hipMemsetAsync(pl->bcsr_val64, 0, sizeof(double) * nbx * B * B, st);
+        if (e == hipSuccess && pl->bcsr_val32) e = hipMemsetAsync(pl->bcsr_val32, 0, sizeof(float) * nbx * B * B, st);
+        if (e == hipSuccess && nbr > 0 && nb > 0)
+            hipLaunchKernelGGL(k_bcsr_fill, dim3((unsigned)nbr), dim3(kBcsrNT), 0, st, A->rowptr, A->colind, A->val64,
+                               A->val32, n, pl->bcsr_brp, pl->bcsr_bci, pl->bcsr_mask, pl->bcsr_val64, pl->bcsr_val32);
+        if (e == hipSuccess) e = hipGetLastError();
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) {
+            free_plan_arrays(ctx, pl);
+            delete pl;
+            return xab_hip_check(ctx, e, "BCSR fill");
         }
     } else if (v == XAB_XCB) {
         constexpr int KB = xab_plan::kXcb;
@@ -1024,6 +1210,9 @@ int xab_plan_array(const xab_plan *pl, int32_t which, int32_t *h_out, int64_t *l
         case 12: src = pl->sell.rlen; m = pl->sell.rlen ? pl->A->n : 0; break;
         case 13: src = pl->sell.clen; m = pl->sell.clen ? pl->sell.nch : 0; break;
         case 14: src = pl->sell.cols; m = pl->sell.cols ? pl->sell.total : 0; break;
+        case 15: src = pl->bcsr_brp; m = pl->bcsr_brp ? pl->bcsr_nbr + 1 : 0; break;
+        case 16: src = pl->bcsr_bci; m = pl->bcsr_bci ? pl->bcsr_nb : 0; break;
+        case 17: src = pl->bcsr_mask; m = pl->bcsr_mask ? pl->bcsr_nb : 0; break;
         default: return XAB_E_SHAPE;
     }
     *len = m;

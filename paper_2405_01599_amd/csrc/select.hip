@@ -23,7 +23,7 @@ __global__ void k_fill_f32(float *p, int64_t n, float v) {
     if (i < n) p[i] = v;
 }
 
-bool class_applies(int k, bool sym) { return sym ? (k >= 9 && k <= 11) : (k < 9 || k == 12 || k == 13); }
+bool class_applies(int k, bool sym) { return sym ? (k >= 9 && k <= 11) : (k < 9 || k >= 12); }
 
 constexpr int kStableGeneral = 3, kStableSym = 11, kStableSymFallback = 9;
 

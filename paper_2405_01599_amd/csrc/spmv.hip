@@ -22,6 +22,7 @@ int run(xab_ctx *ctx, const xab_plan *pl, const VT *val, const void *x, void *y)
         case XAB_SYM_ATOMIC: return xab::launch_sym_atomic<VT, XT, YT, AT>(ctx, pl, val, xx, yy);
         case XAB_XCB: return xab::launch_xcb<VT, XT, YT, AT>(ctx, pl, val, xx, yy);
         case XAB_SELL: return xab::launch_sell<VT, XT, YT, AT>(ctx, pl, val, xx, yy);
+        case XAB_BCSR: return xab::launch_bcsr<VT, XT, YT, AT>(ctx, pl, val, xx, yy);
     }
     return xab_fail(ctx, XAB_E_UNSUPPORTED, "variant %d", (int)pl->variant);
 }

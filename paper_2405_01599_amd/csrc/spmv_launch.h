@@ -19,6 +19,8 @@ template <class VT, class XT, class YT, class AT>
 int launch_xcb(xab_ctx *ctx, const xab_plan *pl, const VT *val, const XT *x, YT *y);
 template <class VT, class XT, class YT, class AT>
 int launch_sell(xab_ctx *ctx, const xab_plan *pl, const VT *val, const XT *x, YT *y);
+template <class VT, class XT, class YT, class AT>
+int launch_bcsr(xab_ctx *ctx, const xab_plan *pl, const VT *val, const XT *x, YT *y);
 }  // namespace xab
 
 #define XAB_INSTANTIATE_LAUNCHER(name)                                                               \

@@ -64,8 +64,9 @@ def test_class_table():
     assert seen[9][0] == xab.SYM_ATOMIC and seen[10][0] == seen[11][0] == xab.SYM_S3
     assert seen[12][0] == xab.XCB and seen[12][3] == 4
     assert seen[13][0] == xab.SELL and xab.class_params(13)[1].tile_rows == 1024
+    assert seen[14][0] == xab.BCSR
     with pytest.raises(xab.XabError):
-        xab.class_params(14)
+        xab.class_params(15)
 
 
 def test_status_strings_and_null_checks():
@@ -83,7 +84,7 @@ def test_status_strings_and_null_checks():
     assert L.xab_bicgstab(None, None, None, None, None, None, None) == -1
     assert L.xab_features(None, None, None, None) == -1
     assert L.xab_class_params(0, None, None) == -1
-    assert xab.MLP_NPARAMS == 64 * 12 + 64 + 64 * 64 + 64 + 14 * 64 + 14
+    assert xab.MLP_NPARAMS == 64 * 12 + 64 + 64 * 64 + 64 + 15 * 64 + 15
 
 
 def test_product_path_has_no_oracle_dependency():

@@ -52,9 +52,13 @@ def test_select_time_is_argmin(ctx, name):
     if A.sym_lower:
         assert set(valid) <= set(xab.SYM_CLASSES)
     else:
-        # every general class applies, except SELL outside its limits (rows
-        # of at most 4096 entries): the trans4-shaped matrix has a longer row
-        want = [k for k in xab.GENERAL_CLASSES if not (k == 13 and int(np.max(np.diff(A.rowptr))) > 4096)]
+        # every general class applies, except SELL and BCSR outside their
+        # limits: SELL needs rows of at most 4096 entries (the trans4-shaped
+        # matrix has a longer one), BCSR blocks holding at most twice the
+        # entries (from the oracle's block layout)
+        nb = len(oracle.plan_bcsr(A, 4)["bci"])
+        want = [k for k in xab.GENERAL_CLASSES
+                if not (k == 13 and int(np.max(np.diff(A.rowptr))) > 4096) and not (k == 14 and 16 * nb > 2 * A.nnz)]
         assert valid == want
     t = {k: info.time_ms[k] for k in valid}
     best = min(valid, key=lambda k: (t[k], k))

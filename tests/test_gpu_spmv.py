@@ -58,8 +58,33 @@ def general_suite():
         "powerlaw": gen.powerlaw(60_000, seed=2),
         "trans4": gen.trans4_like(),
         "blockdiag": gen.blockdiag(20_000, 3),
+        "blockdiag_ragged": gen.blockdiag(10_001, 4),   # n not a multiple of 4
+        "kron4": _kron_blocks(gen.laplacian2d(24), 4, seed=6),
     }
     return out
+
+
+def _kron_blocks(A, b, seed):
+    """A with every entry replaced by a dense b x b block of N(0, 1) values
+    (b unknowns per grid node, as in FEM systems): aligned b x b blocks."""
+    rng = np.random.default_rng(seed)
+    rows, cols, vals = [], [], []
+    for i in range(A.n):
+        for k in range(A.rowptr[i], A.rowptr[i + 1]):
+            j = int(A.colind[k])
+            blk = rng.standard_normal((b, b))
+            for p in range(b):
+                for q in range(b):
+                    rows.append(i * b + p)
+                    cols.append(j * b + q)
+                    vals.append(blk[p, q])
+    rows, cols, vals = np.array(rows), np.array(cols), np.array(vals)
+    order = np.lexsort((cols, rows))
+    rows, cols, vals = rows[order], cols[order], vals[order]
+    n = A.n * b
+    rp = np.zeros(n + 1, dtype=np.int32)
+    rp[1:] = np.cumsum(np.bincount(rows, minlength=n))
+    return gen.CSR(n, n, rp, cols.astype(np.int32), vals, name=f"kron{b}")
 
 
 GENERAL = general_suite()
@@ -73,10 +98,20 @@ def _sell_supported(A, sigma=1024):
     return longest <= 4096 and int(p["cptr"][-1]) <= 2 * A.nnz + 64 * longest
 
 
+def _bcsr_supported(A):
+    """The BCSR plan's own limits, from the oracle's layout of A: block rows
+    of at most 4096 entries, blocks holding at most twice the entries."""
+    p = oracle.plan_bcsr(A, 4)
+    rows = np.diff(A.rowptr[np.minimum(np.arange(0, A.n + 4, 4), A.n)]) if A.n else np.zeros(1)
+    return int(np.max(rows, initial=0)) <= 4096 and 16 * len(p["bci"]) <= 2 * A.nnz
+
+
 def _plan_class(ctx, M, A, k):
-    """Plan of class k; for SELL on a matrix outside its limits, check the
-    library refuses it (XAB_E_UNSUPPORTED) and return None."""
-    if xab.class_params(k)[0] == xab.SELL and not _sell_supported(A, xab.class_params(k)[1].tile_rows):
+    """Plan of class k; for SELL or BCSR on a matrix outside its limits,
+    check the library refuses it (XAB_E_UNSUPPORTED) and return None."""
+    v = xab.class_params(k)[0]
+    if (v == xab.SELL and not _sell_supported(A, xab.class_params(k)[1].tile_rows)) or \
+            (v == xab.BCSR and not _bcsr_supported(A)):
         with pytest.raises(xab.XabError) as e:
             ctx.plan_class(M, k)
         assert e.value.status == -6
@@ -137,6 +172,46 @@ def test_sell_plan_bitexact(ctx, sigma):
         assert np.array_equal(P.array(12), ref["rlen"]), (name, sigma)
         assert np.array_equal(P.array(13), ref["clen"]), (name, sigma)
         assert np.array_equal(P.array(14), ref["cols"]), (name, sigma)
+
+
+def test_bcsr_plan_bitexact(ctx):
+    """Block row pointers, block columns and position masks equal the
+    oracle's; the blocked values are checked through the exact SpMVs.  The
+    suite has matrices on both sides of the limits."""
+    seen = [0, 0]
+    for name, A in GENERAL.items():
+        M = ctx.matrix_from_csr(A)
+        if not _bcsr_supported(A):
+            with pytest.raises(xab.XabError) as e:
+                ctx.plan(M, xab.BCSR)
+            assert e.value.status == -6
+            seen[1] += 1
+            continue
+        P = ctx.plan(M, xab.BCSR)
+        ref = oracle.plan_bcsr(A, 4)
+        assert np.array_equal(P.array(15), ref["brp"]), name
+        assert np.array_equal(P.array(16), ref["bci"]), name
+        assert np.array_equal(P.array(17).astype(np.uint32), ref["bmask"]), name
+        seen[0] += 1
+    assert seen[0] >= 3 and seen[1] >= 1
+
+
+def test_bcsr_duplicates_and_nonfinite_x(ctx):
+    """Duplicate entries are summed in the block; a non-finite x entry at a
+    column that shares a block with every row but is stored nowhere does not
+    reach them."""
+    cols = [0, 1, 2, 2, 3, 4, 5, 7]                 # column 2 twice, column 6 never
+    rp = np.arange(0, 4 * len(cols) + 1, len(cols), dtype=np.int32)
+    ci = np.array(cols * 4, dtype=np.int32)
+    v = np.arange(1.0, 4 * len(cols) + 1)
+    A = gen.CSR(4, 8, rp, ci, v)
+    M = ctx.matrix_from_csr(A)
+    P = ctx.plan(M, xab.BCSR)
+    x = np.arange(1.0, 9.0)
+    assert np.array_equal(ctx.spmv(P, dev(x)).cpu().numpy(), oracle.spmv(A, x)[0])
+    x[6] = np.inf
+    y = ctx.spmv(P, dev(x)).cpu().numpy()
+    assert np.all(np.isfinite(y)) and np.array_equal(y, oracle.spmv(A, x)[0])
 
 
 def test_nnz_plan_bitexact(ctx):
@@ -206,7 +281,7 @@ FP32_COMBOS = [  # (y dtype, acc) with x and values FP32
 
 
 @pytest.mark.parametrize("name", ["powerlaw", "trans4", "lap2d", "one_long_row", "blockdiag"])
-@pytest.mark.parametrize("k", [0, 1, 3, 6, 8, 12, 13])
+@pytest.mark.parametrize("k", [0, 1, 3, 6, 8, 12, 13, 14])
 @pytest.mark.parametrize("combo", range(3))
 def test_general_fp32(ctx, name, k, combo):
     ydt, acc = FP32_COMBOS[combo]
