@@ -29,6 +29,14 @@ struct AddStep {
     }
 };
 
+// FP32 vectors are swept two consecutive rows per thread with 8-byte loads
+// (every vector of the basis and the work vectors start on a 64-element
+// boundary, so row pairs are 8-byte aligned); FP64 vectors one row per thread.
+template <class T>
+constexpr int rows_per_thread() { return sizeof(T) == 4 ? 2 : 1; }
+template <class T>
+using Pair = T __attribute__((ext_vector_type(2)));
+
 // part[b * ldp + i] = sum over this workgroup's rows of V_i[r] * w[r]
 // (i < nv), part[b * ldp + nv] = sum of w[r]^2.  Rows are dealt in
 // contiguous chunks of 256 to the workgroups.  The nv + 1 sums are reduced
@@ -40,15 +48,33 @@ __device__ __forceinline__ void mdot_body(const T *__restrict__ V, int64_t ldv, 
     double acc[NV + 1];
 #pragma unroll
     for (int i = 0; i <= NV; ++i) acc[i] = 0.0;
-    for (int64_t r = (int64_t)blockIdx.x * kNT + threadIdx.x; r < n; r += (int64_t)gridDim.x * kNT) {
-        // every load of the row first (selects, no branches), then the products
-        double vr[NV];
+    constexpr int R = rows_per_thread<T>();
+    for (int64_t r = ((int64_t)blockIdx.x * kNT + threadIdx.x) * R; r < n; r += (int64_t)gridDim.x * kNT * R) {
+        if (R == 2 && r + 1 < n) {
+            // two rows: every load first (selects, no branches), then the products
+            Pair<T> vp[NV];
 #pragma unroll
-        for (int i = 0; i < NV; ++i) vr[i] = i < nv ? (double)V[i * ldv + r] : 0.0;
-        const double wr = (double)w[r];
-        acc[NV] += wr * wr;
+            for (int i = 0; i < NV; ++i)
+                vp[i] = i < nv ? *reinterpret_cast<const Pair<T> *>(V + i * ldv + r) : Pair<T>(T(0));
+            const Pair<T> wp = *reinterpret_cast<const Pair<T> *>(w + r);
+            const double w0 = (double)wp[0], w1 = (double)wp[1];
+            acc[NV] += w0 * w0;
+            acc[NV] += w1 * w1;
 #pragma unroll
-        for (int i = 0; i < NV; ++i) acc[i] += vr[i] * wr;
+            for (int i = 0; i < NV; ++i) {
+                acc[i] += (double)vp[i][0] * w0;
+                acc[i] += (double)vp[i][1] * w1;
+            }
+        } else {
+            // one row: every load of the row first, then the products
+            double vr[NV];
+#pragma unroll
+            for (int i = 0; i < NV; ++i) vr[i] = i < nv ? (double)V[i * ldv + r] : 0.0;
+            const double wr = (double)w[r];
+            acc[NV] += wr * wr;
+#pragma unroll
+            for (int i = 0; i < NV; ++i) acc[i] += vr[i] * wr;
+        }
     }
     const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
 #pragma unroll
@@ -85,16 +111,37 @@ __global__ __launch_bounds__(kNT) void k_update_norm(const T *__restrict__ V, in
 #pragma unroll
     for (int i = 0; i < NV; ++i) hh[i] = i < nv ? h[i] : 0.0;
     double acc = 0.0;
-    for (int64_t r = (int64_t)blockIdx.x * kNT + threadIdx.x; r < n; r += (int64_t)gridDim.x * kNT) {
-        double vr[NV];
+    constexpr int R = rows_per_thread<T>();
+    for (int64_t r = ((int64_t)blockIdx.x * kNT + threadIdx.x) * R; r < n; r += (int64_t)gridDim.x * kNT * R) {
+        if (R == 2 && r + 1 < n) {
+            Pair<T> vp[NV];
 #pragma unroll
-        for (int i = 0; i < NV; ++i) vr[i] = i < nv ? (double)V[i * ldv + r] : 0.0;
-        double a = (double)w[r];
+            for (int i = 0; i < NV; ++i)
+                vp[i] = i < nv ? *reinterpret_cast<const Pair<T> *>(V + i * ldv + r) : Pair<T>(T(0));
+            const Pair<T> wp = *reinterpret_cast<const Pair<T> *>(w + r);
+            double a0 = (double)wp[0], a1 = (double)wp[1];
 #pragma unroll
-        for (int i = 0; i < NV; ++i) a -= hh[i] * vr[i];
-        const T at = (T)a;
-        w[r] = at;
-        acc += (double)at * (double)at;
+            for (int i = 0; i < NV; ++i) {
+                a0 -= hh[i] * (double)vp[i][0];
+                a1 -= hh[i] * (double)vp[i][1];
+            }
+            Pair<T> out;
+            out[0] = (T)a0;
+            out[1] = (T)a1;
+            *reinterpret_cast<Pair<T> *>(w + r) = out;
+            acc += (double)out[0] * (double)out[0];
+            acc += (double)out[1] * (double)out[1];
+        } else {
+            double vr[NV];
+#pragma unroll
+            for (int i = 0; i < NV; ++i) vr[i] = i < nv ? (double)V[i * ldv + r] : 0.0;
+            double a = (double)w[r];
+#pragma unroll
+            for (int i = 0; i < NV; ++i) a -= hh[i] * vr[i];
+            const T at = (T)a;
+            w[r] = at;
+            acc += (double)at * (double)at;
+        }
     }
     acc = block_sum(acc, sh);
     if (threadIdx.x == 0) part[blockIdx.x] = acc;
@@ -118,7 +165,44 @@ __global__ __launch_bounds__(kNT) void k_update_mdot(const T *__restrict__ Vu, i
 #pragma unroll
     for (int i = 0; i <= NV; ++i) acc[i] = 0.0;
     const bool same = Vd == Vu && nvd == nvu;
-    for (int64_t r = (int64_t)blockIdx.x * kNT + threadIdx.x; r < n; r += (int64_t)gridDim.x * kNT) {
+    constexpr int R = rows_per_thread<T>();
+    for (int64_t r = ((int64_t)blockIdx.x * kNT + threadIdx.x) * R; r < n; r += (int64_t)gridDim.x * kNT * R) {
+        if (R == 2 && r + 1 < n) {
+            Pair<T> vp[NV];
+#pragma unroll
+            for (int i = 0; i < NV; ++i)
+                vp[i] = i < nvu ? *reinterpret_cast<const Pair<T> *>(Vu + i * ldv + r) : Pair<T>(T(0));
+            const Pair<T> wp = *reinterpret_cast<const Pair<T> *>(w + r);
+            double a0 = (double)wp[0], a1 = (double)wp[1];
+#pragma unroll
+            for (int i = 0; i < NV; ++i) {
+                a0 -= hh[i] * (double)vp[i][0];
+                a1 -= hh[i] * (double)vp[i][1];
+            }
+            Pair<T> out;
+            out[0] = (T)a0;
+            out[1] = (T)a1;
+            *reinterpret_cast<Pair<T> *>(w + r) = out;
+            const double d0 = (double)out[0], d1 = (double)out[1];
+            acc[NV] += d0 * d0;
+            acc[NV] += d1 * d1;
+            if (same) {
+#pragma unroll
+                for (int i = 0; i < NV; ++i) {
+                    acc[i] += (double)vp[i][0] * d0;
+                    acc[i] += (double)vp[i][1] * d1;
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < NV; ++i)
+                    if (i < nvd) {
+                        const Pair<T> q = *reinterpret_cast<const Pair<T> *>(Vd + i * ldv + r);
+                        acc[i] += (double)q[0] * d0;
+                        acc[i] += (double)q[1] * d1;
+                    }
+            }
+            continue;
+        }
         double vr[NV];
         double a = (double)w[r];
 #pragma unroll
