@@ -351,3 +351,19 @@ def test_arnoldi_convdiff_values_in_closed_form(ctx):
     for v in ev:
         assert abs(v.imag) <= 1e-9 * info["anrm"] and np.min(np.abs(lam - v.real)) <= 1e-9 * info["anrm"]
     assert info["max_resid"] <= 1.5e-8
+
+
+def test_arnoldi_on_lower_stored_plan(ctx):
+    """Arnoldi through a symmetric lower-storage plan (S3): the 1D Laplacian's
+    closed-form top eigenvalues, real, as with Lanczos."""
+    n = 400
+    L = lap1d(n)
+    rows = np.repeat(np.arange(n), np.diff(L.rowptr))
+    keep = L.colind <= rows
+    rp = np.zeros(n + 1, dtype=np.int32)
+    rp[1:] = np.cumsum(np.bincount(rows[keep], minlength=n))
+    Lo = gen.CSR(n, n, rp, L.colind[keep].copy(), L.val[keep].copy(), sym_lower=True)
+    ev, X, info, st = arun(ctx, Lo, 10, 6, 30, gen.uniform_vec(n, 1), tol=1e-9, which=xab.EIG_LARGEST)
+    want = np.sort(2.0 - 2.0 * np.cos(np.arange(1, n + 1) * np.pi / (n + 1)))[::-1][:6]
+    assert st == 0 and np.all(ev.imag == 0.0)
+    assert np.max(np.abs(ev.real - want)) <= 1e-10 * info["anrm"]

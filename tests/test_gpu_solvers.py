@@ -183,6 +183,23 @@ def _long_row_batch():
     return gen.Batch(3, row_off, nnz_off, rp, ci, v, np.zeros(3), np.zeros(3))
 
 
+@pytest.mark.parametrize("tiles", [False, True])
+def test_batch_single_system_matches_single_solve(ctx, tiles):
+    """A batch of one system: SpMV exact, BiCGStab to 1e-10 like the oracle."""
+    B = gen.batch(1, seed=4, nmin=2000, nmax=2001)
+    x = gen.int_vec(B.n, 4)
+    Bi = gen.Batch(B.nsys, B.row_off, B.nnz_off, B.rowptr, B.colind,
+                   np.random.default_rng(2).integers(-8, 9, B.nnz).astype(np.float64), B.kinds, B.params)
+    bt = ctx.batch(Bi, tiles=tiles)
+    _batch_check_exact(Bi, x, bt.spmv(dev(x)).cpu().numpy())
+    bt = ctx.batch(B, tiles=tiles)
+    b = np.ones(B.n)
+    xs, per, agg, st = ctx.bicgstab(bt, dev(b), tol=1e-10)
+    assert st == 0 and per[0]["true_relres"] <= 1e-10 * 1.01
+    ref = oracle.bicgstab(B.system(0), b, tol=1e-10, precond=1)
+    assert np.linalg.norm(xs.cpu().numpy() - ref["x"]) / np.linalg.norm(ref["x"]) <= 1e-8
+
+
 def test_batch_long_row_uses_tiles(ctx):
     B = _long_row_batch()
     x = gen.int_vec(B.n, 7)
