@@ -1,10 +1,14 @@
 // Batched independent systems: the block-diagonal concatenation of many
 // CSR matrices, one persistent SpMV launch over all of them, and BiCGStab
 // (van der Vorst's form, the paper's second linear solver) advancing every
-// system at once.  One iteration is five kernels; it is captured once in a
-// HIP graph and replayed.  Per-system scalars live on the device; a system
-// that converges (or breaks down) is masked from then on, and tiles whose
-// systems are all inactive skip their SpMV work.
+// system at once.  One iteration is eleven kernels: two SpMVs, five row
+// kernels over segments of kSegRows rows (a large system spans many
+// workgroups) and four one-wave-per-system kernels that sum the segments'
+// partial inner products in a fixed order and take the scalar decisions.  It
+// is captured once in a HIP graph and replayed.  Per-system scalars live on
+// the device; a system that converges (or breaks down) is masked from then
+// on, and SpMV chunks or tiles whose systems are all inactive skip their
+// work.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -18,7 +22,10 @@ namespace {
 using xab::Seg;
 constexpr int kNT = 256;
 constexpr int kBatchJ = 4;  // entries per lane of the batched SpMV tiles
-constexpr int kBiNT = 1024; // threads of the per-system solver kernels (one workgroup per system)
+constexpr int kBiNT = 1024; // threads of the set-up / final kernels (one workgroup per system)
+constexpr int kSegRows = 1024; // rows of one system per workgroup of the BiCGStab row kernels
+constexpr int kVT = 256;      // threads of the BiCGStab row kernels
+constexpr int kFT = 256;      // threads of the per-system kernels (one wave per system)
 constexpr int kSellSigma = 1024; // sorting window of the sliced ELLPACK copy
 
 
@@ -110,16 +117,18 @@ __device__ __forceinline__ double bsum(double v, double *sh) {
 
 // Per-system solver state (device).
 struct SysState {
-    double rho_prev, alpha, omega, bnorm, res;
+    double rho, alpha, omega, beta, bnorm, res;
     int iters, status;  // status: 0 converged, 1 running/not converged, 2 breakdown
 };
 
-// ||b||, r = b - A x0 (A x0 given in t), rhat = r, p = v = 0, scalars reset.
+// ||b||, r = b - A x0 (A x0 given in ax), rhat = r, p = v = 0, rho = <rhat, r>,
+// scalars reset (beta = 0 makes the first direction p = r)
 template <class T>
 __global__ __launch_bounds__(kBiNT) void k_bi_init(const int64_t *__restrict__ row_off, const T *__restrict__ bvec,
                                                  const T *__restrict__ ax, T *__restrict__ r, T *__restrict__ rh,
                                                  T *__restrict__ p, T *__restrict__ v, SysState *__restrict__ st,
-                                                 int *__restrict__ active, double tol, int *__restrict__ n_active) {
+                                                 int *__restrict__ active, int *__restrict__ early, double tol,
+                                                 int *__restrict__ n_active) {
     __shared__ double sh[kBiNT / xab::kWave];
     const int k = blockIdx.x;
     const int64_t r0 = row_off[k], r1 = row_off[k + 1];
@@ -138,175 +147,258 @@ __global__ __launch_bounds__(kBiNT) void k_bi_init(const int64_t *__restrict__ r
     rr = bsum(rr, sh);
     if (threadIdx.x == 0) {
         SysState s;
-        s.rho_prev = 1.0;
+        s.rho = rr;
         s.alpha = 1.0;
         s.omega = 1.0;
+        s.beta = 0.0;
         s.bnorm = bb > 0.0 ? sqrt(bb) : 1.0;
         s.res = sqrt(rr) / s.bnorm;
         s.iters = 0;
-        s.status = s.res <= tol ? 0 : 1;
+        s.status = s.res <= tol ? 0 : (rr == 0.0 ? 2 : 1);
         st[k] = s;
         active[k] = s.status == 1;
+        early[k] = 0;
         if (s.status == 1) atomicAdd(n_active, 1);
     }
 }
 
-// rho = <rhat, r>, beta, p = r + beta (p - omega v), phat = M^-1 p
-template <class T>
-__global__ __launch_bounds__(kBiNT) void k_bi_p(const int64_t *__restrict__ row_off, const T *__restrict__ r,
-                                              const T *__restrict__ rh, T *__restrict__ p, const T *__restrict__ v,
-                                              T *__restrict__ ph, const T *__restrict__ d, SysState *__restrict__ st,
-                                              int *__restrict__ active, double *__restrict__ rho_out,
-                                              int *__restrict__ n_active) {
-    __shared__ double sh[kBiNT / xab::kWave];
-    __shared__ double beta_s;
-    const int k = blockIdx.x;
-    if (!active[k]) return;
-    const int64_t r0 = row_off[k], r1 = row_off[k + 1];
-    double a = 0.0;
-    for (int64_t i = r0 + threadIdx.x; i < r1; i += kBiNT) a += (double)rh[i] * (double)r[i];
-    const double rho = bsum(a, sh);
-    if (threadIdx.x == 0) {
-        SysState s = st[k];
-        if (rho == 0.0) {
-            s.status = 2;
-            st[k] = s;
-            active[k] = 0;
-            atomicSub(n_active, 1);
-            beta_s = NAN;
-        } else {
-            beta_s = (rho / s.rho_prev) * (s.alpha / s.omega);
-            rho_out[k] = rho;
-        }
-    }
+// ---- row kernels: one workgroup per segment of kSegRows rows of one system,
+// so that a large system is spread over many CUs.  Each reads the scalars of
+// its system (written by the per-system kernels, never by a row kernel) and
+// leaves its inner products as one partial per segment.
+struct SegRange {
+    int k;
+    int64_t r0, r1;
+};
+
+__device__ __forceinline__ SegRange seg_range(const int32_t *__restrict__ seg_sys, const int32_t *__restrict__ seg_off,
+                                              const int64_t *__restrict__ row_off) {
+    const int j = blockIdx.x;
+    const int k = seg_sys[j];
+    const int64_t r0 = row_off[k] + (int64_t)(j - seg_off[k]) * kSegRows;
+    return {k, r0, min(r0 + (int64_t)kSegRows, row_off[k + 1])};
+}
+
+// workgroup sum in a fixed order: xor tree in each wave, then the waves in order
+__device__ __forceinline__ double vsum(double v, double *sh) {
+    v = xab::wave_sum(v);
+    if (threadIdx.x % xab::kWave == 0) sh[threadIdx.x / xab::kWave] = v;
     __syncthreads();
-    const double beta = beta_s;
-    if (beta != beta) return;
-    const double om = st[k].omega;
-    for (int64_t i = r0 + threadIdx.x; i < r1; i += kBiNT) {
+    double t = 0.0;
+#pragma unroll
+    for (int i = 0; i < kVT / xab::kWave; ++i) t += sh[i];
+    __syncthreads();
+    return t;
+}
+
+#define XAB_SEG_ROWS(R, i)                                              \
+    _Pragma("unroll") for (int u_ = 0; u_ < kSegRows / kVT; ++u_)       \
+        if (const int64_t i = (R).r0 + threadIdx.x + (int64_t)u_ * kVT; i < (R).r1)
+
+// p = r + beta (p - omega v), phat = M^-1 p
+template <class T>
+__global__ __launch_bounds__(kVT) void k_bv_p(const int32_t *__restrict__ seg_sys, const int32_t *__restrict__ seg_off,
+                                            const int64_t *__restrict__ row_off, const T *__restrict__ r,
+                                            T *__restrict__ p, const T *__restrict__ v, T *__restrict__ ph,
+                                            const T *__restrict__ d, const SysState *__restrict__ st,
+                                            const int *__restrict__ active) {
+    const SegRange R = seg_range(seg_sys, seg_off, row_off);
+    if (!active[R.k]) return;
+    const double beta = st[R.k].beta, om = st[R.k].omega;
+    XAB_SEG_ROWS(R, i) {
         T pi = (T)((double)r[i] + beta * ((double)p[i] - om * (double)v[i]));
         p[i] = pi;
         ph[i] = d ? (T)((double)pi / (double)d[i]) : pi;
     }
 }
 
-// alpha = rho / <rhat, v>, s = r - alpha v, ||s||; early exit when ||s||
-// meets tol (x += alpha phat); else shat = M^-1 s
-template <class T>
-__global__ __launch_bounds__(kBiNT) void k_bi_s(const int64_t *__restrict__ row_off, const T *__restrict__ r,
-                                              const T *__restrict__ rh, const T *__restrict__ v, T *__restrict__ s,
-                                              T *__restrict__ sh_vec, const T *__restrict__ ph, T *__restrict__ x,
-                                              const T *__restrict__ d, SysState *__restrict__ st,
-                                              int *__restrict__ active, const double *__restrict__ rho_in, double tol,
-                                              int *__restrict__ n_active) {
-    __shared__ double sh[kBiNT / xab::kWave];
-    __shared__ double alpha_s;
-    __shared__ int done_s;
-    const int k = blockIdx.x;
-    if (!active[k]) return;
-    const int64_t r0 = row_off[k], r1 = row_off[k + 1];
-    double a = 0.0;
-    for (int64_t i = r0 + threadIdx.x; i < r1; i += kBiNT) a += (double)rh[i] * (double)v[i];
-    const double rv = bsum(a, sh);
+// partial <a, b> (and <a, a> when kTwo) of each segment
+template <class T, bool kTwo>
+__global__ __launch_bounds__(kVT) void k_bv_dot(const int32_t *__restrict__ seg_sys,
+                                              const int32_t *__restrict__ seg_off,
+                                              const int64_t *__restrict__ row_off, const T *__restrict__ a,
+                                              const T *__restrict__ b, const int *__restrict__ active,
+                                              double *__restrict__ part) {
+    __shared__ double sh[kVT / xab::kWave];
+    const SegRange R = seg_range(seg_sys, seg_off, row_off);
+    if (!active[R.k]) return;
+    double ab = 0.0, aa = 0.0;
+    XAB_SEG_ROWS(R, i) {
+        const double ai = (double)a[i];
+        ab += ai * (double)b[i];
+        if (kTwo) aa += ai * ai;
+    }
+    ab = vsum(ab, sh);
+    if (kTwo) aa = vsum(aa, sh);
     if (threadIdx.x == 0) {
-        if (rv == 0.0) {
-            SysState q = st[k];
-            q.status = 2;
-            st[k] = q;
-            active[k] = 0;
-            atomicSub(n_active, 1);
-            alpha_s = NAN;
-        } else {
-            alpha_s = rho_in[k] / rv;
-        }
+        part[2 * blockIdx.x] = ab;
+        if (kTwo) part[2 * blockIdx.x + 1] = aa;
     }
-    __syncthreads();
-    const double alpha = alpha_s;
-    if (alpha != alpha) return;
-    double ss = 0.0;
-    for (int64_t i = r0 + threadIdx.x; i < r1; i += kBiNT) {
-        T si = (T)((double)r[i] - alpha * (double)v[i]);
-        s[i] = si;
-        ss += (double)si * (double)si;
-    }
-    ss = bsum(ss, sh);
-    if (threadIdx.x == 0) {
-        SysState q = st[k];
-        q.alpha = alpha;
-        double res = sqrt(ss) / q.bnorm;
-        done_s = res <= tol;
-        if (done_s) {
-            q.res = res;
-            q.iters += 1;
-            q.status = 0;
-            active[k] = 0;
-            atomicSub(n_active, 1);
-        }
-        st[k] = q;
-    }
-    __syncthreads();
-    if (done_s) {
-        for (int64_t i = r0 + threadIdx.x; i < r1; i += kBiNT) x[i] = (T)((double)x[i] + alpha * (double)ph[i]);
-        return;
-    }
-    for (int64_t i = r0 + threadIdx.x; i < r1; i += kBiNT) sh_vec[i] = d ? (T)((double)s[i] / (double)d[i]) : s[i];
 }
 
-// omega = <t, s> / <t, t>, x += alpha phat + omega shat, r = s - omega t,
-// ||r|| -> convergence
+// s = r - alpha v, shat = M^-1 s, partial <s, s>
 template <class T>
-__global__ __launch_bounds__(kBiNT) void k_bi_x(const int64_t *__restrict__ row_off, const T *__restrict__ s,
-                                              const T *__restrict__ t, const T *__restrict__ ph,
-                                              const T *__restrict__ shv, T *__restrict__ x, T *__restrict__ r,
-                                              SysState *__restrict__ st, int *__restrict__ active,
-                                              const double *__restrict__ rho_in, double tol, int64_t maxiter,
-                                              int *__restrict__ n_active) {
-    __shared__ double sh[kBiNT / xab::kWave];
-    __shared__ double om_s;
-    const int k = blockIdx.x;
-    if (!active[k]) return;
-    const int64_t r0 = row_off[k], r1 = row_off[k + 1];
-    double ts = 0.0, tt = 0.0;
-    for (int64_t i = r0 + threadIdx.x; i < r1; i += kBiNT) {
-        double ti = (double)t[i];
-        ts += ti * (double)s[i];
-        tt += ti * ti;
+__global__ __launch_bounds__(kVT) void k_bv_s(const int32_t *__restrict__ seg_sys, const int32_t *__restrict__ seg_off,
+                                            const int64_t *__restrict__ row_off, const T *__restrict__ r,
+                                            const T *__restrict__ v, T *__restrict__ s, T *__restrict__ shv,
+                                            const T *__restrict__ d, const SysState *__restrict__ st,
+                                            const int *__restrict__ active, double *__restrict__ part) {
+    __shared__ double sh[kVT / xab::kWave];
+    const SegRange R = seg_range(seg_sys, seg_off, row_off);
+    if (!active[R.k]) return;
+    const double alpha = st[R.k].alpha;
+    double ss = 0.0;
+    XAB_SEG_ROWS(R, i) {
+        T si = (T)((double)r[i] - alpha * (double)v[i]);
+        s[i] = si;
+        shv[i] = d ? (T)((double)si / (double)d[i]) : si;
+        ss += (double)si * (double)si;
     }
-    ts = bsum(ts, sh);
-    tt = bsum(tt, sh);
-    if (threadIdx.x == 0) om_s = tt != 0.0 ? ts / tt : 0.0;
-    __syncthreads();
-    const double om = om_s;
-    const double al = st[k].alpha;
-    double rr = 0.0;
-    for (int64_t i = r0 + threadIdx.x; i < r1; i += kBiNT) {
+    ss = vsum(ss, sh);
+    if (threadIdx.x == 0) part[2 * blockIdx.x] = ss;
+}
+
+// x += alpha phat + omega shat, r = s - omega t, partials <r, r> and
+// <rhat, r>; a system whose s met the tolerance this iteration takes
+// x += alpha phat alone
+template <class T>
+__global__ __launch_bounds__(kVT) void k_bv_x(const int32_t *__restrict__ seg_sys, const int32_t *__restrict__ seg_off,
+                                            const int64_t *__restrict__ row_off, const T *__restrict__ s,
+                                            const T *__restrict__ t, const T *__restrict__ ph,
+                                            const T *__restrict__ shv, const T *__restrict__ rh, T *__restrict__ x,
+                                            T *__restrict__ r, const SysState *__restrict__ st,
+                                            const int *__restrict__ active, const int *__restrict__ early,
+                                            double *__restrict__ part) {
+    __shared__ double sh[kVT / xab::kWave];
+    const SegRange R = seg_range(seg_sys, seg_off, row_off);
+    const double al = st[R.k].alpha;
+    if (early[R.k]) {
+        XAB_SEG_ROWS(R, i) x[i] = (T)((double)x[i] + al * (double)ph[i]);
+        return;
+    }
+    if (!active[R.k]) return;
+    const double om = st[R.k].omega;
+    double rr = 0.0, rho = 0.0;
+    XAB_SEG_ROWS(R, i) {
         x[i] = (T)((double)x[i] + al * (double)ph[i] + om * (double)shv[i]);
         T ri = (T)((double)s[i] - om * (double)t[i]);
         r[i] = ri;
         rr += (double)ri * (double)ri;
+        rho += (double)rh[i] * (double)ri;
     }
-    rr = bsum(rr, sh);
+    rr = vsum(rr, sh);
+    rho = vsum(rho, sh);
     if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = rr;
+        part[2 * blockIdx.x + 1] = rho;
+    }
+}
+
+#undef XAB_SEG_ROWS
+
+// ---- per-system kernels: one wave per system sums the partials of its
+// segments in segment order (a fixed xor tree over the lanes), takes the
+// scalar decisions and updates the state and the masks.
+__device__ __forceinline__ double seg_total(const double *__restrict__ part, int c, int j0, int j1) {
+    double a = 0.0;
+    for (int j = j0 + (int)(threadIdx.x % xab::kWave); j < j1; j += xab::kWave) a += part[2 * j + c];
+    return xab::wave_sum(a);
+}
+
+__device__ __forceinline__ int wave_system() {
+    return (int)(blockIdx.x * (kFT / xab::kWave) + threadIdx.x / xab::kWave);
+}
+
+// alpha = rho / <rhat, v>; breakdown when <rhat, v> = 0
+__global__ __launch_bounds__(kFT) void k_bf_alpha(const int32_t *__restrict__ seg_off, int ns,
+                                                const double *__restrict__ part, SysState *__restrict__ st,
+                                                int *__restrict__ active, int *__restrict__ n_active) {
+    const int k = wave_system();
+    if (k >= ns || !active[k]) return;
+    const double rv = seg_total(part, 0, seg_off[k], seg_off[k + 1]);
+    if (threadIdx.x % xab::kWave) return;
+    if (rv == 0.0) {
+        st[k].status = 2;
+        active[k] = 0;
+        atomicSub(n_active, 1);
+    } else {
+        st[k].alpha = st[k].rho / rv;
+    }
+}
+
+// ||s|| / ||b|| <= tol: the system stops after x += alpha phat
+__global__ __launch_bounds__(kFT) void k_bf_s(const int32_t *__restrict__ seg_off, int ns,
+                                            const double *__restrict__ part, SysState *__restrict__ st,
+                                            int *__restrict__ active, int *__restrict__ early, double tol,
+                                            int *__restrict__ n_active) {
+    const int k = wave_system();
+    if (k >= ns || !active[k]) return;
+    const double ss = seg_total(part, 0, seg_off[k], seg_off[k + 1]);
+    if (threadIdx.x % xab::kWave) return;
+    const double res = sqrt(ss) / st[k].bnorm;
+    if (res <= tol) {
         SysState q = st[k];
+        q.res = res;
         q.iters += 1;
-        q.omega = om;
-        q.rho_prev = rho_in[k];
-        q.res = sqrt(rr) / q.bnorm;
-        bool stop = false;
-        if (q.res <= tol) {
-            q.status = 0;
-            stop = true;
-        } else if (om == 0.0) {
-            q.status = 2;
-            stop = true;
-        } else if (q.iters >= maxiter) {
-            stop = true;
-        }
+        q.status = 0;
         st[k] = q;
-        if (stop) {
-            active[k] = 0;
-            atomicSub(n_active, 1);
-        }
+        active[k] = 0;
+        early[k] = 1;
+        atomicSub(n_active, 1);
+    }
+}
+
+// omega = <t, s> / <t, t> (0 when t = 0)
+__global__ __launch_bounds__(kFT) void k_bf_omega(const int32_t *__restrict__ seg_off, int ns,
+                                                const double *__restrict__ part, SysState *__restrict__ st,
+                                                const int *__restrict__ active) {
+    const int k = wave_system();
+    if (k >= ns || !active[k]) return;
+    const double ts = seg_total(part, 0, seg_off[k], seg_off[k + 1]);
+    const double tt = seg_total(part, 1, seg_off[k], seg_off[k + 1]);
+    if (threadIdx.x % xab::kWave) return;
+    st[k].omega = tt != 0.0 ? ts / tt : 0.0;
+}
+
+// end of an iteration: ||r|| / ||b|| against tol, omega = 0 (breakdown), the
+// iteration limit, then rho_next = <rhat, r> (breakdown when 0) and
+// beta = (rho_next / rho) (alpha / omega) for the next direction
+__global__ __launch_bounds__(kFT) void k_bf_x(const int32_t *__restrict__ seg_off, int ns,
+                                            const double *__restrict__ part, SysState *__restrict__ st,
+                                            int *__restrict__ active, int *__restrict__ early, double tol,
+                                            int64_t maxiter, int *__restrict__ n_active) {
+    const int k = wave_system();
+    if (k >= ns) return;
+    const bool lead = threadIdx.x % xab::kWave == 0;
+    if (early[k]) {
+        if (lead) early[k] = 0;
+        return;
+    }
+    if (!active[k]) return;
+    const double rr = seg_total(part, 0, seg_off[k], seg_off[k + 1]);
+    const double rho = seg_total(part, 1, seg_off[k], seg_off[k + 1]);
+    if (!lead) return;
+    SysState q = st[k];
+    q.iters += 1;
+    q.res = sqrt(rr) / q.bnorm;
+    bool stop = true;
+    if (q.res <= tol) {
+        q.status = 0;
+    } else if (q.omega == 0.0) {
+        q.status = 2;
+    } else if (q.iters >= maxiter) {
+        // stays "not converged"
+    } else if (rho == 0.0) {
+        q.status = 2;
+    } else {
+        stop = false;
+        q.beta = (rho / q.rho) * (q.alpha / q.omega);
+        q.rho = rho;
+    }
+    st[k] = q;
+    if (stop) {
+        active[k] = 0;
+        atomicSub(n_active, 1);
     }
 }
 
@@ -406,21 +498,23 @@ int bicgstab_t(xab_ctx *ctx, const xab_batch *B, const T *bvec, T *x, const xab_
     auto al = [](size_t b) { return (b + 255) / 256 * 256; };
     const size_t vb = al(sizeof(T) * (size_t)n);
     size_t off_st = 10 * vb;
-    size_t off_rho = off_st + al(sizeof(SysState) * ns);
-    size_t off_act = off_rho + al(sizeof(double) * ns);
-    size_t off_cnt = off_act + al(sizeof(int) * ns);
+    size_t off_act = off_st + al(sizeof(SysState) * ns);
+    size_t off_early = off_act + al(sizeof(int) * ns);
+    size_t off_cnt = off_early + al(sizeof(int) * ns);
     size_t off_res = off_cnt + 256;
-    size_t total = off_res + al(sizeof(double) * ns);
+    size_t off_part = off_res + al(sizeof(double) * ns);
+    size_t total = off_part + al(sizeof(double) * 2 * (size_t)std::max<int64_t>(B->nseg, 1));
     char *w = (char *)xab_dalloc(ctx, total);
     if (!w) return xab_fail(ctx, XAB_E_NOMEM, "BiCGStab workspace");
     T *r = (T *)w, *rh = (T *)(w + vb), *p = (T *)(w + 2 * vb), *v = (T *)(w + 3 * vb), *ph = (T *)(w + 4 * vb);
     T *s = (T *)(w + 5 * vb), *shv = (T *)(w + 6 * vb), *t = (T *)(w + 7 * vb);
     T *ax = (T *)(w + 9 * vb);
     SysState *stt = (SysState *)(w + off_st);
-    double *rho = (double *)(w + off_rho);
     int *active = (int *)(w + off_act);
+    int *early = (int *)(w + off_early);
     int *n_active = (int *)(w + off_cnt);
     double *res = (double *)(w + off_res);
+    double *part = (double *)(w + off_part);
     hipStream_t st = ctx->stream;
     hipStream_t gs = nullptr;
     hipGraph_t graph = nullptr;
@@ -452,21 +546,31 @@ int bicgstab_t(xab_ctx *ctx, const xab_batch *B, const T *bvec, T *x, const xab_
     }
     hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, st, n_active);
     if ((sres = batch_spmv_t<T>(ctx, B, x, ax, nullptr, st)) != XAB_OK) return cleanup(sres);
-    hipLaunchKernelGGL((k_bi_init<T>), dim3(ns), dim3(kBiNT), 0, st, B->d_row_off, bvec, ax, r, rh, p, v, stt, active, tol,
-                       n_active);
+    hipLaunchKernelGGL((k_bi_init<T>), dim3(ns), dim3(kBiNT), 0, st, B->d_row_off, bvec, ax, r, rh, p, v, stt, active,
+                       early, tol, n_active);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return cleanup(xab_hip_check(ctx, e, "BiCGStab init"));
     const T *dd = jac ? (const T *)B->diag : nullptr;
     // one iteration over all systems
+    const unsigned nseg = (unsigned)B->nseg;
+    const unsigned nfw = (unsigned)((ns + kFT / xab::kWave - 1) / (kFT / xab::kWave));
+    const int32_t *so = B->d_seg_off, *ss = B->d_seg_sys;
+    const int64_t *ro = B->d_row_off;
     auto enqueue_iter = [&](hipStream_t q) {
-        hipLaunchKernelGGL((k_bi_p<T>), dim3(ns), dim3(kBiNT), 0, q, B->d_row_off, r, rh, p, v, ph, dd, stt, active, rho,
-                           n_active);
+        if (nseg) hipLaunchKernelGGL((k_bv_p<T>), dim3(nseg), dim3(kVT), 0, q, ss, so, ro, r, p, v, ph, dd, stt, active);
         launch_batch_spmv<T>(B, ph, v, active, q);
-        hipLaunchKernelGGL((k_bi_s<T>), dim3(ns), dim3(kBiNT), 0, q, B->d_row_off, r, rh, v, s, shv, ph, x, dd, stt, active,
-                           rho, tol, n_active);
+        if (nseg) hipLaunchKernelGGL((k_bv_dot<T, false>), dim3(nseg), dim3(kVT), 0, q, ss, so, ro, v, rh, active, part);
+        hipLaunchKernelGGL(k_bf_alpha, dim3(nfw), dim3(kFT), 0, q, so, ns, part, stt, active, n_active);
+        if (nseg)
+            hipLaunchKernelGGL((k_bv_s<T>), dim3(nseg), dim3(kVT), 0, q, ss, so, ro, r, v, s, shv, dd, stt, active, part);
+        hipLaunchKernelGGL(k_bf_s, dim3(nfw), dim3(kFT), 0, q, so, ns, part, stt, active, early, tol, n_active);
         launch_batch_spmv<T>(B, shv, t, active, q);
-        hipLaunchKernelGGL((k_bi_x<T>), dim3(ns), dim3(kBiNT), 0, q, B->d_row_off, s, t, ph, shv, x, r, stt, active, rho, tol,
-                           maxiter, n_active);
+        if (nseg) hipLaunchKernelGGL((k_bv_dot<T, true>), dim3(nseg), dim3(kVT), 0, q, ss, so, ro, t, s, active, part);
+        hipLaunchKernelGGL(k_bf_omega, dim3(nfw), dim3(kFT), 0, q, so, ns, part, stt, active);
+        if (nseg)
+            hipLaunchKernelGGL((k_bv_x<T>), dim3(nseg), dim3(kVT), 0, q, ss, so, ro, s, t, ph, shv, rh, x, r, stt, active,
+                               early, part);
+        hipLaunchKernelGGL(k_bf_x, dim3(nfw), dim3(kFT), 0, q, so, ns, part, stt, active, early, tol, maxiter, n_active);
     };
     const int every = o->check_every > 0 ? o->check_every : 8;
     hipEvent_t ev = nullptr;
@@ -589,13 +693,27 @@ int xab_batch_csr(xab_ctx *ctx, int32_t nsys, const int64_t *h_row_off, const in
     B->tail_val = (double *)xab_dalloc(ctx, sizeof(double) * B->P);
     B->d_sys_of_row = (int32_t *)xab_dalloc(ctx, sizeof(int32_t) * (n > 0 ? n : 1));
     B->d_row_off = (int64_t *)xab_dalloc(ctx, sizeof(int64_t) * (nsys + 1));
+    // segments of kSegRows rows for the BiCGStab row kernels
+    std::vector<int32_t> seg_off(nsys + 1), seg_sys;
+    for (int k = 0; k < nsys; ++k) {
+        seg_off[k] = (int32_t)seg_sys.size();
+        seg_sys.resize(seg_sys.size() + (size_t)((h_row_off[k + 1] - h_row_off[k] + kSegRows - 1) / kSegRows), k);
+    }
+    seg_off[nsys] = (int32_t)seg_sys.size();
+    B->nseg = (int64_t)seg_sys.size();
+    B->d_seg_off = (int32_t *)xab_dalloc(ctx, sizeof(int32_t) * (nsys + 1));
+    B->d_seg_sys = (int32_t *)xab_dalloc(ctx, sizeof(int32_t) * std::max<size_t>(seg_sys.size(), 1));
     if (!B->row_lo || !B->tile_row || !B->carry_row || !B->tail_row || !B->carry_val || !B->tail_val ||
-        !B->d_sys_of_row || !B->d_row_off) {
+        !B->d_sys_of_row || !B->d_row_off || !B->d_seg_off || !B->d_seg_sys) {
         xab_batch_destroy(B);
         return xab_fail(ctx, XAB_E_NOMEM, "batch plan");
     }
     hipStream_t st = ctx->stream;
     hipError_t e = hipMemcpyAsync(B->d_row_off, h_row_off, sizeof(int64_t) * (nsys + 1), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(B->d_seg_off, seg_off.data(), sizeof(int32_t) * (nsys + 1), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && !seg_sys.empty())
+        e = hipMemcpyAsync(B->d_seg_sys, seg_sys.data(), sizeof(int32_t) * seg_sys.size(), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) {
         xab_launch_split_bss(st, d_rowptr, (int32_t)n, T, B->P, B->row_lo, B->tile_row, B->carry_row);
         hipLaunchKernelGGL(k_sys_of_row, dim3(nsys), dim3(256), 0, st, B->d_row_off, nsys, B->d_sys_of_row);
@@ -645,6 +763,8 @@ void xab_batch_destroy(xab_batch *B) {
     xab_dfree(B->ctx, B->diag);
     xab_dfree(B->ctx, B->d_sys_of_row);
     xab_dfree(B->ctx, B->d_row_off);
+    xab_dfree(B->ctx, B->d_seg_off);
+    xab_dfree(B->ctx, B->d_seg_sys);
     xab_sell_free(B->ctx, &B->sell);
     delete B;
 }

@@ -133,6 +133,10 @@ struct xab_batch {
     double *carry_val = nullptr, *tail_val = nullptr;
     int32_t *d_sys_of_row = nullptr; // system index of every row
     int64_t *d_row_off = nullptr;    // [nsys+1]
+    // BiCGStab row segments: segment j covers rows of system d_seg_sys[j];
+    // system k owns segments [d_seg_off[k], d_seg_off[k+1])
+    int64_t nseg = 0;
+    int32_t *d_seg_sys = nullptr, *d_seg_off = nullptr;
     void *diag = nullptr;            // Jacobi diagonal (value type; lazy, library-owned)
     xab_sell sell;                   // sliced ELLPACK copy (when within its limits): the SpMV of choice
 };

@@ -268,6 +268,40 @@ def test_bicgstab_batch_fp32(ctx, tiles):
         assert np.linalg.norm(rr) / np.linalg.norm(b[r0:r1]) <= 2e-5
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_bicgstab_large_systems_span_segments(ctx, dtype):
+    """Systems of 6000-40000 rows (6-40 row segments each, ragged last
+    segments) with an empty system between them: every per-system solution
+    matches the oracle's, the empty system reports convergence at zero
+    iterations and its (empty) slice leaves the others untouched."""
+    B0 = gen.batch(5, seed=9, nmin=6000, nmax=40000)
+    k0 = 2  # insert an empty system before system 2
+    row_off = np.insert(B0.row_off, k0 + 1, B0.row_off[k0])
+    nnz_off = np.insert(B0.nnz_off, k0 + 1, B0.nnz_off[k0])
+    B = gen.Batch(B0.nsys + 1, row_off, nnz_off, B0.rowptr, B0.colind, B0.val, np.insert(B0.kinds, k0, 0),
+                  np.insert(B0.params, k0, 0))
+    tol = 1e-10 if dtype == "f64" else 1e-5
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    bt = ctx.batch(B, dtype=dtype)
+    b = np.ones(B.n)
+    x, per, agg, st = ctx.bicgstab(bt, dev(b, tdt), tol=tol, check_every=4)
+    assert st == 0
+    assert per[k0]["status"] == 0 and per[k0]["iters"] == 0
+    xs = x.double().cpu().numpy()
+    for k in range(B.nsys):
+        r0, r1 = int(B.row_off[k]), int(B.row_off[k + 1])
+        if r1 == r0:
+            continue
+        S = B.system(k)
+        rr = b[r0:r1] - oracle.spmv(S, xs[r0:r1])[0]
+        assert np.linalg.norm(rr) / np.linalg.norm(b[r0:r1]) <= (tol * 1.01 if dtype == "f64" else 2e-5)
+        if dtype == "f64":
+            ref = oracle.bicgstab(S, b[r0:r1], tol=tol, precond=1)
+            assert ref["status"] == 0
+            assert np.linalg.norm(xs[r0:r1] - ref["x"]) / np.linalg.norm(ref["x"]) <= 1e-8
+            assert abs(per[k]["iters"] - ref["iters"]) <= max(2, 0.25 * ref["iters"])
+
+
 def test_bicgstab_breakdown(ctx):
     """Rotation [[0,-1],[1,0]] as one system: <rhat, A p> = 0 at step one."""
     rp = np.array([0, 1, 2, 3, 4], dtype=np.int32)
