@@ -65,7 +65,7 @@ __global__ __launch_bounds__(kNT) void k_batch_spmv(const int32_t *__restrict__ 
 // whose rows belongs to an active system is skipped (its products are never
 // read); otherwise every row of the chunk is computed.
 constexpr int kSellC = xab_plan::kSellC;
-constexpr int kSellUnroll = 4;
+constexpr int kSellUnroll = 12; // entries per lane in flight: the random-row systems are held by the gather rate
 
 template <class T>
 __global__ __launch_bounds__(kNT) void k_batch_sell(const int64_t *__restrict__ cptr, const int32_t *__restrict__ clen,
