@@ -1,14 +1,15 @@
 // Batched independent systems: the block-diagonal concatenation of many
-// CSR matrices, one persistent SpMV launch over all of them, and BiCGStab
-// (van der Vorst's form, the paper's second linear solver) advancing every
-// system at once.  One iteration is eleven kernels: two SpMVs, five row
-// kernels over segments of kSegRows rows (a large system spans many
-// workgroups) and four one-wave-per-system kernels that sum the segments'
-// partial inner products in a fixed order and take the scalar decisions.  It
-// is captured once in a HIP graph and replayed.  Per-system scalars live on
-// the device; a system that converges (or breaks down) is masked from then
-// on, and SpMV chunks or tiles whose systems are all inactive skip their
-// work.
+// CSR matrices, one SpMV launch over all of them, and BiCGStab (van der
+// Vorst's form, the paper's second linear solver) advancing every system at
+// once.  One iteration is twelve kernels: a work-list kernel (the segments
+// and SELL windows of the systems still active), two SpMVs, five row kernels
+// over segments of kSegRows rows (a large system spans many workgroups) and
+// four one-wave-per-system kernels that sum the segments' partial inner
+// products in a fixed order and take the scalar decisions.  It is captured
+// once in a HIP graph and replayed.  Per-system scalars live on the device;
+// a system that converges (or breaks down) is masked from then on and drops
+// out of the next iteration's lists (segmented-scan tiles whose systems are
+// all inactive skip their work).
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -88,6 +89,36 @@ __global__ __launch_bounds__(kNT) void k_batch_sell(const int64_t *__restrict__ 
     if (row >= 0) y[row] = (T)acc;
 }
 
+// The same SpMV over the windows listed for this iteration (kSellSigma rows:
+// kWinItems workgroup items of 4 chunks).  The items are dealt so that each
+// XCD serves a contiguous range of them, whatever their number; workgroups
+// past the last item return at once.
+constexpr int kWinItems = kSellSigma / kSellC / (kNT / kSellC);
+
+template <class T>
+__global__ __launch_bounds__(kNT) void k_batch_sell_listed(const int64_t *__restrict__ cptr,
+                                                           const int32_t *__restrict__ clen,
+                                                           const int32_t *__restrict__ rlen,
+                                                           const int32_t *__restrict__ perm,
+                                                           const int32_t *__restrict__ cols, const T *__restrict__ val,
+                                                           const T *__restrict__ x, T *__restrict__ y, int32_t n,
+                                                           int64_t nch, const int32_t *__restrict__ win_list,
+                                                           const int *__restrict__ lcount) {
+    const int64_t N = (int64_t)lcount[1] * kWinItems;
+    const int64_t q = N / xab::kXcds, rem = N % xab::kXcds;
+    const int64_t xcd = blockIdx.x % xab::kXcds, slot = blockIdx.x / xab::kXcds;
+    if (slot >= q + (xcd < rem ? 1 : 0)) return;
+    const int64_t item = xcd * q + (xcd < rem ? xcd : rem) + slot;
+    const int64_t c = ((int64_t)win_list[item / kWinItems] * kWinItems + item % kWinItems) * (kNT / kSellC) +
+                      threadIdx.x / kSellC;
+    if (c >= nch) return;
+    const int l = threadIdx.x % kSellC;
+    const int64_t r = c * kSellC + l;
+    const int32_t row = r < n ? perm[r] : -1;
+    const double acc = xab::sell_lane_sum<T, T, double, kSellUnroll>(val, cols, x, cptr[c] + l, clen[c], rlen[r]);
+    if (row >= 0) y[row] = (T)acc;
+}
+
 // rows cut by a tile end: start partial plus the following tiles' carries,
 // in ascending tile order
 template <class T>
@@ -162,18 +193,50 @@ __global__ __launch_bounds__(kBiNT) void k_bi_init(const int64_t *__restrict__ r
     }
 }
 
-// ---- row kernels: one workgroup per segment of kSegRows rows of one system,
-// so that a large system is spread over many CUs.  Each reads the scalars of
-// its system (written by the per-system kernels, never by a row kernel) and
-// leaves its inner products as one partial per segment.
+// ---- work lists of one iteration: the row segments of the systems active at
+// its start and the SELL windows (kSellSigma rows) holding a row of one,
+// appended in any order (each item's work does not depend on its place).
+// The counts are cleared by the last kernel of the previous iteration.
+// Systems that stop during the iteration stay listed; the kernels test
+// their masks.
+__device__ __forceinline__ void wave_append(bool pred, int32_t item, int32_t *__restrict__ list, int *__restrict__ count) {
+    const unsigned long long bal = __ballot(pred);
+    if (bal == 0) return;  // wave-uniform
+    const int lane = threadIdx.x % xab::kWave, leader = __ffsll((long long)bal) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(count, __popcll(bal));
+    base = __shfl(base, leader);
+    if (pred) list[base + __popcll(bal & ((1ull << lane) - 1ull))] = item;
+}
+
+__global__ __launch_bounds__(256) void k_bi_lists(int64_t n, int64_t nseg, int64_t nwin,
+                                                  const int32_t *__restrict__ seg_sys,
+                                                  const int32_t *__restrict__ sys_of_row,
+                                                  const int *__restrict__ active, int32_t *__restrict__ seg_list,
+                                                  int32_t *__restrict__ win_list, int *__restrict__ count) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    wave_append(g < nseg && active[seg_sys[g]] != 0, (int32_t)g, seg_list, &count[0]);
+    bool w_on = false;
+    if (g < nwin) {
+        const int32_t k0 = sys_of_row[g * kSellSigma];
+        const int32_t k1 = sys_of_row[min(n, (g + 1) * kSellSigma) - 1];
+        for (int32_t k = k0; k <= k1 && !w_on; ++k) w_on = active[k] != 0;
+    }
+    wave_append(w_on, (int32_t)g, win_list, &count[1]);
+}
+
+// ---- row kernels: one workgroup per listed segment of kSegRows rows of one
+// system, so that a large system is spread over many CUs.  Each reads the
+// scalars of its system (written by the per-system kernels, never by a row
+// kernel) and leaves its inner products as one partial per segment.
 struct SegRange {
     int k;
     int64_t r0, r1;
 };
 
-__device__ __forceinline__ SegRange seg_range(const int32_t *__restrict__ seg_sys, const int32_t *__restrict__ seg_off,
+__device__ __forceinline__ SegRange seg_range(int32_t j, const int32_t *__restrict__ seg_sys,
+                                              const int32_t *__restrict__ seg_off,
                                               const int64_t *__restrict__ row_off) {
-    const int j = blockIdx.x;
     const int k = seg_sys[j];
     const int64_t r0 = row_off[k] + (int64_t)(j - seg_off[k]) * kSegRows;
     return {k, r0, min(r0 + (int64_t)kSegRows, row_off[k + 1])};
@@ -191,18 +254,25 @@ __device__ __forceinline__ double vsum(double v, double *sh) {
     return t;
 }
 
+// the listed segment of this workgroup (the kernel returns past the list's end)
+#define XAB_LISTED_SEGMENT(j)                                \
+    if ((int64_t)blockIdx.x >= (int64_t)lcount[0]) return;   \
+    const int32_t j = seg_list[blockIdx.x]
+
 #define XAB_SEG_ROWS(R, i)                                              \
     _Pragma("unroll") for (int u_ = 0; u_ < kSegRows / kVT; ++u_)       \
         if (const int64_t i = (R).r0 + threadIdx.x + (int64_t)u_ * kVT; i < (R).r1)
 
 // p = r + beta (p - omega v), phat = M^-1 p
 template <class T>
-__global__ __launch_bounds__(kVT) void k_bv_p(const int32_t *__restrict__ seg_sys, const int32_t *__restrict__ seg_off,
+__global__ __launch_bounds__(kVT) void k_bv_p(const int32_t *__restrict__ seg_list, const int *__restrict__ lcount,
+                                            const int32_t *__restrict__ seg_sys, const int32_t *__restrict__ seg_off,
                                             const int64_t *__restrict__ row_off, const T *__restrict__ r,
                                             T *__restrict__ p, const T *__restrict__ v, T *__restrict__ ph,
                                             const T *__restrict__ d, const SysState *__restrict__ st,
                                             const int *__restrict__ active) {
-    const SegRange R = seg_range(seg_sys, seg_off, row_off);
+    XAB_LISTED_SEGMENT(j);
+    const SegRange R = seg_range(j, seg_sys, seg_off, row_off);
     if (!active[R.k]) return;
     const double beta = st[R.k].beta, om = st[R.k].omega;
     XAB_SEG_ROWS(R, i) {
@@ -214,13 +284,15 @@ __global__ __launch_bounds__(kVT) void k_bv_p(const int32_t *__restrict__ seg_sy
 
 // partial <a, b> (and <a, a> when kTwo) of each segment
 template <class T, bool kTwo>
-__global__ __launch_bounds__(kVT) void k_bv_dot(const int32_t *__restrict__ seg_sys,
+__global__ __launch_bounds__(kVT) void k_bv_dot(const int32_t *__restrict__ seg_list, const int *__restrict__ lcount,
+                                              const int32_t *__restrict__ seg_sys,
                                               const int32_t *__restrict__ seg_off,
                                               const int64_t *__restrict__ row_off, const T *__restrict__ a,
                                               const T *__restrict__ b, const int *__restrict__ active,
                                               double *__restrict__ part) {
     __shared__ double sh[kVT / xab::kWave];
-    const SegRange R = seg_range(seg_sys, seg_off, row_off);
+    XAB_LISTED_SEGMENT(j);
+    const SegRange R = seg_range(j, seg_sys, seg_off, row_off);
     if (!active[R.k]) return;
     double ab = 0.0, aa = 0.0;
     XAB_SEG_ROWS(R, i) {
@@ -231,20 +303,22 @@ __global__ __launch_bounds__(kVT) void k_bv_dot(const int32_t *__restrict__ seg_
     ab = vsum(ab, sh);
     if (kTwo) aa = vsum(aa, sh);
     if (threadIdx.x == 0) {
-        part[2 * blockIdx.x] = ab;
-        if (kTwo) part[2 * blockIdx.x + 1] = aa;
+        part[2 * (int64_t)j] = ab;
+        if (kTwo) part[2 * (int64_t)j + 1] = aa;
     }
 }
 
 // s = r - alpha v, shat = M^-1 s, partial <s, s>
 template <class T>
-__global__ __launch_bounds__(kVT) void k_bv_s(const int32_t *__restrict__ seg_sys, const int32_t *__restrict__ seg_off,
+__global__ __launch_bounds__(kVT) void k_bv_s(const int32_t *__restrict__ seg_list, const int *__restrict__ lcount,
+                                            const int32_t *__restrict__ seg_sys, const int32_t *__restrict__ seg_off,
                                             const int64_t *__restrict__ row_off, const T *__restrict__ r,
                                             const T *__restrict__ v, T *__restrict__ s, T *__restrict__ shv,
                                             const T *__restrict__ d, const SysState *__restrict__ st,
                                             const int *__restrict__ active, double *__restrict__ part) {
     __shared__ double sh[kVT / xab::kWave];
-    const SegRange R = seg_range(seg_sys, seg_off, row_off);
+    XAB_LISTED_SEGMENT(j);
+    const SegRange R = seg_range(j, seg_sys, seg_off, row_off);
     if (!active[R.k]) return;
     const double alpha = st[R.k].alpha;
     double ss = 0.0;
@@ -255,14 +329,15 @@ __global__ __launch_bounds__(kVT) void k_bv_s(const int32_t *__restrict__ seg_sy
         ss += (double)si * (double)si;
     }
     ss = vsum(ss, sh);
-    if (threadIdx.x == 0) part[2 * blockIdx.x] = ss;
+    if (threadIdx.x == 0) part[2 * (int64_t)j] = ss;
 }
 
 // x += alpha phat + omega shat, r = s - omega t, partials <r, r> and
 // <rhat, r>; a system whose s met the tolerance this iteration takes
 // x += alpha phat alone
 template <class T>
-__global__ __launch_bounds__(kVT) void k_bv_x(const int32_t *__restrict__ seg_sys, const int32_t *__restrict__ seg_off,
+__global__ __launch_bounds__(kVT) void k_bv_x(const int32_t *__restrict__ seg_list, const int *__restrict__ lcount,
+                                            const int32_t *__restrict__ seg_sys, const int32_t *__restrict__ seg_off,
                                             const int64_t *__restrict__ row_off, const T *__restrict__ s,
                                             const T *__restrict__ t, const T *__restrict__ ph,
                                             const T *__restrict__ shv, const T *__restrict__ rh, T *__restrict__ x,
@@ -270,7 +345,8 @@ __global__ __launch_bounds__(kVT) void k_bv_x(const int32_t *__restrict__ seg_sy
                                             const int *__restrict__ active, const int *__restrict__ early,
                                             double *__restrict__ part) {
     __shared__ double sh[kVT / xab::kWave];
-    const SegRange R = seg_range(seg_sys, seg_off, row_off);
+    XAB_LISTED_SEGMENT(j);
+    const SegRange R = seg_range(j, seg_sys, seg_off, row_off);
     const double al = st[R.k].alpha;
     if (early[R.k]) {
         XAB_SEG_ROWS(R, i) x[i] = (T)((double)x[i] + al * (double)ph[i]);
@@ -289,12 +365,13 @@ __global__ __launch_bounds__(kVT) void k_bv_x(const int32_t *__restrict__ seg_sy
     rr = vsum(rr, sh);
     rho = vsum(rho, sh);
     if (threadIdx.x == 0) {
-        part[2 * blockIdx.x] = rr;
-        part[2 * blockIdx.x + 1] = rho;
+        part[2 * (int64_t)j] = rr;
+        part[2 * (int64_t)j + 1] = rho;
     }
 }
 
 #undef XAB_SEG_ROWS
+#undef XAB_LISTED_SEGMENT
 
 // ---- per-system kernels: one wave per system sums the partials of its
 // segments in segment order (a fixed xor tree over the lanes), takes the
@@ -366,7 +443,8 @@ __global__ __launch_bounds__(kFT) void k_bf_omega(const int32_t *__restrict__ se
 __global__ __launch_bounds__(kFT) void k_bf_x(const int32_t *__restrict__ seg_off, int ns,
                                             const double *__restrict__ part, SysState *__restrict__ st,
                                             int *__restrict__ active, int *__restrict__ early, double tol,
-                                            int64_t maxiter, int *__restrict__ n_active) {
+                                            int64_t maxiter, int *__restrict__ n_active, int *__restrict__ lcount) {
+    if (blockIdx.x == 0 && threadIdx.x < 2) lcount[threadIdx.x] = 0;  // lists of the next iteration
     const int k = wave_system();
     if (k >= ns) return;
     const bool lead = threadIdx.x % xab::kWave == 0;
@@ -503,7 +581,11 @@ int bicgstab_t(xab_ctx *ctx, const xab_batch *B, const T *bvec, T *x, const xab_
     size_t off_cnt = off_early + al(sizeof(int) * ns);
     size_t off_res = off_cnt + 256;
     size_t off_part = off_res + al(sizeof(double) * ns);
-    size_t total = off_part + al(sizeof(double) * 2 * (size_t)std::max<int64_t>(B->nseg, 1));
+    const int64_t nwin = B->sell.cols ? (n + kSellSigma - 1) / kSellSigma : 0;
+    size_t off_lseg = off_part + al(sizeof(double) * 2 * (size_t)std::max<int64_t>(B->nseg, 1));
+    size_t off_lwin = off_lseg + al(sizeof(int32_t) * (size_t)std::max<int64_t>(B->nseg, 1));
+    size_t off_lcnt = off_lwin + al(sizeof(int32_t) * (size_t)std::max<int64_t>(nwin, 1));
+    size_t total = off_lcnt + 256;
     char *w = (char *)xab_dalloc(ctx, total);
     if (!w) return xab_fail(ctx, XAB_E_NOMEM, "BiCGStab workspace");
     T *r = (T *)w, *rh = (T *)(w + vb), *p = (T *)(w + 2 * vb), *v = (T *)(w + 3 * vb), *ph = (T *)(w + 4 * vb);
@@ -515,6 +597,8 @@ int bicgstab_t(xab_ctx *ctx, const xab_batch *B, const T *bvec, T *x, const xab_
     int *n_active = (int *)(w + off_cnt);
     double *res = (double *)(w + off_res);
     double *part = (double *)(w + off_part);
+    int32_t *seg_list = (int32_t *)(w + off_lseg), *win_list = (int32_t *)(w + off_lwin);
+    int *lcount = (int *)(w + off_lcnt);
     hipStream_t st = ctx->stream;
     hipStream_t gs = nullptr;
     hipGraph_t graph = nullptr;
@@ -545,6 +629,8 @@ int bicgstab_t(xab_ctx *ctx, const xab_batch *B, const T *bvec, T *x, const xab_
                                (const T *)B->val, n, (T *)Bm->diag);
     }
     hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, st, n_active);
+    hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, st, lcount);
+    hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, st, lcount + 1);
     if ((sres = batch_spmv_t<T>(ctx, B, x, ax, nullptr, st)) != XAB_OK) return cleanup(sres);
     hipLaunchKernelGGL((k_bi_init<T>), dim3(ns), dim3(kBiNT), 0, st, B->d_row_off, bvec, ax, r, rh, p, v, stt, active,
                        early, tol, n_active);
@@ -554,23 +640,48 @@ int bicgstab_t(xab_ctx *ctx, const xab_batch *B, const T *bvec, T *x, const xab_
     // one iteration over all systems
     const unsigned nseg = (unsigned)B->nseg;
     const unsigned nfw = (unsigned)((ns + kFT / xab::kWave - 1) / (kFT / xab::kWave));
+    const unsigned nlist = grid_for(std::max<int64_t>(B->nseg, nwin), 256);
+    const unsigned gwin = (unsigned)((nwin * kWinItems + xab::kXcds - 1) / xab::kXcds * xab::kXcds);
     const int32_t *so = B->d_seg_off, *ss = B->d_seg_sys;
     const int64_t *ro = B->d_row_off;
+    auto spmv = [&](const T *xin, T *yout, hipStream_t q) {
+        if (!nwin) {
+            launch_batch_spmv<T>(B, xin, yout, active, q);
+            return;
+        }
+        const xab_sell &S = B->sell;
+        const T *pv;
+        if constexpr (sizeof(T) == 8) pv = (const T *)S.val64;
+        else pv = (const T *)S.val32;
+        hipLaunchKernelGGL((k_batch_sell_listed<T>), dim3(gwin), dim3(kNT), 0, q, S.cptr, S.clen, S.rlen, S.perm,
+                           S.cols, pv, xin, yout, (int32_t)n, S.nch, win_list, lcount);
+    };
     auto enqueue_iter = [&](hipStream_t q) {
-        if (nseg) hipLaunchKernelGGL((k_bv_p<T>), dim3(nseg), dim3(kVT), 0, q, ss, so, ro, r, p, v, ph, dd, stt, active);
-        launch_batch_spmv<T>(B, ph, v, active, q);
-        if (nseg) hipLaunchKernelGGL((k_bv_dot<T, false>), dim3(nseg), dim3(kVT), 0, q, ss, so, ro, v, rh, active, part);
+        if (nlist)
+            hipLaunchKernelGGL(k_bi_lists, dim3(nlist), dim3(256), 0, q, n, B->nseg, nwin, ss, B->d_sys_of_row, active,
+                               seg_list, win_list, lcount);
+        if (nseg)
+            hipLaunchKernelGGL((k_bv_p<T>), dim3(nseg), dim3(kVT), 0, q, seg_list, lcount, ss, so, ro, r, p, v, ph, dd,
+                               stt, active);
+        spmv(ph, v, q);
+        if (nseg)
+            hipLaunchKernelGGL((k_bv_dot<T, false>), dim3(nseg), dim3(kVT), 0, q, seg_list, lcount, ss, so, ro, v, rh,
+                               active, part);
         hipLaunchKernelGGL(k_bf_alpha, dim3(nfw), dim3(kFT), 0, q, so, ns, part, stt, active, n_active);
         if (nseg)
-            hipLaunchKernelGGL((k_bv_s<T>), dim3(nseg), dim3(kVT), 0, q, ss, so, ro, r, v, s, shv, dd, stt, active, part);
+            hipLaunchKernelGGL((k_bv_s<T>), dim3(nseg), dim3(kVT), 0, q, seg_list, lcount, ss, so, ro, r, v, s, shv, dd,
+                               stt, active, part);
         hipLaunchKernelGGL(k_bf_s, dim3(nfw), dim3(kFT), 0, q, so, ns, part, stt, active, early, tol, n_active);
-        launch_batch_spmv<T>(B, shv, t, active, q);
-        if (nseg) hipLaunchKernelGGL((k_bv_dot<T, true>), dim3(nseg), dim3(kVT), 0, q, ss, so, ro, t, s, active, part);
+        spmv(shv, t, q);
+        if (nseg)
+            hipLaunchKernelGGL((k_bv_dot<T, true>), dim3(nseg), dim3(kVT), 0, q, seg_list, lcount, ss, so, ro, t, s,
+                               active, part);
         hipLaunchKernelGGL(k_bf_omega, dim3(nfw), dim3(kFT), 0, q, so, ns, part, stt, active);
         if (nseg)
-            hipLaunchKernelGGL((k_bv_x<T>), dim3(nseg), dim3(kVT), 0, q, ss, so, ro, s, t, ph, shv, rh, x, r, stt, active,
-                               early, part);
-        hipLaunchKernelGGL(k_bf_x, dim3(nfw), dim3(kFT), 0, q, so, ns, part, stt, active, early, tol, maxiter, n_active);
+            hipLaunchKernelGGL((k_bv_x<T>), dim3(nseg), dim3(kVT), 0, q, seg_list, lcount, ss, so, ro, s, t, ph, shv, rh,
+                               x, r, stt, active, early, part);
+        hipLaunchKernelGGL(k_bf_x, dim3(nfw), dim3(kFT), 0, q, so, ns, part, stt, active, early, tol, maxiter, n_active,
+                           lcount);
     };
     const int every = o->check_every > 0 ? o->check_every : 8;
     hipEvent_t ev = nullptr;
