@@ -565,6 +565,13 @@ def main():
     time_wall_ms = (time.perf_counter() - t0) * 1e3
     chosen = int(info.chosen)
     times = {k: round(float(info.time_ms[k]) * 1e3, 2) for k in range(xab.NCLASSES) if info.valid[k]}
+    plan_mb = {k: round(int(info.bytes[k]) / 1e6, 2) for k in range(xab.NCLASSES) if info.valid[k]}
+    # the MEMORY policy: least plan memory, then speed
+    mplan, minfo = ctx.select(M, xab.MEMORY)
+    memory = {"chosen_class": int(minfo.chosen), "plan_mb": round(mplan.bytes / 1e6, 2),
+              "us": round(float(minfo.time_ms[minfo.chosen]) * 1e3, 2)}
+    mplan.close()
+    torch.cuda.synchronize()
 
     # timed region: K steps of the selected FP64 SpMV
     for _ in range(args.warmup):
@@ -651,7 +658,8 @@ def main():
         "gflops": round(2 * A.nnz / (wall / args.steps) / 1e9, 1),
         "fp32_values": fp32,
         "selector": {"chosen_class": chosen, "us_per_class": times, "select_ms": round(float(info.select_ms), 2),
-                     "select_wall_ms": round(time_wall_ms, 2), "learned": learned},
+                     "select_wall_ms": round(time_wall_ms, 2), "learned": learned,
+                     "plan_mb_per_class": plan_mb, "memory_policy": memory},
         "gmres": gm,
         "sym27": c3,
         "batch512": c4,

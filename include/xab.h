@@ -63,10 +63,14 @@ typedef struct xab_batch xab_batch;
 
 typedef enum { XAB_F64 = 0, XAB_F32 = 1 } xab_dtype;
 
-/* Numerical computation policy for the selector (section 2.3): TIME picks
- * the fastest measured implementation; STABLE runs without auto-tuning
- * (fixed default); LEARNED uses the trained cost model instead of timing. */
-typedef enum { XAB_TIME = 0, XAB_STABLE = 1, XAB_LEARNED = 2 } xab_policy;
+/* Numerical computation policy (section 2.3): TIME picks the fastest
+ * measured implementation; STABLE runs without auto-tuning (fixed default);
+ * LEARNED uses the trained cost model instead of timing; MEMORY sets
+ * arguments for the least device memory: the selector keeps to the
+ * implementations whose plans hold the fewest bytes (see xab_select), and
+ * on a context whose default policy is MEMORY the solvers do not grow the
+ * restart length (the basis keeps its starting size). */
+typedef enum { XAB_TIME = 0, XAB_STABLE = 1, XAB_LEARNED = 2, XAB_MEMORY = 3 } xab_policy;
 
 /* SpMV implementations (section 3.2.2 candidate list):
  *   XAB_ROW        row-based decomposition, equal rows per workgroup,
@@ -147,7 +151,9 @@ typedef struct {
 
 /* Create a context: device, stream, allocator and policy defaults (the
  * paper's initialisation call that sets library defaults, Table 1).
- * opts may be NULL for all defaults. */
+ * opts may be NULL for all defaults.  The environment variable XAB_POLICY
+ * (TIME, STABLE, LEARNED or MEMORY) overrides the default policy, as the
+ * paper's policy file does.  XAB_E_SHAPE for a policy outside the enum. */
 int xab_init(xab_ctx **ctx, const xab_init_opts *opts);
 void xab_finalize(xab_ctx *ctx);
 /* Re-point the context at another stream (hipStream_t). */
@@ -212,6 +218,7 @@ typedef struct {
     float time_ms[XAB_NCLASSES];        /* measured (TIME) or predicted (LEARNED) cost; <0 = invalid class */
     float select_ms;                    /* wall time spent selecting, plan builds included */
     int32_t valid[XAB_NCLASSES];        /* 1 if the class applies to this matrix */
+    int64_t bytes[XAB_NCLASSES];        /* device bytes of the class's plan (TIME, MEMORY); -1 = not set up */
 } xab_select_info;
 
 /* Choose an implementation under `policy` and return its plan (the
@@ -219,9 +226,17 @@ typedef struct {
  * valid class, times each over 1 warm-up plus 4 runs (minimum taken) and
  * keeps the fastest (lowest class index on ties); STABLE returns the fixed
  * default (NNZ tile_nnz 2048, or SYM_S3 class 11); LEARNED evaluates the
- * cost model on the matrix features.  Timing runs use FP64 (or the only
- * precision the matrix holds).  info may be NULL.  Synchronous. */
+ * cost model on the matrix features; MEMORY sets every valid class up once
+ * to learn its plan's bytes, then times, as TIME does, only the classes
+ * within 1/64 of the matrix's own bytes (row pointers, columns, values) of
+ * the least, and keeps the fastest of them.  Timing runs use FP64 (or the
+ * only precision the matrix holds).  info may be NULL.  Synchronous. */
 int xab_select(xab_ctx *ctx, const xab_matrix *A, xab_policy policy, xab_plan **plan, xab_select_info *info);
+
+/* Device memory held by a plan (its own arrays: partitions, descriptors,
+ * partials and any re-laid-out copy of the matrix), in bytes; -1 for NULL.
+ * The matrix's own arrays are the caller's and not counted. */
+int64_t xab_plan_bytes(const xab_plan *plan);
 
 /* The 12 selector features of A (device statistics pass, exact integer
  * arithmetic).  h_out[12]: log2 n, log2 nnz, mean row length, log2(1 +

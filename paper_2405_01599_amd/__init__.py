@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libxab.so")
 
 F64, F32 = 0, 1
-TIME, STABLE, LEARNED = 0, 1, 2
+TIME, STABLE, LEARNED, MEMORY = 0, 1, 2, 3
 ROW, NNZ, BSS, SYM_S3, SYM_ATOMIC, XCB, SELL, BCSR = 0, 1, 2, 3, 4, 5, 6, 7
 VARIANT_NAMES = {ROW: "row", NNZ: "nnz", BSS: "bss", SYM_S3: "sym_s3", SYM_ATOMIC: "sym_atomic", XCB: "xcb",
                  SELL: "sell", BCSR: "bcsr"}
@@ -51,7 +51,7 @@ class InitOpts(ctypes.Structure):
 
 class SelectInfo(ctypes.Structure):
     _fields_ = [("chosen", ctypes.c_int32), ("time_ms", ctypes.c_float * NCLASSES), ("select_ms", ctypes.c_float),
-                ("valid", ctypes.c_int32 * NCLASSES)]
+                ("valid", ctypes.c_int32 * NCLASSES), ("bytes", ctypes.c_int64 * NCLASSES)]
 
 
 class TrainOpts(ctypes.Structure):
@@ -115,6 +115,7 @@ SIGNATURES = {
     "xab_plan_destroy": (None, [_P]),
     "xab_plan_array": (ctypes.c_int, [_P, _I32, _P, ctypes.POINTER(_I64)]),
     "xab_plan_info": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(Params)]),
+    "xab_plan_bytes": (ctypes.c_int64, [_P]),
     "xab_spmv_csr": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, _P, ctypes.c_int, ctypes.c_int]),
     "xab_spmv_sym": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, _P, ctypes.c_int, ctypes.c_int]),
     "xab_time_spmv": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, _P, ctypes.c_int, ctypes.c_int, _I32, _I32,
@@ -465,6 +466,11 @@ class Plan:
         p = Params()
         lib().xab_plan_info(self.h, ctypes.byref(v), ctypes.byref(p))
         self.variant, self.params = v.value, p
+
+    @property
+    def bytes(self):
+        """Device bytes held by the plan's own arrays."""
+        return int(lib().xab_plan_bytes(self.h))
 
     def array(self, which):
         n = _I64()

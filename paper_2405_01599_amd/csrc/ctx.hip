@@ -22,17 +22,26 @@ int xab_hip_check(xab_ctx *ctx, hipError_t e, const char *what) {
 
 void *xab_dalloc(xab_ctx *ctx, size_t bytes) {
     if (bytes == 0) bytes = 256;
-    if (ctx->alloc_fn) return ctx->alloc_fn(bytes, ctx->user);
     void *p = nullptr;
-    if (hipMalloc(&p, bytes) != hipSuccess) {
+    if (ctx->alloc_fn) {
+        p = ctx->alloc_fn(bytes, ctx->user);
+    } else if (hipMalloc(&p, bytes) != hipSuccess) {
         (void)hipGetLastError();
-        return nullptr;
+        p = nullptr;
     }
+    if (p) ctx->live[p] = bytes;
     return p;
+}
+
+size_t xab_dbytes(const xab_ctx *ctx, const void *p) {
+    if (!p) return 0;
+    auto it = ctx->live.find(p);
+    return it == ctx->live.end() ? 0 : it->second;
 }
 
 void xab_dfree(xab_ctx *ctx, void *p) {
     if (!p) return;
+    ctx->live.erase(p);
     if (ctx->free_fn) ctx->free_fn(p, ctx->user);
     else (void)hipFree(p);
 }
@@ -65,6 +74,10 @@ int xab_init(xab_ctx **out, const xab_init_opts *opts) {
         ctx->free_fn = opts->free;
         ctx->user = opts->user;
         ctx->stream = (hipStream_t)opts->stream;
+        if (opts->policy < XAB_TIME || opts->policy > XAB_MEMORY) {
+            delete ctx;
+            return XAB_E_SHAPE;
+        }
         ctx->policy = opts->policy;
     }
     int dev = (opts && opts->device >= 0) ? opts->device : -1;
@@ -88,6 +101,7 @@ int xab_init(xab_ctx **out, const xab_init_opts *opts) {
         if (!strcmp(pol, "TIME")) ctx->policy = XAB_TIME;
         else if (!strcmp(pol, "STABLE")) ctx->policy = XAB_STABLE;
         else if (!strcmp(pol, "LEARNED")) ctx->policy = XAB_LEARNED;
+        else if (!strcmp(pol, "MEMORY")) ctx->policy = XAB_MEMORY;
     }
     *out = ctx;
     return XAB_OK;

@@ -233,7 +233,7 @@ extern "C" int xab_gmres(xab_ctx *ctx, const xab_plan *pl, const double *d_b, do
     if (A->n != A->ncols) return xab_fail(ctx, XAB_E_SHAPE, "GMRES needs a square matrix");
     const int m0 = opts->m;
     if (m0 < 1 || m0 > 63) return xab_fail(ctx, XAB_E_SHAPE, "restart length must be in [1, 63]");
-    const bool tune = opts->restart_step > 0;
+    const bool tune = opts->restart_step > 0 && ctx->policy != XAB_MEMORY;  // MEMORY: the basis keeps its size
     if (tune && (opts->m_max < m0 || opts->m_max > 63))
         return xab_fail(ctx, XAB_E_SHAPE, "m_max must be in [m, 63]");
     const int mcap = tune ? opts->m_max : m0;  // basis capacity

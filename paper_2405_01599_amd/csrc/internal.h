@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/xab.h"
@@ -23,6 +24,7 @@ struct xab_ctx {
     // device scratch owned by the context (grown on demand)
     void *scratch = nullptr;
     size_t scratch_bytes = 0;
+    std::unordered_map<const void *, size_t> live;  // bytes of every block from xab_dalloc not yet freed
     int *d_flag = nullptr;          // validation error flags
     // cost model (host copy; uploaded on use)
     std::vector<float> mlp;         // XAB_MLP_NPARAMS
@@ -148,6 +150,8 @@ void xab_dfree(xab_ctx *ctx, void *p);
 int xab_hip_check(xab_ctx *ctx, hipError_t e, const char *what);
 // scratch: at least `bytes` of context-owned device memory (reused across calls)
 void *xab_scratch(xab_ctx *ctx, size_t bytes);
+// bytes of a live block from xab_dalloc (0 for NULL or unknown pointers)
+size_t xab_dbytes(const xab_ctx *ctx, const void *p);
 
 #define XAB_HIP(ctx, call)                                   \
     do {                                                     \

@@ -73,7 +73,7 @@ extern "C" int xab_lanczos(xab_ctx *ctx, const xab_plan *pl, const double *d_v0,
     const int64_t n = A->n;
     const int nev = opts->nev;
     int m = opts->m;  // length of the next cycle
-    const bool tune = opts->restart_step > 0;
+    const bool tune = opts->restart_step > 0 && ctx->policy != XAB_MEMORY;  // MEMORY: the basis keeps its size
     const int mc = tune ? opts->m_max : m;  // basis capacity
     const int window = opts->window > 0 ? opts->window : 5;
     if (A->n != A->ncols) return xab_fail(ctx, XAB_E_SHAPE, "Lanczos needs a square matrix");

@@ -621,6 +621,22 @@ static void free_plan_arrays(xab_ctx *ctx, xab_plan *pl) {
     xab_dfree(ctx, pl->xcb_Y);
 }
 
+// device bytes of the plan's own arrays
+static size_t plan_device_bytes(const xab_plan *pl) {
+    const xab_ctx *c = pl->ctx;
+    const void *arrays[] = {pl->b, pl->row_lo, pl->tile_row, pl->carry_row, pl->carry_val, pl->tail_val,
+                            pl->tail_row, pl->tm_ptr, pl->tm_tile, pl->tile_ptr, pl->tile_blk, pl->tile_slot,
+                            pl->tile_minblk, pl->partial, pl->xcb_rowptr, pl->xcb_gbase, pl->s3_ci, pl->s3_dense,
+                            pl->sell.perm, pl->sell.rlen, pl->sell.clen, pl->sell.cptr, pl->sell.cols,
+                            pl->sell.val64, pl->sell.val32, pl->bcsr_brp, pl->bcsr_bci, pl->bcsr_mask,
+                            pl->bcsr_val64, pl->bcsr_val32, pl->xcb_mask, pl->xcb_colind, pl->xcb_val64,
+                            pl->xcb_val32, pl->xcb_row_lo, pl->xcb_tile_row, pl->xcb_carry_row, pl->xcb_tail_row,
+                            pl->xcb_carry_val, pl->xcb_tail_val, pl->xcb_Y};
+    size_t t = 0;
+    for (const void *p : arrays) t += xab_dbytes(c, p);
+    return t;
+}
+
 #define ALLOC(ptr, T, count)                                              \
     do {                                                                  \
         (ptr) = (T *)xab_dalloc(ctx, sizeof(T) * (size_t)(count));        \
@@ -1175,6 +1191,8 @@ extern "C" {
 int xab_plan_fixed(xab_ctx *ctx, const xab_matrix *A, xab_variant v, const xab_params *p, xab_plan **plan) {
     return xab_build_plan(ctx, A, v, p, plan);
 }
+
+int64_t xab_plan_bytes(const xab_plan *pl) { return pl ? (int64_t)plan_device_bytes(pl) : -1; }
 
 void xab_plan_destroy(xab_plan *pl) {
     if (!pl) return;

@@ -5,6 +5,10 @@
 //   STABLE   no tuning: a fixed default (section 2.3, policy STABLE)
 //   LEARNED  the cost model predicts every class from the matrix features;
 //            the best predicted class that can be set up wins
+//   MEMORY   the least device memory (section 2.3, policy MEMORY): every
+//            valid class is set up once to learn its plan's bytes; those
+//            within 1/64 of the matrix's own bytes of the least are timed as
+//            under TIME and the fastest of them wins
 #include <chrono>
 #include <cmath>
 
@@ -39,6 +43,7 @@ extern "C" int xab_select(xab_ctx *ctx, const xab_matrix *A, xab_policy policy, 
     for (int k = 0; k < XAB_NCLASSES; ++k) {
         inf.time_ms[k] = -1.f;
         inf.valid[k] = class_applies(k, A->sym()) ? 1 : 0;
+        inf.bytes[k] = -1;
     }
     inf.chosen = -1;
     const bool sym = A->sym();
@@ -93,8 +98,31 @@ extern "C" int xab_select(xab_ctx *ctx, const xab_matrix *A, xab_policy policy, 
         return xab_fail(ctx, XAB_E_UNSUPPORTED, "no applicable SpMV class");
     }
 
-    if (policy != XAB_TIME) return xab_fail(ctx, XAB_E_SHAPE, "unknown policy %d", (int)policy);
-    // TIME: measure every valid class
+    if (policy != XAB_TIME && policy != XAB_MEMORY) return xab_fail(ctx, XAB_E_SHAPE, "unknown policy %d", (int)policy);
+    // MEMORY: the plan bytes of every valid class first; only the classes
+    // within the slack of the least are timed below
+    bool timed[XAB_NCLASSES];
+    for (int k = 0; k < XAB_NCLASSES; ++k) timed[k] = inf.valid[k] != 0;
+    if (policy == XAB_MEMORY) {
+        int64_t least = -1;
+        for (int k = 0; k < XAB_NCLASSES; ++k) {
+            if (!inf.valid[k]) continue;
+            xab_plan *pl = nullptr;
+            int s = build(k, &pl);
+            if (s == XAB_E_UNSUPPORTED) {
+                inf.valid[k] = 0;
+                timed[k] = false;
+                continue;
+            }
+            if (s != XAB_OK) return s;
+            inf.bytes[k] = xab_plan_bytes(pl);
+            xab_plan_destroy(pl);
+            if (least < 0 || inf.bytes[k] < least) least = inf.bytes[k];
+        }
+        const int64_t own = 4 * ((int64_t)A->n + 1) + A->nnz * (4 + (A->has64 ? 8 : 4));
+        for (int k = 0; k < XAB_NCLASSES; ++k) timed[k] = inf.valid[k] && inf.bytes[k] <= least + own / 64;
+    }
+    // TIME: measure every valid class (MEMORY: the classes kept above)
     const bool f64 = A->has64;
     const size_t es = f64 ? 8 : 4;
     const int64_t nx = A->ncols, ny = A->n;
@@ -110,7 +138,7 @@ extern "C" int xab_select(xab_ctx *ctx, const xab_matrix *A, xab_policy policy, 
     xab_plan *best_plan = nullptr;
     int best = -1, status = XAB_OK;
     for (int k = 0; k < XAB_NCLASSES && status == XAB_OK; ++k) {
-        if (!inf.valid[k]) continue;
+        if (!timed[k]) continue;
         xab_plan *pl = nullptr;
         int s = build(k, &pl);
         if (s == XAB_E_UNSUPPORTED) {
@@ -121,6 +149,7 @@ extern "C" int xab_select(xab_ctx *ctx, const xab_matrix *A, xab_policy policy, 
             status = s;
             break;
         }
+        inf.bytes[k] = xab_plan_bytes(pl);
         s = xab_spmv_dispatch(ctx, pl, x, dt, y, dt, dt);  // warm-up
         float tmin = INFINITY;
         for (int r = 0; r < 4 && s == XAB_OK; ++r) {

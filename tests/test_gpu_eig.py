@@ -199,6 +199,23 @@ def test_restart_tuning_extremes(ctx):
     assert e.value.status == -2
 
 
+def test_memory_policy_keeps_basis_size():
+    """On a context whose policy is MEMORY the rule that grows m after
+    every cycle (threshold infinity) leaves it at its start, for Lanczos and
+    Arnoldi."""
+    cm = xab.Context(0, policy=xab.MEMORY)
+    n = 400
+    A = lap1d(n)
+    v0 = gen.uniform_vec(n, 1)
+    ev, X, info, st = run(cm, A, 3, 3, 12, v0, restart_step=5, m_max=30, mm_ratio=np.inf, window=3, maxiter=300)
+    assert st in (0, 1) and info["m_final"] == 12
+    M = cm.matrix_from_csr(A)
+    P = cm.plan_class(M, 3)
+    ev, X, info, st = cm.arnoldi(P, dev(v0), nev=3, m=12, which=xab.EIG_LARGEST, restart_step=5, m_max=30,
+                                 mm_ratio=np.inf, window=3, maxiter=300)
+    assert st in (0, 1) and info["m_final"] == 12
+
+
 # --------------------------------------------------------------- Arnoldi
 def from_dense(D):
     n = D.shape[0]

@@ -226,3 +226,57 @@ def test_mlp_training_vs_oracle_and_determinism(ctx, tmp_path):
     ctx.selector_load(path)
     p3, mu3, sd3 = ctx.selector_get()
     assert np.array_equal(p3, p1) and np.array_equal(mu3, mu) and np.array_equal(sd3, sd)
+
+
+# ---------------------------------------------------------- MEMORY policy
+COPY_CLASSES = (12, 13, 14)  # XCB, SELL and BCSR hold a re-laid-out copy of the matrix
+
+
+@pytest.mark.parametrize("name", sorted(MATS))
+def test_select_memory_least_bytes(ctx, name):
+    """MEMORY: every valid class reports its plan's bytes; only the classes
+    within 1/64 of the matrix's own bytes of the least are timed, and the
+    fastest of them is chosen.  Copies of the matrix are never chosen; on
+    symmetric matrices (where S3 keeps a flagged column copy) the atomic
+    symmetric class wins."""
+    A = MATS[name]()
+    M = ctx.matrix_from_csr(A)
+    P, info = ctx.select(M, xab.MEMORY)
+    valid = [k for k in range(K) if info.valid[k]]
+    by = {k: info.bytes[k] for k in valid}
+    assert all(b >= 0 for b in by.values())
+    own = 4 * (A.n + 1) + A.nnz * 12
+    least = min(by.values())
+    keep = [k for k in valid if by[k] <= least + own // 64]
+    assert [k for k in valid if info.time_ms[k] >= 0] == keep
+    assert info.chosen == min(keep, key=lambda k: (info.time_ms[k], k))
+    assert P.bytes == by[info.chosen]
+    for k in COPY_CLASSES:
+        if k in by:
+            # XCB and SELL copy every column index and value; BCSR stores
+            # 16 values for every block of the oracle's layout
+            floor = 128 * len(oracle.plan_bcsr(A, 4)["bci"]) if k == 14 else 12 * A.nnz
+            assert by[k] >= floor and k not in keep
+    if A.sym_lower:
+        assert by[10] >= 4 * A.nnz and by[11] >= 4 * A.nnz
+        assert info.chosen == 9
+    x = gen.uniform_vec(A.n, 1)
+    y = ctx.spmv(P, torch.from_numpy(x).cuda()).cpu().numpy()
+    yo, s = oracle.spmv(A, x)
+    assert np.all(np.abs(y - yo) <= 1e-12 * s)
+
+
+def test_plan_bytes_closed_forms(ctx):
+    """Plan bytes against the arrays each layout needs: the row-split plan
+    holds nothing; the nnz-split plan exactly its P + 1 row boundaries; XCB
+    at least the blocked copy of every column index and value; SELL at least
+    its padded copy (the oracle's layout)."""
+    A = gen.powerlaw(20_000, seed=3)
+    M = ctx.matrix_from_csr(A)
+    assert ctx.plan_class(M, 0).bytes == 0
+    Pn = ctx.plan_class(M, 3)
+    b = Pn.array(0)
+    assert Pn.bytes == 4 * b.size
+    assert ctx.plan_class(M, 12).bytes >= 12 * A.nnz
+    S = oracle.plan_sell(A, 64, 1024)
+    assert ctx.plan_class(M, 13).bytes >= 12 * int(S["cptr"][-1])

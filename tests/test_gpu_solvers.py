@@ -404,3 +404,23 @@ def test_gmres_accuracy_policy(ctx):
                            ortho=xab.ORTHO_POLICY)
     assert st == 1 and ref["status"] == 1
     assert inf["faults"] >= 1 and ref["faults"] >= 1 and inf["ortho"] == xab.ORTHO_DGKS
+
+
+def test_memory_policy_keeps_restart_length():
+    """On a context whose policy is MEMORY the MM-ratio rule does not grow
+    the basis: GMRES(4) on the 32x32 Laplacian with the rule of the tuning
+    test above (which grows m to 28 and needs 240 steps) stays at m = 4 and
+    takes about the oracle's fixed GMRES(4) count (1,256 steps)."""
+    cm = xab.Context(0, policy=xab.MEMORY)
+    A = gen.laplacian2d(32)
+    b = np.ones(A.n)
+    ref = oracle.gmres(A, b, m=4, tol=1e-10, maxiter=5000)
+    assert ref["status"] == 0
+    M = cm.matrix_from_csr(A)
+    P = cm.plan_class(M, 5)
+    x, inf, st = cm.gmres(P, dev(b), m=4, tol=1e-10, maxiter=5000, precond=xab.PRECOND_NONE, restart_step=4,
+                          m_max=40, mm_ratio=10.0)
+    assert st == 0 and inf["m_final"] == 4
+    assert abs(inf["iters"] - ref["iters"]) <= 0.2 * ref["iters"]
+    xs = x.cpu().numpy()
+    assert np.linalg.norm(b - oracle.spmv(A, xs)[0]) / np.linalg.norm(b) <= 1e-10
