@@ -170,15 +170,19 @@ __global__ __launch_bounds__(kNT) void k_xcb_combine(XcbArgs a, const uint8_t *_
     }
     __syncthreads();
     if (i >= n) return;
-    AT acc = AT(0);
+    // every block's partial is fetched under its mask bit before any is
+    // added, so the up to 8 loads are in flight together; the sum still
+    // runs in block order over the set bits
+    AT v[kXcds];
 #pragma unroll
     for (int k = 0; k < kXcds; ++k) {
-        if ((m >> k) & 1u) {
-            int64_t off = (int64_t)gbase[(int64_t)k * (G + 1) + g] + pre[k];
-            for (int q = 0; q < w; ++q) off += wcnt[k][q];
-            acc += ((const AT *)a.Y[k])[off];
-        }
+        int64_t off = (int64_t)gbase[(int64_t)k * (G + 1) + g] + pre[k];
+        for (int q = 0; q < w; ++q) off += wcnt[k][q];
+        v[k] = ((m >> k) & 1u) ? ((const AT *)a.Y[k])[off] : AT(0);
     }
+    AT acc = AT(0);
+#pragma unroll
+    for (int k = 0; k < kXcds; ++k) acc = ((m >> k) & 1u) ? acc + v[k] : acc;
     y[i] = (YT)acc;
 }
 
