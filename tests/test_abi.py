@@ -99,3 +99,49 @@ def test_product_path_has_no_oracle_dependency():
     path = _lib_path()
     out = subprocess.run(["nm", "-D", path], capture_output=True, text=True, check=True).stdout
     assert "orc_" not in out
+
+
+STRUCTS = {"Params": "xab_params", "InitOpts": "xab_init_opts", "SelectInfo": "xab_select_info",
+           "TrainOpts": "xab_train_opts", "TrainInfo": "xab_train_info", "KrylovOpts": "xab_krylov_opts",
+           "KrylovInfo": "xab_krylov_info", "EigOpts": "xab_eig_opts", "EigInfo": "xab_eig_info"}
+
+
+def test_header_is_strict_c99(tmp_path):
+    """The boundary header stands alone as ISO C99 (no C++ in it)."""
+    src = tmp_path / "h.c"
+    src.write_text('#include "xab.h"\nint main(void) { return 0; }\n')
+    subprocess.run(["gcc", "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", "-fsyntax-only",
+                    "-I", os.path.join(ROOT, "include"), str(src)], check=True)
+
+
+def test_binding_struct_layouts_match_the_header(tmp_path):
+    """Every ctypes mirror of a header struct has the C compiler's size and
+    the same offset and size for every field (a field added on one side
+    only, or out of order, fails here)."""
+    import ctypes
+
+    import paper_2405_01599_amd as xab
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "xab.h"', "int main(void) {"]
+    for py, c in STRUCTS.items():
+        cls = getattr(xab, py)
+        lines.append(f'    printf("{py} %zu\\n", sizeof({c}));')
+        for f in cls._fields_:
+            name = f[0]
+            lines.append(f'    printf("{py}.{name} %zu %zu\\n", offsetof({c}, {name}), sizeof((({c} *)0)->{name}));')
+    lines += ["    return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    got = {}
+    for line in out:
+        if line.strip():
+            key, *vals = line.split()
+            got[key] = [int(v) for v in vals]
+    for py in STRUCTS:
+        cls = getattr(xab, py)
+        assert got[f"{py}"] == [ctypes.sizeof(cls)], py
+        for f in cls._fields_:
+            d = getattr(cls, f[0])
+            assert got[f"{py}.{f[0]}"] == [d.offset, d.size], (py, f[0])
