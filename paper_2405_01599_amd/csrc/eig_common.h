@@ -21,9 +21,12 @@ constexpr int kRotNT = 256;
 // out[:, c] = sum_{j < mm} V[:, j] * Y[j + c * mm] for c < k (column-major
 // Y; mm <= 64, k <= 63).  A workgroup takes 64 rows: it stages their mm basis entries in LDS
 // (one coalesced 512-byte run per vector), then wave q forms the outputs
-// c = q, q + 4, ... for those rows, lane = row, so every basis entry is read
-// from HBM once and every output written once.
+// c = q, q + 4, ... for those rows, lane = row, all of them at once in
+// registers, so each staged entry is read from LDS once per wave; every
+// basis entry is read from HBM once and every output written once.  Each
+// output is one fma chain over j = 0, 1, ..., mm - 1.
 constexpr int kRotRows = 64;
+constexpr int kRotOut = (kMaxM + kRotNT / kRotRows - 1) / (kRotNT / kRotRows);  // outputs per wave
 __global__ __launch_bounds__(kRotNT) void k_rotate(const double *__restrict__ V, int64_t ldv, int mm,
                                                    const double *__restrict__ Y, int k, double *__restrict__ out,
                                                    int64_t ldo, int64_t n) {
@@ -33,15 +36,33 @@ __global__ __launch_bounds__(kRotNT) void k_rotate(const double *__restrict__ V,
     const int lane = threadIdx.x % kRotRows, q = threadIdx.x / kRotRows;
     const int64_t r = r0 + lane;
     for (int i = threadIdx.x; i < mm * k; i += kRotNT) ys[i] = Y[i];
-    for (int j = q; j < mm; j += kRotNT / kRotRows) vs[j * kRotRows + lane] = r < n ? V[(int64_t)j * ldv + r] : 0.0;
+    constexpr int G = kRotNT / kRotRows;
+    {
+        // every load of this wave's share first, then the LDS stores
+        double st[kRotOut + 1];
+#pragma unroll
+        for (int t = 0; t <= kRotOut; ++t) {
+            const int j = q + t * G;
+            st[t] = (j < mm && r < n) ? V[(int64_t)j * ldv + r] : 0.0;
+        }
+#pragma unroll
+        for (int t = 0; t <= kRotOut; ++t)
+            if (q + t * G < mm) vs[(q + t * G) * kRotRows + lane] = st[t];
+    }
     __syncthreads();
     if (r >= n) return;
-    for (int c = q; c < k; c += kRotNT / kRotRows) {
-        const double *y = ys + c * mm;
-        double a = 0.0;
-        for (int j = 0; j < mm; ++j) a = fma(vs[j * kRotRows + lane], y[j], a);
-        out[(int64_t)c * ldo + r] = a;
+    double acc[kRotOut];
+#pragma unroll
+    for (int t = 0; t < kRotOut; ++t) acc[t] = 0.0;
+    for (int j = 0; j < mm; ++j) {
+        const double v = vs[j * kRotRows + lane];
+#pragma unroll
+        for (int t = 0; t < kRotOut; ++t)
+            if (q + t * G < k) acc[t] = fma(v, ys[(q + t * G) * mm + j], acc[t]);
     }
+#pragma unroll
+    for (int t = 0; t < kRotOut; ++t)
+        if (q + t * G < k) out[(int64_t)(q + t * G) * ldo + r] = acc[t];
 }
 
 // part[block] = sum over its rows of (ax - c1 x1 - c2 x2)^2 (x2 may be null)
