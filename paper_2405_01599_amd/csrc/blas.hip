@@ -31,7 +31,10 @@ struct AddStep {
 
 // FP32 vectors are swept two consecutive rows per thread with 8-byte loads
 // (every vector of the basis and the work vectors start on a 64-element
-// boundary, so row pairs are 8-byte aligned); FP64 vectors one row per thread.
+// boundary, so row pairs are 8-byte aligned); FP64 vectors one row per
+// thread, the basis read with non-temporal loads (it streams through once
+// per sweep, and the work vector then stays cached between the sweeps; the
+// FP32 pairs are faster with ordinary loads).
 template <class T>
 constexpr int rows_per_thread() { return sizeof(T) == 4 ? 2 : 1; }
 template <class T>
@@ -69,7 +72,7 @@ __device__ __forceinline__ void mdot_body(const T *__restrict__ V, int64_t ldv, 
             // one row: every load of the row first, then the products
             double vr[NV];
 #pragma unroll
-            for (int i = 0; i < NV; ++i) vr[i] = i < nv ? (double)V[i * ldv + r] : 0.0;
+            for (int i = 0; i < NV; ++i) vr[i] = i < nv ? (double)ld_nt(V + i * ldv + r) : 0.0;
             const double wr = (double)w[r];
             acc[NV] += wr * wr;
 #pragma unroll
@@ -134,7 +137,7 @@ __global__ __launch_bounds__(kNT) void k_update_norm(const T *__restrict__ V, in
         } else {
             double vr[NV];
 #pragma unroll
-            for (int i = 0; i < NV; ++i) vr[i] = i < nv ? (double)V[i * ldv + r] : 0.0;
+            for (int i = 0; i < NV; ++i) vr[i] = i < nv ? (double)ld_nt(V + i * ldv + r) : 0.0;
             double a = (double)w[r];
 #pragma unroll
             for (int i = 0; i < NV; ++i) a -= hh[i] * vr[i];
@@ -207,7 +210,7 @@ __global__ __launch_bounds__(kNT) void k_update_mdot(const T *__restrict__ Vu, i
         double a = (double)w[r];
 #pragma unroll
         for (int i = 0; i < NV; ++i) {
-            vr[i] = i < nvu ? (double)Vu[i * ldv + r] : 0.0;
+            vr[i] = i < nvu ? (double)ld_nt(Vu + i * ldv + r) : 0.0;
             a -= hh[i] * vr[i];
         }
         const T at = (T)a;
@@ -325,7 +328,7 @@ __global__ void k_combine(const T *__restrict__ V, int64_t ldv, int k, const dou
     int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n) return;
     double a = 0.0;
-    for (int i = 0; i < k; ++i) a += y[i] * (double)V[i * ldv + r];
+    for (int i = 0; i < k; ++i) a += y[i] * (double)ld_nt(V + i * ldv + r);
     a *= scale;
     if (d) a /= (double)d[r];
     x[r] += a;
