@@ -69,8 +69,11 @@ typedef enum { XAB_F64 = 0, XAB_F32 = 1 } xab_dtype;
  * arguments for the least device memory: the selector keeps to the
  * implementations whose plans hold the fewest bytes (see xab_select), and
  * on a context whose default policy is MEMORY the solvers do not grow the
- * restart length (the basis keeps its starting size). */
-typedef enum { XAB_TIME = 0, XAB_STABLE = 1, XAB_LEARNED = 2, XAB_MEMORY = 3 } xab_policy;
+ * restart length (the basis keeps its starting size); ACCURACY selects as
+ * TIME does, and on a context whose default policy is ACCURACY GMRES
+ * follows the accuracy policy's orthogonalisation rule and fault-convergence
+ * retry (XAB_ORTHO_POLICY, section 3.3.2) whatever opts->ortho asks. */
+typedef enum { XAB_TIME = 0, XAB_STABLE = 1, XAB_LEARNED = 2, XAB_MEMORY = 3, XAB_ACCURACY = 4 } xab_policy;
 
 /* SpMV implementations (section 3.2.2 candidate list):
  *   XAB_ROW        row-based decomposition, equal rows per workgroup,
@@ -152,8 +155,9 @@ typedef struct {
 /* Create a context: device, stream, allocator and policy defaults (the
  * paper's initialisation call that sets library defaults, Table 1).
  * opts may be NULL for all defaults.  The environment variable XAB_POLICY
- * (TIME, STABLE, LEARNED or MEMORY) overrides the default policy, as the
- * paper's policy file does.  XAB_E_SHAPE for a policy outside the enum. */
+ * (TIME, STABLE, LEARNED, MEMORY or ACCURACY) overrides the default
+ * policy, as the paper's policy file does.  XAB_E_SHAPE for a policy
+ * outside the enum. */
 int xab_init(xab_ctx **ctx, const xab_init_opts *opts);
 void xab_finalize(xab_ctx *ctx);
 /* Re-point the context at another stream (hipStream_t). */
@@ -226,7 +230,8 @@ typedef struct {
  * valid class, times each over 1 warm-up plus 4 runs (minimum taken) and
  * keeps the fastest (lowest class index on ties); STABLE returns the fixed
  * default (NNZ tile_nnz 2048, or SYM_S3 class 11); LEARNED evaluates the
- * cost model on the matrix features; MEMORY sets every valid class up once
+ * cost model on the matrix features; ACCURACY chooses as TIME does;
+ * MEMORY sets every valid class up once
  * to learn its plan's bytes, then times, as TIME does, only the classes
  * within 1/64 of the matrix's own bytes (row pointers, columns, values) of
  * the least, and keeps the fastest of them.  Timing runs use FP64 (or the

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libxab.so")
 
 F64, F32 = 0, 1
-TIME, STABLE, LEARNED, MEMORY = 0, 1, 2, 3
+TIME, STABLE, LEARNED, MEMORY, ACCURACY = 0, 1, 2, 3, 4
 ROW, NNZ, BSS, SYM_S3, SYM_ATOMIC, XCB, SELL, BCSR = 0, 1, 2, 3, 4, 5, 6, 7
 VARIANT_NAMES = {ROW: "row", NNZ: "nnz", BSS: "bss", SYM_S3: "sym_s3", SYM_ATOMIC: "sym_atomic", XCB: "xcb",
                  SELL: "sell", BCSR: "bcsr"}

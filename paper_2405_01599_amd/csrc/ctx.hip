@@ -74,7 +74,7 @@ int xab_init(xab_ctx **out, const xab_init_opts *opts) {
         ctx->free_fn = opts->free;
         ctx->user = opts->user;
         ctx->stream = (hipStream_t)opts->stream;
-        if (opts->policy < XAB_TIME || opts->policy > XAB_MEMORY) {
+        if (opts->policy < XAB_TIME || opts->policy > XAB_ACCURACY) {
             delete ctx;
             return XAB_E_SHAPE;
         }
@@ -102,6 +102,7 @@ int xab_init(xab_ctx **out, const xab_init_opts *opts) {
         else if (!strcmp(pol, "STABLE")) ctx->policy = XAB_STABLE;
         else if (!strcmp(pol, "LEARNED")) ctx->policy = XAB_LEARNED;
         else if (!strcmp(pol, "MEMORY")) ctx->policy = XAB_MEMORY;
+        else if (!strcmp(pol, "ACCURACY")) ctx->policy = XAB_ACCURACY;
     }
     *out = ctx;
     return XAB_OK;

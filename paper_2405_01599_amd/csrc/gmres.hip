@@ -239,7 +239,8 @@ extern "C" int xab_gmres(xab_ctx *ctx, const xab_plan *pl, const double *d_b, do
     const int mcap = tune ? opts->m_max : m0;  // basis capacity
     int m = m0;                                // restart length of the next cycle
     if (opts->ortho < XAB_ORTHO_DGKS || opts->ortho > XAB_ORTHO_POLICY) return xab_fail(ctx, XAB_E_SHAPE, "ortho");
-    const bool policy = opts->ortho == XAB_ORTHO_POLICY;
+    // on an ACCURACY context the accuracy policy's rule replaces the choice
+    const bool policy = opts->ortho == XAB_ORTHO_POLICY || ctx->policy == XAB_ACCURACY;
     // the policy's rule applies to the requirement of the solve being
     // orthogonalised: the FP64 solve's tol, or in IR mode the inner tolerance
     const double req = opts->mode == XAB_MODE_IR ? (opts->inner_tol > 0 ? opts->inner_tol : 1e-6) : opts->tol;

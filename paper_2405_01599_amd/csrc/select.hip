@@ -5,6 +5,8 @@
 //   STABLE   no tuning: a fixed default (section 2.3, policy STABLE)
 //   LEARNED  the cost model predicts every class from the matrix features;
 //            the best predicted class that can be set up wins
+//   ACCURACY as TIME (the implementation changes the product only by
+//            rounding; the policy acts in the solvers)
 //   MEMORY   the least device memory (section 2.3, policy MEMORY): every
 //            valid class is set up once to learn its plan's bytes; those
 //            within 1/64 of the matrix's own bytes of the least are timed as
@@ -98,6 +100,9 @@ extern "C" int xab_select(xab_ctx *ctx, const xab_matrix *A, xab_policy policy, 
         return xab_fail(ctx, XAB_E_UNSUPPORTED, "no applicable SpMV class");
     }
 
+    // ACCURACY: the SpMV implementation does not change what is computed
+    // beyond rounding, so it is chosen as under TIME
+    if (policy == XAB_ACCURACY) policy = XAB_TIME;
     if (policy != XAB_TIME && policy != XAB_MEMORY) return xab_fail(ctx, XAB_E_SHAPE, "unknown policy %d", (int)policy);
     // MEMORY: the plan bytes of every valid class first; only the classes
     // within the slack of the least are timed below

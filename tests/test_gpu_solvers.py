@@ -424,3 +424,29 @@ def test_memory_policy_keeps_restart_length():
     assert abs(inf["iters"] - ref["iters"]) <= 0.2 * ref["iters"]
     xs = x.cpu().numpy()
     assert np.linalg.norm(b - oracle.spmv(A, xs)[0]) / np.linalg.norm(b) <= 1e-10
+
+
+def test_accuracy_policy_context(ctx):
+    """On a context whose policy is ACCURACY, GMRES follows the accuracy
+    policy whatever ortho asks: the same solution bit for bit, the same
+    steps and the same method as an explicit ORTHO_POLICY solve on a TIME
+    context (MGS at 1e-10; at 1e-15 faults and the switch to DGKS); the
+    selector then chooses as TIME does."""
+    ca = xab.Context(0, policy=xab.ACCURACY)
+    A = gen.laplacian2d(32)
+    b = np.ones(A.n)
+    Pt = ctx.plan_class(ctx.matrix_from_csr(A), 5)
+    Ma = ca.matrix_from_csr(A)
+    Pa = ca.plan_class(Ma, 5)
+    for tol, maxiter in ((1e-10, 1500), (1e-15, 600)):
+        xt, it, st_t = ctx.gmres(Pt, dev(b), m=30, tol=tol, maxiter=maxiter, precond=xab.PRECOND_NONE,
+                                 ortho=xab.ORTHO_POLICY)
+        xa, ia, st_a = ca.gmres(Pa, dev(b), m=30, tol=tol, maxiter=maxiter, precond=xab.PRECOND_NONE,
+                                ortho=xab.ORTHO_CGS)
+        assert st_a == st_t and ia["iters"] == it["iters"] and ia["ortho"] == it["ortho"]
+        assert ia["faults"] == it["faults"]
+        assert torch.equal(xa, xt)
+    P, info = ca.select(Ma, xab.ACCURACY)
+    valid = [k for k in range(xab.NCLASSES) if info.valid[k]]
+    assert all(info.time_ms[k] >= 0 for k in valid)
+    assert info.chosen == min(valid, key=lambda k: (info.time_ms[k], k))
