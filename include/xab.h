@@ -72,7 +72,8 @@ typedef enum { XAB_F64 = 0, XAB_F32 = 1 } xab_dtype;
  * restart length (the basis keeps its starting size); ACCURACY selects as
  * TIME does, and on a context whose default policy is ACCURACY GMRES
  * follows the accuracy policy's orthogonalisation rule and fault-convergence
- * retry (XAB_ORTHO_POLICY, section 3.3.2) whatever opts->ortho asks. */
+ * retry (XAB_ORTHO_POLICY, section 3.3.2) whatever opts->ortho asks, and
+ * the batched BiCGStab reruns systems whose true residual misses tol. */
 typedef enum { XAB_TIME = 0, XAB_STABLE = 1, XAB_LEARNED = 2, XAB_MEMORY = 3, XAB_ACCURACY = 4 } xab_policy;
 
 /* SpMV implementations (section 3.2.2 candidate list):
@@ -467,10 +468,15 @@ int xab_batch_layout(const xab_batch *batch);
 int xab_batch_spmv(xab_ctx *ctx, const xab_batch *batch, const void *d_x, void *d_y);
 /* BiCGStab (section 2.2, standard van der Vorst form) on every system at
  * once; each system stops when its own recurrence residual meets tol and
- * is masked from then on.  d_b, d_x in the batch's value precision; d_x
- * holds x0.  h_info[nsys] receives per-system results (may be NULL);
- * *all receives the aggregate.  One iteration over all systems is captured
- * as a HIP graph and replayed when opts->graph != 0.  Synchronous. */
+ * is masked from then on.  Every system's true residual is recomputed at
+ * the end (true_relres).  On a context whose policy is ACCURACY (section
+ * 3.3.2) a system whose recurrence met its threshold while the true
+ * residual misses tol runs again from its x with the threshold narrowed
+ * tenfold (at most 8 times, within maxiter); h_info[k].faults counts the
+ * narrowings.  d_b, d_x in the batch's value precision; d_x holds x0.
+ * h_info[nsys] receives per-system results (may be NULL); *all receives
+ * the aggregate.  One iteration over all systems is captured as a HIP graph
+ * and replayed when opts->graph != 0.  Synchronous. */
 int xab_bicgstab(xab_ctx *ctx, const xab_batch *batch, const void *d_b, void *d_x, const xab_krylov_opts *opts,
                  xab_krylov_info *h_info, xab_krylov_info *all);
 

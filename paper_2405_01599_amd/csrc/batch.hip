@@ -28,6 +28,7 @@ constexpr int kSegRows = 1024; // rows of one system per workgroup of the BiCGSt
 constexpr int kVT = 256;      // threads of the BiCGStab row kernels
 constexpr int kFT = 256;      // threads of the per-system kernels (one wave per system)
 constexpr int kSellSigma = 1024; // sorting window of the sliced ELLPACK copy
+constexpr int kMaxNarrow = 8;    // accuracy policy: tenfold narrowings of a system's threshold at most
 
 
 // Batched SpMV over the concatenation, in segmented-scan tiles of
@@ -153,15 +154,19 @@ struct SysState {
 };
 
 // ||b||, r = b - A x0 (A x0 given in ax), rhat = r, p = v = 0, rho = <rhat, r>,
-// scalars reset (beta = 0 makes the first direction p = r)
+// scalars reset (beta = 0 makes the first direction p = r).  With `redo`,
+// only the marked systems restart (from their current x, keeping their
+// iteration counts): the accuracy policy's second run.
 template <class T>
 __global__ __launch_bounds__(kBiNT) void k_bi_init(const int64_t *__restrict__ row_off, const T *__restrict__ bvec,
                                                  const T *__restrict__ ax, T *__restrict__ r, T *__restrict__ rh,
                                                  T *__restrict__ p, T *__restrict__ v, SysState *__restrict__ st,
-                                                 int *__restrict__ active, int *__restrict__ early, double tol,
+                                                 int *__restrict__ active, int *__restrict__ early,
+                                                 const double *__restrict__ tolv, const int *__restrict__ redo,
                                                  int *__restrict__ n_active) {
     __shared__ double sh[kBiNT / xab::kWave];
     const int k = blockIdx.x;
+    if (redo && !redo[k]) return;
     const int64_t r0 = row_off[k], r1 = row_off[k + 1];
     double bb = 0.0, rr = 0.0;
     for (int64_t i = r0 + threadIdx.x; i < r1; i += kBiNT) {
@@ -184,8 +189,8 @@ __global__ __launch_bounds__(kBiNT) void k_bi_init(const int64_t *__restrict__ r
         s.beta = 0.0;
         s.bnorm = bb > 0.0 ? sqrt(bb) : 1.0;
         s.res = sqrt(rr) / s.bnorm;
-        s.iters = 0;
-        s.status = s.res <= tol ? 0 : (rr == 0.0 ? 2 : 1);
+        s.iters = redo ? st[k].iters : 0;
+        s.status = s.res <= tolv[k] ? 0 : (rr == 0.0 ? 2 : 1);
         st[k] = s;
         active[k] = s.status == 1;
         early[k] = 0;
@@ -403,17 +408,17 @@ __global__ __launch_bounds__(kFT) void k_bf_alpha(const int32_t *__restrict__ se
     }
 }
 
-// ||s|| / ||b|| <= tol: the system stops after x += alpha phat
+// ||s|| / ||b|| <= the system's threshold: it stops after x += alpha phat
 __global__ __launch_bounds__(kFT) void k_bf_s(const int32_t *__restrict__ seg_off, int ns,
                                             const double *__restrict__ part, SysState *__restrict__ st,
-                                            int *__restrict__ active, int *__restrict__ early, double tol,
-                                            int *__restrict__ n_active) {
+                                            int *__restrict__ active, int *__restrict__ early,
+                                            const double *__restrict__ tolv, int *__restrict__ n_active) {
     const int k = wave_system();
     if (k >= ns || !active[k]) return;
     const double ss = seg_total(part, 0, seg_off[k], seg_off[k + 1]);
     if (threadIdx.x % xab::kWave) return;
     const double res = sqrt(ss) / st[k].bnorm;
-    if (res <= tol) {
+    if (res <= tolv[k]) {
         SysState q = st[k];
         q.res = res;
         q.iters += 1;
@@ -442,8 +447,9 @@ __global__ __launch_bounds__(kFT) void k_bf_omega(const int32_t *__restrict__ se
 // beta = (rho_next / rho) (alpha / omega) for the next direction
 __global__ __launch_bounds__(kFT) void k_bf_x(const int32_t *__restrict__ seg_off, int ns,
                                             const double *__restrict__ part, SysState *__restrict__ st,
-                                            int *__restrict__ active, int *__restrict__ early, double tol,
-                                            int64_t maxiter, int *__restrict__ n_active, int *__restrict__ lcount) {
+                                            int *__restrict__ active, int *__restrict__ early,
+                                            const double *__restrict__ tolv, int64_t maxiter,
+                                            int *__restrict__ n_active, int *__restrict__ lcount) {
     if (blockIdx.x == 0 && threadIdx.x < 2) lcount[threadIdx.x] = 0;  // lists of the next iteration
     const int k = wave_system();
     if (k >= ns) return;
@@ -460,7 +466,7 @@ __global__ __launch_bounds__(kFT) void k_bf_x(const int32_t *__restrict__ seg_of
     q.iters += 1;
     q.res = sqrt(rr) / q.bnorm;
     bool stop = true;
-    if (q.res <= tol) {
+    if (q.res <= tolv[k]) {
         q.status = 0;
     } else if (q.omega == 0.0) {
         q.status = 2;
@@ -585,7 +591,9 @@ int bicgstab_t(xab_ctx *ctx, const xab_batch *B, const T *bvec, T *x, const xab_
     size_t off_lseg = off_part + al(sizeof(double) * 2 * (size_t)std::max<int64_t>(B->nseg, 1));
     size_t off_lwin = off_lseg + al(sizeof(int32_t) * (size_t)std::max<int64_t>(B->nseg, 1));
     size_t off_lcnt = off_lwin + al(sizeof(int32_t) * (size_t)std::max<int64_t>(nwin, 1));
-    size_t total = off_lcnt + 256;
+    size_t off_tolv = off_lcnt + 256;
+    size_t off_redo = off_tolv + al(sizeof(double) * ns);
+    size_t total = off_redo + al(sizeof(int) * ns);
     char *w = (char *)xab_dalloc(ctx, total);
     if (!w) return xab_fail(ctx, XAB_E_NOMEM, "BiCGStab workspace");
     T *r = (T *)w, *rh = (T *)(w + vb), *p = (T *)(w + 2 * vb), *v = (T *)(w + 3 * vb), *ph = (T *)(w + 4 * vb);
@@ -599,6 +607,8 @@ int bicgstab_t(xab_ctx *ctx, const xab_batch *B, const T *bvec, T *x, const xab_
     double *part = (double *)(w + off_part);
     int32_t *seg_list = (int32_t *)(w + off_lseg), *win_list = (int32_t *)(w + off_lwin);
     int *lcount = (int *)(w + off_lcnt);
+    double *tolv = (double *)(w + off_tolv);  // each system's threshold (the accuracy policy narrows it)
+    int *redo = (int *)(w + off_redo);
     hipStream_t st = ctx->stream;
     hipStream_t gs = nullptr;
     hipGraph_t graph = nullptr;
@@ -628,13 +638,17 @@ int bicgstab_t(xab_ctx *ctx, const xab_batch *B, const T *bvec, T *x, const xab_
             hipLaunchKernelGGL((k_diag_b<T>), dim3(grid_for(n * 8, 256)), dim3(256), 0, st, B->rowptr, B->colind,
                                (const T *)B->val, n, (T *)Bm->diag);
     }
+    std::vector<double> htol(ns, tol);
+    std::vector<int> hredo(ns, 0), narrowed(ns, 0);
     hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, st, n_active);
     hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, st, lcount);
     hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, st, lcount + 1);
+    hipError_t e = hipMemcpyAsync(tolv, htol.data(), sizeof(double) * ns, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return cleanup(xab_hip_check(ctx, e, "BiCGStab thresholds"));
     if ((sres = batch_spmv_t<T>(ctx, B, x, ax, nullptr, st)) != XAB_OK) return cleanup(sres);
     hipLaunchKernelGGL((k_bi_init<T>), dim3(ns), dim3(kBiNT), 0, st, B->d_row_off, bvec, ax, r, rh, p, v, stt, active,
-                       early, tol, n_active);
-    hipError_t e = hipGetLastError();
+                       early, tolv, nullptr, n_active);
+    e = hipGetLastError();
     if (e != hipSuccess) return cleanup(xab_hip_check(ctx, e, "BiCGStab init"));
     const T *dd = jac ? (const T *)B->diag : nullptr;
     // one iteration over all systems
@@ -671,7 +685,7 @@ int bicgstab_t(xab_ctx *ctx, const xab_batch *B, const T *bvec, T *x, const xab_
         if (nseg)
             hipLaunchKernelGGL((k_bv_s<T>), dim3(nseg), dim3(kVT), 0, q, seg_list, lcount, ss, so, ro, r, v, s, shv, dd,
                                stt, active, part);
-        hipLaunchKernelGGL(k_bf_s, dim3(nfw), dim3(kFT), 0, q, so, ns, part, stt, active, early, tol, n_active);
+        hipLaunchKernelGGL(k_bf_s, dim3(nfw), dim3(kFT), 0, q, so, ns, part, stt, active, early, tolv, n_active);
         spmv(shv, t, q);
         if (nseg)
             hipLaunchKernelGGL((k_bv_dot<T, true>), dim3(nseg), dim3(kVT), 0, q, seg_list, lcount, ss, so, ro, t, s,
@@ -680,7 +694,7 @@ int bicgstab_t(xab_ctx *ctx, const xab_batch *B, const T *bvec, T *x, const xab_
         if (nseg)
             hipLaunchKernelGGL((k_bv_x<T>), dim3(nseg), dim3(kVT), 0, q, seg_list, lcount, ss, so, ro, s, t, ph, shv, rh,
                                x, r, stt, active, early, part);
-        hipLaunchKernelGGL(k_bf_x, dim3(nfw), dim3(kFT), 0, q, so, ns, part, stt, active, early, tol, maxiter, n_active,
+        hipLaunchKernelGGL(k_bf_x, dim3(nfw), dim3(kFT), 0, q, so, ns, part, stt, active, early, tolv, maxiter, n_active,
                            lcount);
     };
     const int every = o->check_every > 0 ? o->check_every : 8;
@@ -705,34 +719,70 @@ int bicgstab_t(xab_ctx *ctx, const xab_batch *B, const T *bvec, T *x, const xab_
     }
     hipStream_t run = o->graph ? gs : st;
     int64_t done_iters = 0;
-    int h_active = 1;
-    while (done_iters < maxiter) {
-        if (o->graph) e = hipGraphLaunch(exec, gs);
-        else {
-            for (int i = 0; i < every; ++i) enqueue_iter(st);
-            e = hipGetLastError();
+    std::vector<SysState> hs(ns);
+    std::vector<double> hr(ns);
+    for (int pass = 0;; ++pass) {
+        int h_active = 1;
+        while (done_iters < maxiter) {
+            if (o->graph) e = hipGraphLaunch(exec, gs);
+            else {
+                for (int i = 0; i < every; ++i) enqueue_iter(st);
+                e = hipGetLastError();
+            }
+            if (e != hipSuccess) break;
+            done_iters += every;
+            e = hipMemcpyAsync(&h_active, n_active, sizeof(int), hipMemcpyDeviceToHost, run);
+            if (e == hipSuccess) e = hipStreamSynchronize(run);
+            if (e != hipSuccess || h_active <= 0) break;
         }
         if (e != hipSuccess) break;
-        done_iters += every;
-        e = hipMemcpyAsync(&h_active, n_active, sizeof(int), hipMemcpyDeviceToHost, run);
-        if (e == hipSuccess) e = hipStreamSynchronize(run);
-        if (e != hipSuccess || h_active <= 0) break;
+        if (o->graph) {
+            e = hipStreamSynchronize(gs);
+            if (e != hipSuccess) break;
+        }
+        // true residuals
+        if ((sres = batch_spmv_t<T>(ctx, B, x, ax, nullptr, st)) != XAB_OK) {
+            if (ev) (void)hipEventDestroy(ev);
+            return cleanup(sres);
+        }
+        hipLaunchKernelGGL((k_bi_true<T>), dim3(ns), dim3(kBiNT), 0, st, B->d_row_off, bvec, ax, stt, res);
+        e = hipMemcpyAsync(hs.data(), stt, sizeof(SysState) * ns, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(hr.data(), res, sizeof(double) * ns, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) break;
+        // accuracy policy (section 3.3.2): a system whose recurrence met its
+        // threshold while its true residual misses tol runs again from its
+        // current x with the threshold narrowed tenfold, while iterations
+        // remain (at most kMaxNarrow times)
+        if (ctx->policy != XAB_ACCURACY || done_iters >= maxiter) break;
+        int nredo = 0;
+        for (int k = 0; k < ns; ++k) {
+            hredo[k] = hs[k].status == 0 && hr[k] > tol && narrowed[k] < kMaxNarrow;
+            if (hredo[k]) {
+                htol[k] /= 10.0;
+                ++narrowed[k];
+                ++nredo;
+            }
+        }
+        if (!nredo) break;
+        e = hipMemcpyAsync(tolv, htol.data(), sizeof(double) * ns, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(redo, hredo.data(), sizeof(int) * ns, hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) break;
+        // ax = A x is current: the restart starts from the true residual
+        hipLaunchKernelGGL((k_bi_init<T>), dim3(ns), dim3(kBiNT), 0, st, B->d_row_off, bvec, ax, r, rh, p, v, stt,
+                           active, early, tolv, redo, n_active);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = hipStreamSynchronize(st);  // the host vectors are rewritten by the next pass
+        if (e != hipSuccess) break;
+        if (o->graph) {
+            // the graph's stream runs after the host-side work above
+            e = hipEventRecord(ev, st);
+            if (e == hipSuccess) e = hipStreamWaitEvent(gs, ev, 0);
+            if (e != hipSuccess) break;
+        }
     }
     if (ev) (void)hipEventDestroy(ev);
     if (e != hipSuccess) return cleanup(xab_hip_check(ctx, e, "BiCGStab iterations"));
-    if (o->graph) {
-        e = hipStreamSynchronize(gs);
-        if (e != hipSuccess) return cleanup(xab_hip_check(ctx, e, "BiCGStab sync"));
-    }
-    // true residuals
-    if ((sres = batch_spmv_t<T>(ctx, B, x, ax, nullptr, st)) != XAB_OK) return cleanup(sres);
-    hipLaunchKernelGGL((k_bi_true<T>), dim3(ns), dim3(kBiNT), 0, st, B->d_row_off, bvec, ax, stt, res);
-    std::vector<SysState> hs(ns);
-    std::vector<double> hr(ns);
-    e = hipMemcpyAsync(hs.data(), stt, sizeof(SysState) * ns, hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(hr.data(), res, sizeof(double) * ns, hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
-    if (e != hipSuccess) return cleanup(xab_hip_check(ctx, e, "BiCGStab results"));
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     int agg = XAB_OK;
     int64_t maxit = 0;
@@ -749,6 +799,7 @@ int bicgstab_t(xab_ctx *ctx, const xab_batch *B, const T *bvec, T *x, const xab_
             hinfo[k].true_relres = hr[k];
             hinfo[k].seconds = secs;
             hinfo[k].status = sk;
+            hinfo[k].faults = narrowed[k];
         }
     }
     if (all) {

@@ -450,3 +450,37 @@ def test_accuracy_policy_context(ctx):
     valid = [k for k in range(xab.NCLASSES) if info.valid[k]]
     assert all(info.time_ms[k] >= 0 for k in valid)
     assert info.chosen == min(valid, key=lambda k: (info.time_ms[k], k))
+
+
+def test_bicgstab_accuracy_policy(ctx):
+    """FP32 batched BiCGStab at 1e-7 on 64 systems: under TIME some systems
+    stop on their recurrence residual while the true residual misses tol
+    (the fault convergence of the accuracy policy's section).  On an
+    ACCURACY context each such system runs again from its x with a tenfold
+    narrower threshold, so a system that reports convergence meets tol with
+    its true residual; the others report non-convergence.  Where TIME has no
+    fault (FP64 at 1e-10) both contexts give the same solution bit for bit."""
+    B = gen.batch(64, seed=4, nmin=1000, nmax=20000)
+    b = np.ones(B.n)
+    x, per, agg, st = ctx.bicgstab(ctx.batch(B, dtype="f32"), dev(b, torch.float32), tol=1e-7, maxiter=2000)
+    faults = [k for k, p in enumerate(per) if p["status"] == 0 and p["true_relres"] > 1e-7]
+    assert faults
+    ca = xab.Context(0, policy=xab.ACCURACY)
+    xa, pa, agga, sta = ca.bicgstab(ca.batch(B, dtype="f32"), dev(b, torch.float32), tol=1e-7, maxiter=2000)
+    for k, p in enumerate(pa):
+        assert p["status"] in (0, 1)
+        if p["status"] == 0:
+            assert p["true_relres"] <= 1e-7
+    assert all(pa[k]["faults"] >= 1 for k in faults)
+    xs = xa.double().cpu().numpy()
+    for k, p in enumerate(pa):
+        if p["status"] == 0:
+            r0, r1 = int(B.row_off[k]), int(B.row_off[k + 1])
+            rr = b[r0:r1] - oracle.spmv(B.system(k), xs[r0:r1])[0]
+            assert np.linalg.norm(rr) / np.linalg.norm(b[r0:r1]) <= 5e-7
+    Bs = _batch()
+    bs = dev(np.ones(Bs.n))
+    x1, p1, _, s1 = ctx.bicgstab(ctx.batch(Bs), bs, tol=1e-10)
+    x2, p2, _, s2 = ca.bicgstab(ca.batch(Bs), bs, tol=1e-10)
+    assert s1 == s2 == 0 and all(p["true_relres"] <= 1e-10 for p in p1)
+    assert torch.equal(x1, x2) and all(p["faults"] == 0 for p in p2)
