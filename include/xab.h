@@ -395,6 +395,8 @@ typedef struct {
     int32_t status;     /* same as the return value */
     int32_t m_final;    /* m of the last cycle */
     int32_t nret;       /* eigenvalues returned: nev, or nev + 1 when Arnoldi's nev-th is one of a complex pair */
+    int32_t faults;     /* ACCURACY context: convergences the true residuals did not confirm (the threshold
+                           was narrowed tenfold after each) */
 } xab_eig_info;
 
 /* Thick-restart Lanczos (Wu and Simon's restart; the paper names a
@@ -417,8 +419,13 @@ typedef struct {
  * Out: h_evals[nev] (host, wanted end first), d_evecs (device FP64,
  * column-major n x nev, ld = n, orthonormal columns).  XAB_BREAKDOWN when
  * the Krylov space of d_v0 is invariant with dimension below nev;
- * XAB_NOT_CONVERGED / XAB_TIME_LIMIT return the current Ritz pairs.
- * Synchronous. */
+ * XAB_NOT_CONVERGED / XAB_TIME_LIMIT return the current Ritz pairs.  On a
+ * context whose policy is ACCURACY (section 3.3.2) a convergence of the
+ * estimates that the true residuals do not confirm (max_resid > tol)
+ * narrows the threshold tenfold and the run goes on (at most 8 times,
+ * within maxiter and max_time_s); if it cannot be confirmed the call
+ * returns XAB_NOT_CONVERGED (info->faults counts the narrowings; the same
+ * holds for xab_arnoldi).  Synchronous. */
 int xab_lanczos(xab_ctx *ctx, const xab_plan *plan, const double *d_v0, const xab_eig_opts *opts,
                 double *h_evals, double *d_evecs, xab_eig_info *info);
 

@@ -90,7 +90,8 @@ class EigOpts(ctypes.Structure):
 class EigInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int64), ("restarts", ctypes.c_int64), ("nconv", ctypes.c_int32),
                 ("anrm", ctypes.c_double), ("max_resid", ctypes.c_double), ("seconds", ctypes.c_double),
-                ("status", ctypes.c_int32), ("m_final", ctypes.c_int32), ("nret", ctypes.c_int32)]
+                ("status", ctypes.c_int32), ("m_final", ctypes.c_int32), ("nret", ctypes.c_int32),
+                ("faults", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

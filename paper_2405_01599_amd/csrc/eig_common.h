@@ -17,6 +17,7 @@ namespace {
 constexpr double kEta = 0.70710678118654752440;  // DGKS threshold 1/sqrt(2)
 constexpr int kMaxM = 63;                         // basis vectors per cycle (slots of the fused dots)
 constexpr int kRotNT = 256;
+constexpr int kMaxNarrowEig = 8;  // accuracy policy: tenfold narrowings of the threshold at most
 
 // out[:, c] = sum_{j < mm} V[:, j] * Y[j + c * mm] for c < k (column-major
 // Y; mm <= 64, k <= 63).  A workgroup takes 64 rows: it stages their mm basis entries in LDS

@@ -216,6 +216,39 @@ def test_memory_policy_keeps_basis_size():
     assert st in (0, 1) and info["m_final"] == 12
 
 
+def test_accuracy_policy_eigensolvers(ctx):
+    """Near rounding the Ritz estimates can meet tol while the true residuals
+    do not: on the 1D Laplacian (n = 400, the 4 largest, m = 20) Lanczos at
+    1e-13 stops under TIME with true residuals of about 5e-13, Arnoldi at
+    3e-15 with about 7e-15.  On an ACCURACY context each such stop narrows
+    the threshold tenfold and the run goes on; it ends with true residuals
+    within tol or reports no convergence, never with an unconfirmed
+    convergence.  Where TIME's convergence is confirmed (1e-10) both
+    contexts return the same eigenvalues bit for bit and no fault."""
+    n = 400
+    A = lap1d(n)
+    v0 = gen.uniform_vec(n, 1)
+    ca = xab.Context(0, policy=xab.ACCURACY)
+    ev, X, info, st = run(ctx, A, 3, 4, 20, v0, tol=1e-13, maxiter=20000)
+    assert st == 0 and info["max_resid"] > 1e-13 and info["faults"] == 0
+    ev2, X2, info2, st2 = run(ca, A, 3, 4, 20, v0, tol=1e-13, maxiter=20000)
+    assert info2["faults"] >= 1
+    assert (st2 == 0 and info2["max_resid"] <= 1e-13) or st2 == 1
+    for c, want_fault in ((ctx, False), (ca, True)):
+        M = c.matrix_from_csr(A)
+        P = c.plan_class(M, 3)
+        e, Xa, inf, s = c.arnoldi(P, dev(v0), nev=4, m=20, tol=3e-15, which=xab.EIG_LARGEST, maxiter=20000)
+        if want_fault:
+            assert inf["faults"] >= 1
+            assert (s == 0 and inf["max_resid"] <= 3e-15) or s == 1
+        else:
+            assert s == 0 and inf["max_resid"] > 3e-15 and inf["faults"] == 0
+    ev, X, info, st = run(ctx, A, 3, 4, 20, v0, tol=1e-10)
+    ev2, X2, info2, st2 = run(ca, A, 3, 4, 20, v0, tol=1e-10)
+    assert st == st2 == 0 and info2["faults"] == 0 and info["max_resid"] <= 1e-10
+    assert np.array_equal(ev, ev2)
+
+
 # --------------------------------------------------------------- Arnoldi
 def from_dense(D):
     n = D.shape[0]
