@@ -204,7 +204,8 @@ __global__ __launch_bounds__(kBiNT) void k_bi_init(const int64_t *__restrict__ r
 // The counts are cleared by the last kernel of the previous iteration.
 // Systems that stop during the iteration stay listed; the kernels test
 // their masks.
-__device__ __forceinline__ void wave_append(bool pred, int32_t item, int32_t *__restrict__ list, int *__restrict__ count) {
+__device__ __forceinline__ void wave_append(bool pred, int32_t item, int32_t *__restrict__ list,
+                                            int *__restrict__ count) {
     const unsigned long long bal = __ballot(pred);
     if (bal == 0) return;  // wave-uniform
     const int lane = threadIdx.x % xab::kWave, leader = __ffsll((long long)bal) - 1;
@@ -694,8 +695,8 @@ int bicgstab_t(xab_ctx *ctx, const xab_batch *B, const T *bvec, T *x, const xab_
         if (nseg)
             hipLaunchKernelGGL((k_bv_x<T>), dim3(nseg), dim3(kVT), 0, q, seg_list, lcount, ss, so, ro, s, t, ph, shv, rh,
                                x, r, stt, active, early, part);
-        hipLaunchKernelGGL(k_bf_x, dim3(nfw), dim3(kFT), 0, q, so, ns, part, stt, active, early, tolv, maxiter, n_active,
-                           lcount);
+        hipLaunchKernelGGL(k_bf_x, dim3(nfw), dim3(kFT), 0, q, so, ns, part, stt, active, early, tolv, maxiter,
+                           n_active, lcount);
     };
     const int every = o->check_every > 0 ? o->check_every : 8;
     hipEvent_t ev = nullptr;
