@@ -263,8 +263,17 @@ __global__ __launch_bounds__(kNT) void k_reduce_parts(const double *__restrict__
     __shared__ double sh[kNT];
     if (gate && *gate == 0) return;
     const int i = blockIdx.x;
+    // the thread's partials in ascending b, their loads issued 8 at a time
     double a = 0.0;
-    for (int b = threadIdx.x; b < nb; b += kNT) a += part[(int64_t)b * ldp + i];
+    int b = threadIdx.x;
+    for (; b + 7 * kNT < nb; b += 8 * kNT) {
+        double t[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) t[u] = part[(int64_t)(b + u * kNT) * ldp + i];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a += t[u];
+    }
+    for (; b < nb; b += kNT) a += part[(int64_t)b * ldp + i];
     sh[threadIdx.x] = a;
     __syncthreads();
 #pragma unroll
