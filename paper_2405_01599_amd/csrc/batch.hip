@@ -9,7 +9,9 @@
 // once in a HIP graph and replayed.  Per-system scalars live on the device;
 // a system that converges (or breaks down) is masked from then on and drops
 // out of the next iteration's lists (segmented-scan tiles whose systems are
-// all inactive skip their work).
+// all inactive skip their work).  Each system has its own threshold: under
+// the accuracy policy a system whose true residual misses tol at the end
+// restarts from its x with a tenfold narrower one.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
