@@ -480,7 +480,11 @@ int xab_batch_spmv(xab_ctx *ctx, const xab_batch *batch, const void *d_x, void *
  * 3.3.2) a system whose recurrence met its threshold while the true
  * residual misses tol runs again from its x with the threshold narrowed
  * tenfold (at most 8 times, within maxiter); h_info[k].faults counts the
- * narrowings.  d_b, d_x in the batch's value precision; d_x holds x0.
+ * narrowings, and a system whose true residual still misses tol when the
+ * narrowings or the iterations run out reports XAB_NOT_CONVERGED.  On other
+ * contexts a system's status is its recurrence's outcome: compare
+ * true_relres with tol to confirm it.  d_b, d_x in the batch's value
+ * precision; d_x holds x0.
  * h_info[nsys] receives per-system results (may be NULL); *all receives
  * the aggregate.  One iteration over all systems is captured as a HIP graph
  * and replayed when opts->graph != 0.  Synchronous. */

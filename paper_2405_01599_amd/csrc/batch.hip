@@ -792,6 +792,9 @@ int bicgstab_t(xab_ctx *ctx, const xab_batch *B, const T *bvec, T *x, const xab_
     double worst = 0.0;
     for (int k = 0; k < ns; ++k) {
         int sk = hs[k].status == 0 ? XAB_OK : (hs[k].status == 2 ? XAB_BREAKDOWN : XAB_NOT_CONVERGED);
+        // accuracy policy: a convergence the true residual does not confirm
+        // (narrowing cap or iteration limit reached) is not a convergence
+        if (sk == XAB_OK && ctx->policy == XAB_ACCURACY && !(hr[k] <= tol)) sk = XAB_NOT_CONVERGED;
         if (sk == XAB_BREAKDOWN) agg = XAB_BREAKDOWN;
         else if (sk == XAB_NOT_CONVERGED && agg == XAB_OK) agg = XAB_NOT_CONVERGED;
         maxit = std::max<int64_t>(maxit, hs[k].iters);

@@ -250,6 +250,8 @@ extern "C" int xab_gmres(xab_ctx *ctx, const xab_plan *pl, const double *d_b, do
     if (opts->mode != XAB_MODE_FP64 && opts->mode != XAB_MODE_IR) return xab_fail(ctx, XAB_E_SHAPE, "mode");
     if (!A->has64) return xab_fail(ctx, XAB_E_DTYPE, "GMRES needs FP64 values for the residual");
     if (opts->mode == XAB_MODE_IR && !A->has32) return xab_fail(ctx, XAB_E_DTYPE, "IR mode needs FP32 values");
+    if (opts->mode == XAB_MODE_IR && pl->variant == XAB_SYM_ATOMIC)
+        return xab_fail(ctx, XAB_E_DTYPE, "IR mode's inner product (FP32 y, FP64 accumulation) has no atomic form");
     if (d_b == d_x) return xab_fail(ctx, XAB_E_ALIAS, "b and x alias");
     const int64_t n = A->n;
     xab_krylov_info loc{};

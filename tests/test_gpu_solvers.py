@@ -95,10 +95,16 @@ def test_gmres_powerlaw_vs_oracle(ctx, k, mode):
 @pytest.mark.parametrize("k", [9, 10, 11])
 @pytest.mark.parametrize("mode", [xab.MODE_FP64, xab.MODE_IR])
 def test_gmres_sym_stencil(ctx, k, mode):
-    if k == 9 and mode == xab.MODE_IR:
-        pytest.skip("the atomic baseline accumulates in its output type: no FP32-out/FP64-acc form")
     A = gen.stencil27(24, lower=True)
     b = np.ones(A.n)
+    if k == 9 and mode == xab.MODE_IR:
+        # the atomic baseline accumulates in its output type: it has no
+        # FP32-out / FP64-accumulation form, and the library says so
+        M, P = _setup(ctx, A, k)
+        with pytest.raises(xab.XabError) as ei:
+            ctx.gmres(P, dev(b), m=30, tol=1e-10, mode=mode, precond=xab.PRECOND_JACOBI)
+        assert ei.value.status == -3
+        return
     rp, ci, v = oracle.sym_expand(A)
     F = gen.CSR(A.n, A.n, rp, ci, v)
     ref = oracle.gmres(F, b, m=30, tol=1e-10, precond=1)
@@ -484,3 +490,24 @@ def test_bicgstab_accuracy_policy(ctx):
     x2, p2, _, s2 = ca.bicgstab(ca.batch(Bs), bs, tol=1e-10)
     assert s1 == s2 == 0 and all(p["true_relres"] <= 1e-10 for p in p1)
     assert torch.equal(x1, x2) and all(p["faults"] == 0 for p in p2)
+
+
+@pytest.mark.parametrize("maxiter", [40, 4000])
+def test_bicgstab_accuracy_policy_unconfirmed(ctx, maxiter):
+    """ACCURACY context, FP32 values and a tolerance FP32 cannot reach with
+    its true residual (1e-10): the narrowed reruns run out (after 8
+    narrowings, or at the iteration limit), and every system whose true
+    residual misses tol reports non-convergence, as does the aggregate."""
+    B = gen.batch(16, seed=4, nmin=1000, nmax=5000)
+    b = np.ones(B.n)
+    ca = xab.Context(0, policy=xab.ACCURACY)
+    xa, pa, agg, st = ca.bicgstab(ca.batch(B, dtype="f32"), dev(b, torch.float32), tol=1e-10, maxiter=maxiter)
+    missed = [k for k, p in enumerate(pa) if p["true_relres"] > 1e-10]
+    assert missed
+    for k, p in enumerate(pa):
+        assert p["status"] in (0, 1, 2)
+        if p["true_relres"] > 1e-10:
+            assert p["status"] != 0
+    assert st != 0 and agg["status"] == st
+    if maxiter == 4000:
+        assert any(pa[k]["faults"] == 8 for k in missed)
