@@ -211,6 +211,28 @@ int xab_spmv_csr(xab_ctx *ctx, const xab_plan *plan, const void *d_x, xab_dtype 
 int xab_spmv_sym(xab_ctx *ctx, const xab_plan *plan, const void *d_x, xab_dtype xt, void *d_y, xab_dtype yt,
                  xab_dtype acc);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): y = A x
+ * for a general CSR matrix given by its arrays, with no matrix handle, no
+ * plan and no device allocation.  It runs the branchless segmented scan
+ * (XAB_BSS, 256 * j_per_lane entries per workgroup, j_per_lane a power of
+ * two in [1, 32]) and gives the result of xab_spmv_csr with a BSS plan of
+ * the same j_per_lane, bit for bit.  Its tile descriptors and carries live
+ * in a library-owned device buffer of XAB_NOALLOC_SCRATCH_BYTES on each GPU
+ * (set up by xab_init, held until the process ends), which limits the
+ * matrix to ceil(nnz / (256 * j_per_lane)) <= XAB_NOALLOC_MAX_TILES tiles
+ * (XAB_E_SHAPE beyond).  All calls on one GPU share that buffer: calls
+ * that overlap in time on one GPU (other streams or contexts) race, so
+ * order them on one stream.  The input is trusted (no validation pass):
+ * rowptr[nrows + 1] monotone from 0 to nnz, 0 <= colind < ncols.  Value
+ * precision = xt; precisions, alignment and aliasing as for xab_spmv_csr.
+ * Asynchronous. */
+#define XAB_NOALLOC_SCRATCH_BYTES (8u << 20)
+#define XAB_NOALLOC_MAX_TILES 262000
+int xab_spmv_csr_noalloc(xab_ctx *ctx, int32_t nrows, int32_t ncols, int64_t nnz, const int32_t *d_rowptr,
+                         const int32_t *d_colind, const void *d_val, int32_t j_per_lane, const void *d_x,
+                         xab_dtype xt, void *d_y, xab_dtype yt, xab_dtype acc);
+
 /* Average device time of one SpMV with this plan: `warmup` untimed calls,
  * then `reps` calls between two events on the context stream.
  * Synchronous.  Writes milliseconds per call to *ms. */

@@ -28,6 +28,7 @@ MODE_FP64, MODE_IR = 0, 1
 PRECOND_NONE, PRECOND_JACOBI = 0, 1
 ORTHO_DGKS, ORTHO_CGS, ORTHO_MGS, ORTHO_BCGS, ORTHO_POLICY = 0, 1, 2, 3, 4
 EIG_LARGEST, EIG_SMALLEST, EIG_MAGNITUDE = 0, 1, 2
+NOALLOC_MAX_TILES = 262000  # XAB_NOALLOC_MAX_TILES
 
 STATUS = {0: "ok", -1: "null", -2: "shape", -3: "dtype", -4: "struct", -5: "alias", -6: "unsupported",
           -7: "nomem", -8: "device", -9: "align", 1: "not_converged", 2: "breakdown", 3: "time_limit"}
@@ -119,6 +120,8 @@ SIGNATURES = {
     "xab_plan_bytes": (ctypes.c_int64, [_P]),
     "xab_spmv_csr": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, _P, ctypes.c_int, ctypes.c_int]),
     "xab_spmv_sym": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, _P, ctypes.c_int, ctypes.c_int]),
+    "xab_spmv_csr_noalloc": (ctypes.c_int, [_P, _I32, _I32, _I64, _P, _P, _P, _I32, _P, ctypes.c_int, _P,
+                                            ctypes.c_int, ctypes.c_int]),
     "xab_time_spmv": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, _P, ctypes.c_int, ctypes.c_int, _I32, _I32,
                                      ctypes.POINTER(_F)]),
     "xab_select": (ctypes.c_int, [_P, _P, ctypes.c_int, _PP, ctypes.POINTER(SelectInfo)]),
@@ -281,6 +284,18 @@ class Context:
         at = (F64 if (xt == F64 or yt == F64) else F32) if acc is None else acc
         fn = lib().xab_spmv_sym if plan.A.sym_lower else lib().xab_spmv_csr
         self._check(fn(self.h, plan.h, _ptr(x), xt, _ptr(y), yt, at), "spmv")
+        return y
+
+    def spmv_noalloc(self, rowptr, colind, val, x, y, j=8, ncols=None, acc=None):
+        """y = A x for the CSR arrays (device tensors; values in x's precision)
+        with no plan and no device allocation (xab_spmv_csr_noalloc).  The
+        caller provides y."""
+        xt, yt = _dt(x), _dt(y)
+        at = (F64 if (xt == F64 or yt == F64) else F32) if acc is None else acc
+        n = rowptr.numel() - 1
+        nc = x.numel() if ncols is None else ncols
+        self._check(lib().xab_spmv_csr_noalloc(self.h, n, nc, colind.numel(), _ptr(rowptr), _ptr(colind), _ptr(val), j,
+                                               _ptr(x), xt, _ptr(y), yt, at), "xab_spmv_csr_noalloc")
         return y
 
     def time_spmv(self, plan, x, y, acc=None, warmup=3, reps=20):

@@ -96,6 +96,12 @@ int xab_init(xab_ctx **out, const xab_init_opts *opts) {
         delete ctx;
         return XAB_E_NOMEM;
     }
+    const int ns = xab_noalloc_setup(ctx);
+    if (ns != XAB_OK) {
+        xab_dfree(ctx, ctx->d_flag);
+        delete ctx;
+        return ns;
+    }
     const char *pol = getenv("XAB_POLICY");
     if (pol) {
         if (!strcmp(pol, "TIME")) ctx->policy = XAB_TIME;

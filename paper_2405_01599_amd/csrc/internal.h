@@ -178,6 +178,10 @@ void xab_sell_free(xab_ctx *ctx, xab_sell *s);
 void xab_launch_split_bss(hipStream_t st, const int32_t *rowptr, int32_t n, int64_t T, int64_t P, int32_t *row_lo,
                           int32_t *tile_row, int32_t *carry_row);
 
+// the allocation-free SpMV's device buffer: its address on the context's
+// device, looked up once per device (noalloc.hip; called by xab_init)
+int xab_noalloc_setup(xab_ctx *ctx);
+
 // SpMV dispatch (spmv.hip)
 int xab_spmv_dispatch(xab_ctx *ctx, const xab_plan *plan, const void *x, xab_dtype xt, void *y, xab_dtype yt,
                       xab_dtype acc);

@@ -256,31 +256,36 @@ int launch_nnz(xab_ctx *ctx, const xab_plan *pl, const VT *val, const XT *x, YT 
 }
 
 template <class VT, class XT, class YT, class AT, int J>
-static int launch_bss_j(xab_ctx *ctx, const xab_plan *pl, const VT *val, const XT *x, YT *y) {
-    const xab_matrix *A = pl->A;
-    hipLaunchKernelGGL((k_spmv_bss<VT, XT, YT, AT, J>), dim3((unsigned)pl->P), dim3(kNT), 0, ctx->stream, A->rowptr,
-                       A->colind, val, x, y, A->nnz, pl->P, pl->row_lo, pl->carry_row, (AT *)pl->carry_val,
-                       (AT *)pl->tail_val, pl->tail_row);
+static int launch_bss_j(xab_ctx *ctx, const BssArgs &a, const VT *val, const XT *x, YT *y) {
+    hipLaunchKernelGGL((k_spmv_bss<VT, XT, YT, AT, J>), dim3((unsigned)a.P), dim3(kNT), 0, ctx->stream, a.rowptr,
+                       a.colind, val, x, y, a.nnz, a.P, a.row_lo, a.carry_row, (AT *)a.carry_val, (AT *)a.tail_val,
+                       a.tail_row);
     XAB_LAUNCH_CHECK(ctx, "k_spmv_bss");
-    hipLaunchKernelGGL((k_bss_fixup<YT, AT>), dim3(grid_for(pl->P, 256)), dim3(256), 0, ctx->stream, y, pl->P,
-                       pl->carry_row, (const AT *)pl->carry_val, (const AT *)pl->tail_val, pl->tail_row);
+    hipLaunchKernelGGL((k_bss_fixup<YT, AT>), dim3(grid_for(a.P, 256)), dim3(256), 0, ctx->stream, y, a.P,
+                       a.carry_row, (const AT *)a.carry_val, (const AT *)a.tail_val, a.tail_row);
     XAB_LAUNCH_CHECK(ctx, "k_bss_fixup");
     return XAB_OK;
 }
 
 template <class VT, class XT, class YT, class AT>
-int launch_bss(xab_ctx *ctx, const xab_plan *pl, const VT *val, const XT *x, YT *y) {
-    switch (pl->params.j_per_lane) {
-        case 1: return launch_bss_j<VT, XT, YT, AT, 1>(ctx, pl, val, x, y);
-        case 2: return launch_bss_j<VT, XT, YT, AT, 2>(ctx, pl, val, x, y);
-        case 4: return launch_bss_j<VT, XT, YT, AT, 4>(ctx, pl, val, x, y);
-        case 8: return launch_bss_j<VT, XT, YT, AT, 8>(ctx, pl, val, x, y);
-        case 16: return launch_bss_j<VT, XT, YT, AT, 16>(ctx, pl, val, x, y);
-        case 32: return launch_bss_j<VT, XT, YT, AT, 32>(ctx, pl, val, x, y);
-        default: return xab_fail(ctx, XAB_E_UNSUPPORTED, "j_per_lane %d", pl->params.j_per_lane);
+int launch_bss_raw(xab_ctx *ctx, const BssArgs &a, const VT *val, const XT *x, YT *y) {
+    switch (a.j) {
+        case 1: return launch_bss_j<VT, XT, YT, AT, 1>(ctx, a, val, x, y);
+        case 2: return launch_bss_j<VT, XT, YT, AT, 2>(ctx, a, val, x, y);
+        case 4: return launch_bss_j<VT, XT, YT, AT, 4>(ctx, a, val, x, y);
+        case 8: return launch_bss_j<VT, XT, YT, AT, 8>(ctx, a, val, x, y);
+        case 16: return launch_bss_j<VT, XT, YT, AT, 16>(ctx, a, val, x, y);
+        case 32: return launch_bss_j<VT, XT, YT, AT, 32>(ctx, a, val, x, y);
+        default: return xab_fail(ctx, XAB_E_UNSUPPORTED, "j_per_lane %d", a.j);
     }
 }
 
+template <class VT, class XT, class YT, class AT>
+int launch_bss(xab_ctx *ctx, const xab_plan *pl, const VT *val, const XT *x, YT *y) {
+    const BssArgs a{pl->A->rowptr, pl->A->colind, pl->A->nnz, pl->P, pl->params.j_per_lane, pl->row_lo,
+                    pl->carry_row, pl->carry_val, pl->tail_val, pl->tail_row};
+    return launch_bss_raw<VT, XT, YT, AT>(ctx, a, val, x, y);
+}
 
 template <class VT, class XT, class YT, class AT, int C>
 static int launch_s3_c(xab_ctx *ctx, const xab_plan *pl, const VT *val, const XT *x, YT *y) {
@@ -319,6 +324,14 @@ int launch_sym_s3(xab_ctx *ctx, const xab_plan *pl, const VT *val, const XT *x, 
 
 XAB_INSTANTIATE_LAUNCHER(launch_nnz)
 XAB_INSTANTIATE_LAUNCHER(launch_bss)
+template int launch_bss_raw<double, double, double, double>(xab_ctx *, const BssArgs &, const double *,
+                                                            const double *, double *);
+template int launch_bss_raw<float, float, float, float>(xab_ctx *, const BssArgs &, const float *, const float *,
+                                                        float *);
+template int launch_bss_raw<float, float, float, double>(xab_ctx *, const BssArgs &, const float *, const float *,
+                                                         float *);
+template int launch_bss_raw<float, float, double, double>(xab_ctx *, const BssArgs &, const float *, const float *,
+                                                          double *);
 XAB_INSTANTIATE_LAUNCHER(launch_sym_s3)
 
 }  // namespace xab
