@@ -37,6 +37,7 @@ def lib():
             "orc_plan_sym_touch": (i64, [i64, P, P, i64, P, i64, P, P, P, P, P]),
             "orc_plan_xcb": (None, [i64, i64, P, P, ci, P, P]),
             "orc_xcb_flag_heads": (None, [i64, ci, P, P]),
+            "orc_plan_sym_colflags": (None, [i64, P, P, i64, P, i64, i64, P]),
             "orc_plan_sell": (i64, [i64, P, P, P, ci, ci, P, P, P, P, P, P]),
             "orc_plan_bcsr": (i64, [i64, P, P, P, ci, P, P, P, P]),
             "orc_features": (None, [i64, P, P, ci, P, P]),
@@ -150,6 +151,16 @@ def plan_sym(A, T, Rmax, C):
                              _p(tile_blk), _p(tile_slot))
     return dict(b=b, tm_ptr=tm_ptr, tm_tile=tm_tile[:nt], tile_ptr=tile_ptr, tile_blk=tile_blk[:nt],
                 tile_slot=tile_slot[:nt])
+
+
+def plan_sym_colflags(A, b, lanes=64, J=8):
+    """The symmetric walk's column copy for tiles b: bit 31 on each non-empty
+    row's first entry, bit 30 on an entry added after its chunk's slots."""
+    rp, ci, _ = _csr(A)
+    out = np.empty(max(A.nnz, 1), dtype=np.int32)
+    bb = np.ascontiguousarray(b, dtype=np.int32)
+    lib().orc_plan_sym_colflags(A.n, _p(rp), _p(ci), len(bb) - 1, _p(bb), lanes, J, _p(out))
+    return out[:A.nnz]
 
 
 def plan_xcb(A, nb=8, flagged=False):

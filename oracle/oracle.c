@@ -324,6 +324,33 @@ void orc_xcb_flag_heads(int64_t n, int nb, const int32_t *rp, int32_t *ci) {
     }
 }
 
+/* The symmetric walk's column copy.  The walk issues the transposed adds
+ * of a chunk of lanes * J consecutive entries (chunks start at multiples of
+ * lanes * J) one slot at a time: slot k holds entry k of every lane, i.e.
+ * the entries q with q % J = k.  Within one tile (rows [b_p, b_{p+1})),
+ * entry q gets bit 30 when an earlier entry of its chunk and its slot has
+ * the same column (then it is added after the chunk's slots, so no two
+ * lanes of one add meet on a row).  The first entry of every non-empty row
+ * gets bit 31.  out[nnz] receives colind with these bits. */
+void orc_plan_sym_colflags(int64_t n, const int32_t *rowptr, const int32_t *colind, int64_t P, const int32_t *b,
+                           int64_t lanes, int64_t J, int32_t *out) {
+    const int64_t CH = lanes * J;
+    for (int64_t q = 0; q < rowptr[n]; ++q) out[q] = colind[q];
+    for (int64_t p = 0; p < P; ++p) {
+        const int64_t s = rowptr[b[p]], e = rowptr[b[p + 1]];
+        for (int64_t q = s; q < e; ++q) {
+            /* the earlier entries of q's chunk and slot inside the tile */
+            const int64_t lo = q - q % CH > s ? q - q % CH : s;
+            int later = 0;
+            for (int64_t u = q - J; u >= lo; u -= J)
+                if (colind[u] == colind[q]) later = 1;
+            if (later) out[q] = (int32_t)((uint32_t)out[q] | 0x40000000u);
+        }
+    }
+    for (int64_t i = 0; i < n; ++i)
+        if (rowptr[i + 1] > rowptr[i]) out[rowptr[i]] = (int32_t)((uint32_t)out[rowptr[i]] | 0x80000000u);
+}
+
 /* Block CSR (orc_plan_bcsr in oracle.h): per block row, the block columns
  * of its entries are collected, sorted and made unique; each entry then
  * finds its block by binary search and adds its value to its position. */

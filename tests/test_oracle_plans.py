@@ -461,3 +461,74 @@ def test_bcsr_walk_is_exact():
                     r, c = R * b + e // b, p["bci"][q] * b + e % b
                     y[r] += p["bval"][q][e] * x[c]
     assert np.array_equal(y, oracle.spmv(A, x)[0])
+
+
+# ------------------------------------------------- symmetric walk: deferred adds
+def _colflags_brute(A, b, lanes, J):
+    """Per tile, a dictionary of (chunk, slot, column) seen so far in stream
+    order: an entry whose key was seen gets bit 30; each non-empty row's
+    first entry gets bit 31."""
+    CH = lanes * J
+    rp = A.rowptr.astype(np.int64)
+    out = A.colind.astype(np.int64) & 0xFFFFFFFF
+    for p in range(len(b) - 1):
+        seen = set()
+        for q in range(rp[b[p]], rp[b[p + 1]]):
+            key = (q // CH, q % J, int(A.colind[q]))
+            if key in seen:
+                out[q] |= 1 << 30
+            seen.add(key)
+    for i in range(A.n):
+        if rp[i + 1] > rp[i]:
+            out[rp[i]] |= 1 << 31
+    return out.astype(np.uint32).view(np.int32)
+
+
+@pytest.mark.parametrize("n,seed,band,pe", SYM_CASES)
+@pytest.mark.parametrize("lanes,J", [(4, 2), (2, 3), (64, 8), (1, 1)])
+def test_sym_colflags_brute(n, seed, band, pe, lanes, J):
+    A = _mat_sym(n, seed, band, pe)
+    for T, Rmax in ((16, 8), (40, 1000), (7, 3)):
+        b = oracle.plan_sym(A, T, Rmax, 4)["b"]
+        got = oracle.plan_sym_colflags(A, b, lanes, J)
+        assert np.array_equal(got, _colflags_brute(A, b, lanes, J))
+
+
+def test_sym_colflags_hand_case():
+    """Chunks of 4 lanes x 2 entries (8 entries, slot = position % 2).
+    Rows (columns): 0: 0 | 1: 0 1 | 2: 0 2 | 3: 0 1 3 | 4: 0 4, so the
+    stream's columns are 0 0 1 0 2 0 1 3 | 0 4 (chunk 0 | chunk 1).
+    One tile: slot 1 holds column 0 at positions 1, 3, 5 (3 and 5 flagged),
+    slot 0 holds column 1 at positions 2 and 6 (6 flagged); column 0 at
+    position 8 is in chunk 1 and at 0, 4 in the other slot (not flagged).
+    Tiles [0, 2) and [2, 5): position 2 belongs to the first tile, so 6 is
+    no longer flagged, and neither is 3 (position 1 is in the first tile)."""
+    rows = [[0], [0, 1], [0, 2], [0, 1, 3], [0, 4]]
+    rp = _rp([len(r) for r in rows])
+    ci = np.concatenate(rows).astype(np.int32)
+    A = gen.CSR(5, 5, rp, ci, np.ones(ci.size), sym_lower=True)
+    got = oracle.plan_sym_colflags(A, np.array([0, 5]), 4, 2)
+    assert [(int(v) >> 30) & 1 for v in got] == [0, 0, 0, 1, 0, 1, 1, 0, 0, 0]
+    assert [(int(v) >> 31) & 1 for v in got] == [1, 1, 0, 1, 0, 1, 0, 0, 1, 0]
+    assert [int(v) & 0x3FFFFFFF for v in got] == list(ci)
+    got2 = oracle.plan_sym_colflags(A, np.array([0, 2, 5]), 4, 2)
+    assert [(int(v) >> 30) & 1 for v in got2] == [0, 0, 0, 0, 0, 1, 0, 0, 0, 0]
+
+
+@pytest.mark.parametrize("n,seed,band,pe", SYM_CASES)
+def test_sym_colflags_make_slots_distinct(n, seed, band, pe):
+    """What the kernel relies on: inside a tile, the entries of one chunk
+    and slot that are not flagged have distinct columns."""
+    A = _mat_sym(n, seed, band, pe)
+    lanes, J = 4, 2
+    b = oracle.plan_sym(A, 16, 8, 4)["b"]
+    f = oracle.plan_sym_colflags(A, b, lanes, J).view(np.uint32)
+    rp = A.rowptr
+    for p in range(len(b) - 1):
+        groups = {}
+        for q in range(rp[b[p]], rp[b[p + 1]]):
+            if not (f[q] >> 30) & 1:
+                key = (q // (lanes * J), q % J)
+                groups.setdefault(key, []).append(int(f[q] & 0x3FFFFFFF))
+        for cols in groups.values():
+            assert len(cols) == len(set(cols))
