@@ -84,7 +84,14 @@ typedef enum { XAB_TIME = 0, XAB_STABLE = 1, XAB_LEARNED = 2, XAB_MEMORY = 3, XA
  *   XAB_BSS        branchless segmented scan over the entry stream,
  *                  256 * j_per_lane entries per workgroup
  *   XAB_SYM_S3     symmetric, lower storage, zero-element omission in the
- *                  transpose reduction (column blocks of col_block rows)
+ *                  transpose reduction (column blocks of col_block rows);
+ *                  reproducible bit for bit (every addition in an order
+ *                  fixed by the plan).  When the padding stays within a
+ *                  quarter of the entries and no row exceeds 4096 entries
+ *                  the plan keeps a sliced copy of the matrix (chunks of
+ *                  64 rows, one lane per row) and values changed after
+ *                  plan creation are not seen; otherwise it walks the
+ *                  caller's CSR entries.  Fewer than 2^30 - 1 rows.
  *   XAB_SYM_ATOMIC symmetric, lower storage, transpose part by device
  *                  atomics (baseline; not bitwise reproducible)
  *   XAB_XCB        column-blocked segmented scan: the plan copies the
@@ -195,7 +202,15 @@ void xab_plan_destroy(xab_plan *plan);
  * bit 31 set on the first entry of each row within its block, 11 SELL
  * row order (original row of each ordered row), 12 SELL ordered row
  * lengths, 13 SELL chunk widths, 14 SELL padded column indices, 15 BCSR
- * block row pointers, 16 BCSR block columns, 17 BCSR position masks.
+ * block row pointers, 16 BCSR block columns, 17 BCSR position masks, 18
+ * SYM_S3 entry-stream walk: column indices with bit 31 set on the first
+ * entry of each non-empty row and bit 30 set on an entry that its 64-lane
+ * chunk adds after the others (an entry 8, 16, ... positions earlier in
+ * the same 512-entry chunk and the same tile has the same column), 19-21
+ * SYM_S3 sliced walk: 19 first chunk of each tile (P + 1), 20 chunk
+ * widths, 21 padded column-major columns (-1 padding, bit 30 on an entry
+ * whose column a lower row of the same chunk has in the same slot).  The
+ * arrays of the walk a plan does not take have length 0.
  * *len receives the length; h_out may be NULL to query it.  Synchronous. */
 int xab_plan_array(const xab_plan *plan, int32_t which, int32_t *h_out, int64_t *len);
 int xab_plan_info(const xab_plan *plan, xab_variant *v, xab_params *p);

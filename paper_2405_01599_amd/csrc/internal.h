@@ -87,8 +87,22 @@ struct xab_plan {
     int32_t s3_own_cap = 0;    // most rows of a tile
     int32_t s3_ext_cap = 0;    // most touched blocks of a tile times col_block
     int32_t s3_lut_cap = 0;    // widest span of touched block ids of a tile
-    int32_t *s3_ci = nullptr;  // copy of colind, bit 31 on the first entry of every non-empty row
+    int32_t s3_walk = 0;       // 0: walk over the CSR entry stream, 1: sliced walk (lane = row)
+    // stream walk: copy of colind, bit 31 on the first entry of every non-empty
+    // row, bit 30 on an entry added after its chunk's slots
+    int32_t *s3_ci = nullptr;
     uint8_t *s3_dense = nullptr; // per tile: 1 when none of its rows is empty (the flagged walk applies)
+    // sliced walk: each tile's rows in chunks of 64 (the last one partial),
+    // every chunk stored column-major (stride = its row count), padded to
+    // its longest row; columns carry bit 30 like the stream walk's
+    int64_t s3_nch = 0;          // chunks
+    int64_t s3_padded = 0;       // padded entries
+    int32_t *s3_ch0 = nullptr;   // [P + 1] first chunk of each tile
+    int32_t *s3_cw = nullptr;    // [nch] chunk widths
+    int64_t *s3_coff = nullptr;  // [nch + 1] chunk offsets (the last = padded size)
+    int32_t *s3_cols = nullptr;  // padded columns (padding: -1)
+    double *s3_v64 = nullptr;    // padded values (padding: 0)
+    float *s3_v32 = nullptr;
     // XCB: column-blocked copy of the matrix, one CSR per column block
     static constexpr int kXcb = 8;
     int32_t *xcb_rowptr = nullptr;      // kXcb * (n + 1), each relative to its block's first entry

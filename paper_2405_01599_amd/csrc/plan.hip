@@ -316,6 +316,116 @@ __global__ void k_flag_row_heads(const int32_t *rowptr, int32_t n, int32_t *ci) 
     if (rowptr[r + 1] > e0) ci[e0] = (int32_t)((uint32_t)ci[e0] | 0x80000000u);
 }
 
+// bit 30 of the symmetric column copy: entry q of tile p is added after
+// its chunk's slots when an entry of the same tile, the same chunk of
+// sym::kChunk entries and the same slot (q - J, q - 2J, ... down to the
+// chunk's or the tile's start) has the same column
+__global__ __launch_bounds__(256) void k_sym_defer(const int32_t *rowptr, const int32_t *colind, const int32_t *b,
+                                                   int32_t *ci) {
+    constexpr int J = xab::sym::kChunkJ, CH = xab::sym::kChunk;
+    const int64_t p = blockIdx.x;
+    const int64_t s = rowptr[b[p]], e = rowptr[b[p + 1]];
+    for (int64_t q = s + threadIdx.x; q < e; q += 256) {
+        const int32_t j = colind[q];
+        const int64_t c0 = q - q % CH, lo = c0 > s ? c0 : s;
+        bool d = false;
+        for (int64_t u = q - J; u >= lo && !d; u -= J) d = colind[u] == j;
+        if (d) ci[q] = (int32_t)((uint32_t)ci[q] | xab::sym::kDeferBit);
+    }
+}
+
+// sliced symmetric walk, step 1: chunks of 64 rows per tile (the last
+// one partial)
+__global__ void k_sym_nch(const int32_t *b, int64_t P, int32_t *cnt) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < P) cnt[p] = (b[p + 1] - b[p] + xab::sym::kLanes - 1) / xab::sym::kLanes;
+}
+
+// step 2 (one wave per tile): each chunk's width (its longest row) and
+// stored size (width x rows); the widest chunk goes to *widest
+__global__ __launch_bounds__(64) void k_sym_widths(const int32_t *rowptr, const int32_t *b, const int32_t *ch0,
+                                                   int32_t *cw, int64_t *csz, int *widest) {
+    const int64_t p = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int32_t r0 = b[p], r1 = b[p + 1], g0 = ch0[p];
+    int32_t most = 0;
+    for (int32_t g = g0; g < ch0[p + 1]; ++g) {
+        const int32_t rc = r0 + xab::sym::kLanes * (g - g0);
+        const int32_t i = rc + lane;
+        int32_t w = i < r1 ? rowptr[i + 1] - rowptr[i] : 0;
+        for (int m = 32; m > 0; m >>= 1) w = max(w, __shfl_xor(w, m, 64));
+        if (lane == 0) {
+            cw[g] = w;
+            csz[g] = (int64_t)w * min(xab::sym::kLanes, r1 - rc);
+        }
+        most = max(most, w);
+    }
+    if (lane == 0) atomicMax(widest, most);
+}
+
+// exclusive scan of int64 values in one workgroup: out[0..m] (out[m] = total)
+__global__ void k_scan_i64(const int64_t *in, int64_t m, int64_t *out) {
+    __shared__ int64_t part[1024];
+    __shared__ int64_t carry;
+    const int t = threadIdx.x;
+    if (t == 0) carry = 0;
+    __syncthreads();
+    for (int64_t base = 0; base < m; base += 1024) {
+        const int64_t i = base + t;
+        const int64_t v = i < m ? in[i] : 0;
+        part[t] = v;
+        __syncthreads();
+        for (int d = 1; d < 1024; d <<= 1) {
+            const int64_t u = t >= d ? part[t - d] : 0;
+            __syncthreads();
+            part[t] += u;
+            __syncthreads();
+        }
+        if (i < m) out[i] = carry + part[t] - v;
+        __syncthreads();
+        if (t == 1023) carry += part[1023];
+        __syncthreads();
+    }
+    if (t == 0) out[m] = carry;
+}
+
+// step 3 (one wave per tile): the padded column-major copy.  Entry k of
+// the chunk's lane l (row r0 + 64 c + l) sits at coff[g] + k * rows + l;
+// padding has column -1 and value 0.  Bit 30: a lower lane of the same
+// chunk has the same column in slot k.
+__global__ __launch_bounds__(64) void k_sym_slice_fill(const int32_t *rowptr, const int32_t *colind,
+                                                       const double *v64, const float *v32, const int32_t *b,
+                                                       const int32_t *ch0, const int32_t *cw, const int64_t *coff,
+                                                       int32_t *cols, double *o64, float *o32) {
+    __shared__ int32_t slot[64];
+    const int64_t p = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int32_t r0 = b[p], r1 = b[p + 1], g0 = ch0[p];
+    for (int32_t g = g0; g < ch0[p + 1]; ++g) {
+        const int32_t rc = r0 + xab::sym::kLanes * (g - g0);
+        const int32_t i = rc + lane, nr = min(xab::sym::kLanes, r1 - rc);
+        const bool on = lane < nr;
+        const int32_t s = on ? rowptr[i] : 0, len = on ? rowptr[i + 1] - s : 0;
+        const int32_t w = cw[g];
+        const int64_t o = coff[g];
+        for (int32_t k = 0; k < w; ++k) {
+            const int32_t c = k < len ? colind[s + k] : -1;
+            slot[lane] = c;
+            __syncthreads();
+            bool later = false;
+            if (c >= 0)
+                for (int l = 0; l < lane; ++l) later |= slot[l] == c;
+            __syncthreads();
+            if (on) {
+                const int64_t q = o + (int64_t)k * nr + lane;
+                cols[q] = later ? (int32_t)((uint32_t)c | xab::sym::kDeferBit) : c;
+                if (o64) o64[q] = k < len ? v64[s + k] : 0.0;
+                if (o32) o32[q] = k < len ? v32[s + k] : 0.0f;
+            }
+        }
+    }
+}
+
 // dense[p] = 1 when every row of tile p (rows [b[p], b[p+1])) has an entry
 __global__ void k_tile_dense(const int32_t *rowptr, const int32_t *b, int64_t P, uint8_t *dense) {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -602,6 +712,12 @@ static void free_plan_arrays(xab_ctx *ctx, xab_plan *pl) {
     xab_dfree(ctx, pl->xcb_gbase);
     xab_dfree(ctx, pl->s3_ci);
     xab_dfree(ctx, pl->s3_dense);
+    xab_dfree(ctx, pl->s3_ch0);
+    xab_dfree(ctx, pl->s3_cw);
+    xab_dfree(ctx, pl->s3_coff);
+    xab_dfree(ctx, pl->s3_cols);
+    xab_dfree(ctx, pl->s3_v64);
+    xab_dfree(ctx, pl->s3_v32);
     xab_sell_free(ctx, &pl->sell);
     xab_dfree(ctx, pl->bcsr_brp);
     xab_dfree(ctx, pl->bcsr_bci);
@@ -627,6 +743,7 @@ static size_t plan_device_bytes(const xab_plan *pl) {
     const void *arrays[] = {pl->b, pl->row_lo, pl->tile_row, pl->carry_row, pl->carry_val, pl->tail_val,
                             pl->tail_row, pl->tm_ptr, pl->tm_tile, pl->tile_ptr, pl->tile_blk, pl->tile_slot,
                             pl->tile_minblk, pl->partial, pl->xcb_rowptr, pl->xcb_gbase, pl->s3_ci, pl->s3_dense,
+                            pl->s3_ch0, pl->s3_cw, pl->s3_coff, pl->s3_cols, pl->s3_v64, pl->s3_v32,
                             pl->sell.perm, pl->sell.rlen, pl->sell.clen, pl->sell.cptr, pl->sell.cols,
                             pl->sell.val64, pl->sell.val32, pl->bcsr_brp, pl->bcsr_bci, pl->bcsr_mask,
                             pl->bcsr_val64, pl->bcsr_val32, pl->xcb_mask, pl->xcb_colind, pl->xcb_val64,
@@ -772,6 +889,8 @@ int xab_build_plan(xab_ctx *ctx, const xab_matrix *A, xab_variant v, const xab_p
             if (p.tile_rows < 1 || p.tile_rows > xab::sym::kRowCap)
                 return xab_fail(ctx, XAB_E_UNSUPPORTED, "tile_rows must be in [1, %d]", xab::sym::kRowCap);
             if (p.tile_nnz < 64) return xab_fail(ctx, XAB_E_UNSUPPORTED, "tile_nnz < 64");
+            if (A->n >= xab::sym::kMaxCols)
+                return xab_fail(ctx, XAB_E_UNSUPPORTED, "symmetric tiles need fewer than 2^30 - 1 rows");
             break;
         default:
             return xab_fail(ctx, XAB_E_UNSUPPORTED, "unknown variant %d", (int)v);
@@ -1134,7 +1253,7 @@ int xab_build_plan(xab_ctx *ctx, const xab_matrix *A, xab_variant v, const xab_p
         pl->s3_own_cap = own;
         pl->s3_ext_cap = nbmax * C;
         pl->s3_lut_cap = (span + 7) / 8 * 8;
-        size_t lds = xab::sym::kFixedBytes + 16 + 8 * (2 * (size_t)pl->s3_own_cap + pl->s3_ext_cap) + 2 * (size_t)pl->s3_lut_cap;
+        const size_t lds = xab::sym::lds_bytes(pl->s3_own_cap, pl->s3_ext_cap, pl->s3_lut_cap, 8);
         if (lds > (size_t)xab::sym::kLdsCap) {
             free_plan_arrays(ctx, pl);
             delete pl;
@@ -1163,18 +1282,80 @@ int xab_build_plan(xab_ctx *ctx, const xab_matrix *A, xab_variant v, const xab_p
             delete pl;
             return xab_fail(ctx, XAB_E_NOMEM, "partial buffer");
         }
-        // flagged copy of the columns and the per-tile "no empty row" marks
-        ALLOC(pl->s3_ci, int32_t, std::max<int64_t>(1, nnz));
-        ALLOC(pl->s3_dense, uint8_t, std::max<int64_t>(1, P));
-        if (nnz > 0) {
-            e = hipMemcpyAsync(pl->s3_ci, A->colind, sizeof(int32_t) * (size_t)nnz, hipMemcpyDeviceToDevice, st);
-            CHECKED(hip_ok(ctx, e, "column copy"));
-            hipLaunchKernelGGL(k_flag_row_heads, dim3(grid_for(n, 256)), dim3(256), 0, st, A->rowptr, n, pl->s3_ci);
+        // the walk: sliced (lane = row, chunks of 64 rows padded to their
+        // longest row) when the padding stays within a quarter of the entries
+        // and no row is longer than the sliced walk's serial row sum allows,
+        // else the stream walk over the CSR entries
+        ALLOC(pl->s3_ch0, int32_t, P + 1);
+        {
+            int32_t *cnt1 = (int32_t *)xab_dalloc(ctx, sizeof(int32_t) * (P + 1));
+            if (!cnt1) {
+                free_plan_arrays(ctx, pl);
+                delete pl;
+                return xab_fail(ctx, XAB_E_NOMEM, "plan allocation");
+            }
+            hipLaunchKernelGGL(k_sym_nch, dim3(grid_for(P, 256)), dim3(256), 0, st, pl->b, (int64_t)P, cnt1);
+            hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, st, cnt1, (int64_t)P, pl->s3_ch0);
+            int32_t nch = 0;
+            e = hipMemcpyAsync(&nch, pl->s3_ch0 + P, sizeof(int32_t), hipMemcpyDeviceToHost, st);
+            if (e == hipSuccess) e = hipStreamSynchronize(st);
+            xab_dfree(ctx, cnt1);
+            CHECKED(hip_ok(ctx, e, "sym chunk count"));
+            pl->s3_nch = nch;
         }
-        if (P > 0)
-            hipLaunchKernelGGL(k_tile_dense, dim3(grid_for(P, 256)), dim3(256), 0, st, A->rowptr, pl->b, (int64_t)P,
-                               pl->s3_dense);
-        CHECKED(hip_ok(ctx, hipGetLastError(), "flagged columns"));
+        const int64_t nch = std::max<int64_t>(1, pl->s3_nch);
+        ALLOC(pl->s3_cw, int32_t, nch);
+        ALLOC(pl->s3_coff, int64_t, nch + 1);
+        int64_t padded = 0;
+        int widest = 0;
+        {
+            int64_t *csz = (int64_t *)xab_dalloc(ctx, sizeof(int64_t) * nch);
+            if (!csz) {
+                free_plan_arrays(ctx, pl);
+                delete pl;
+                return xab_fail(ctx, XAB_E_NOMEM, "plan allocation");
+            }
+            hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, st, (int32_t *)ctx->d_flag, (int64_t)1);
+            if (P > 0)
+                hipLaunchKernelGGL(k_sym_widths, dim3((unsigned)P), dim3(64), 0, st, A->rowptr, pl->b, pl->s3_ch0,
+                                   pl->s3_cw, csz, ctx->d_flag);
+            hipLaunchKernelGGL(k_scan_i64, dim3(1), dim3(1024), 0, st, csz, pl->s3_nch, pl->s3_coff);
+            e = hipMemcpyAsync(&padded, pl->s3_coff + pl->s3_nch, sizeof(int64_t), hipMemcpyDeviceToHost, st);
+            if (e == hipSuccess) e = hipMemcpyAsync(&widest, ctx->d_flag, sizeof(int), hipMemcpyDeviceToHost, st);
+            if (e == hipSuccess) e = hipStreamSynchronize(st);
+            xab_dfree(ctx, csz);
+            CHECKED(hip_ok(ctx, e, "sym chunk widths"));
+        }
+        pl->s3_walk = xab::sym::sliced(nnz, padded, widest) ? 1 : 0;
+        pl->s3_padded = padded;
+        if (pl->s3_walk) {
+            const int64_t tot = std::max<int64_t>(1, padded);
+            ALLOC(pl->s3_cols, int32_t, tot);
+            if (A->has64) ALLOC(pl->s3_v64, double, tot);
+            if (A->has32) ALLOC(pl->s3_v32, float, tot);
+            if (P > 0)
+                hipLaunchKernelGGL(k_sym_slice_fill, dim3((unsigned)P), dim3(64), 0, st, A->rowptr, A->colind,
+                                   A->val64, A->val32, pl->b, pl->s3_ch0, pl->s3_cw, pl->s3_coff, pl->s3_cols,
+                                   pl->s3_v64, pl->s3_v32);
+            CHECKED(hip_ok(ctx, hipGetLastError(), "sliced copy"));
+        } else {
+            // flagged copy of the columns and the per-tile "no empty row" marks
+            ALLOC(pl->s3_ci, int32_t, std::max<int64_t>(1, nnz));
+            ALLOC(pl->s3_dense, uint8_t, std::max<int64_t>(1, P));
+            if (nnz > 0) {
+                e = hipMemcpyAsync(pl->s3_ci, A->colind, sizeof(int32_t) * (size_t)nnz, hipMemcpyDeviceToDevice, st);
+                CHECKED(hip_ok(ctx, e, "column copy"));
+                hipLaunchKernelGGL(k_flag_row_heads, dim3(grid_for(n, 256)), dim3(256), 0, st, A->rowptr, n,
+                                   pl->s3_ci);
+                if (P > 0)
+                    hipLaunchKernelGGL(k_sym_defer, dim3((unsigned)P), dim3(256), 0, st, A->rowptr, A->colind, pl->b,
+                                       pl->s3_ci);
+            }
+            if (P > 0)
+                hipLaunchKernelGGL(k_tile_dense, dim3(grid_for(P, 256)), dim3(256), 0, st, A->rowptr, pl->b,
+                                   (int64_t)P, pl->s3_dense);
+            CHECKED(hip_ok(ctx, hipGetLastError(), "flagged columns"));
+        }
     }
     hipError_t e = hipStreamSynchronize(st);
     if (e != hipSuccess) {
@@ -1231,6 +1412,10 @@ int xab_plan_array(const xab_plan *pl, int32_t which, int32_t *h_out, int64_t *l
         case 15: src = pl->bcsr_brp; m = pl->bcsr_brp ? pl->bcsr_nbr + 1 : 0; break;
         case 16: src = pl->bcsr_bci; m = pl->bcsr_bci ? pl->bcsr_nb : 0; break;
         case 17: src = pl->bcsr_mask; m = pl->bcsr_mask ? pl->bcsr_nb : 0; break;
+        case 18: src = pl->s3_ci; m = pl->s3_ci ? pl->A->nnz : 0; break;
+        case 19: src = pl->s3_cols ? pl->s3_ch0 : nullptr; m = pl->s3_cols ? pl->P + 1 : 0; break;
+        case 20: src = pl->s3_cols ? pl->s3_cw : nullptr; m = pl->s3_cols ? pl->s3_nch : 0; break;
+        case 21: src = pl->s3_cols; m = pl->s3_cols ? pl->s3_padded : 0; break;
         default: return XAB_E_SHAPE;
     }
     *len = m;

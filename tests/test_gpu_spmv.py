@@ -325,9 +325,44 @@ def _drop_rows(L, rows):
     return gen.CSR(L.n, L.ncols, rp, L.colind[m].copy(), L.val[m].copy(), sym_lower=True, name="holes")
 
 
+def _arrow(n, band, seed):
+    """Lower triangle of an arrowhead matrix: row i holds column 0 and the
+    band i - band .. i.  Rows of 8 entries start at multiples of 8, so one
+    slot of every chunk holds column 0 in every lane: the walk adds those
+    entries one lane at a time."""
+    rng = np.random.default_rng(seed)
+    rows = [np.unique(np.r_[0, np.arange(max(0, i - band), i + 1)]) for i in range(n)]
+    rp = np.zeros(n + 1, dtype=np.int32)
+    rp[1:] = np.cumsum([r.size for r in rows])
+    ci = np.concatenate(rows).astype(np.int32)
+    v = rng.standard_normal(ci.size)
+    return gen.CSR(n, n, rp, ci, v, sym_lower=True, name="arrow")
+
+
+def _sym_powerlaw(n, seed):
+    """Lower triangle with lognormal row lengths (the diagonal plus distinct
+    random columns in the 600 below it): rows of very different lengths, so
+    the symmetric product walks the CSR entry stream, not the sliced copy."""
+    rng = np.random.default_rng(seed)
+    lens = np.clip(np.round(np.exp(rng.normal(1.5, 1.2, n))), 1, 400).astype(np.int64)
+    rows = []
+    for i in range(n):
+        lo = max(0, i - 600)
+        k = int(min(lens[i] - 1, i - lo))
+        below = lo + rng.choice(i - lo, size=k, replace=False) if k > 0 else np.zeros(0, dtype=np.int64)
+        rows.append(np.sort(np.r_[below, i]).astype(np.int32))
+    rp = np.zeros(n + 1, dtype=np.int32)
+    rp[1:] = np.cumsum([r.size for r in rows])
+    ci = np.concatenate(rows)
+    return gen.CSR(n, n, rp, ci, rng.standard_normal(ci.size), sym_lower=True, name="sym_powerlaw")
+
+
 def sym_suite():
     B = gen.banded(20_000, 30, 9, lower=True)
     return {
+        "arrow": _arrow(3000, 6, 5),
+        "sym_powerlaw": _sym_powerlaw(12_000, 4),
+        "sym_powerlaw_holes": _drop_rows(_sym_powerlaw(9_000, 6), np.r_[0:3, 2000:2040, 5001:9000:211, 8999]),
         "banded_holes": _drop_rows(B, np.r_[0:5, 7000:7100, 13001:20000:997, 19999]),
         "lap2d_lower": gen.laplacian2d(64, lower=True),
         "st27_16": gen.stencil27(16, lower=True),
@@ -396,6 +431,15 @@ def test_sym_plan_bitexact(ctx, name, C, T, R):
     assert np.array_equal(P.array(6), want["tile_ptr"])
     assert np.array_equal(P.array(7), want["tile_blk"])
     assert np.array_equal(P.array(8), want["tile_slot"])
+    lay = oracle.plan_sym_slices(A, want["b"])
+    if lay["sliced"]:
+        assert P.array(18).size == 0
+        assert np.array_equal(P.array(19), lay["ch0"])
+        assert np.array_equal(P.array(20), lay["cw"])
+        assert np.array_equal(P.array(21), lay["cols"])
+    else:
+        assert P.array(19).size == 0 and P.array(21).size == 0
+        assert np.array_equal(P.array(18), oracle.plan_sym_colflags(A, want["b"], 64, 8))
     x = gen.int_vec(A.n, 1)
     Ai = _int_version(A)
     Mi = ctx.matrix_from_csr(Ai)
@@ -418,12 +462,22 @@ def test_sym_fp32(ctx, k, combo):
     assert np.all(np.abs(y - y_exact) <= bound * s)
 
 
-def test_sym_determinism(ctx):
-    A = SYM["st27_24"]
-    x = dev(gen.uniform_vec(A.n, 1))
-    M = ctx.matrix_from_csr(A)
-    P = ctx.plan_class(M, 10)
-    a = ctx.spmv(P, x).cpu().numpy()
-    b = ctx.spmv(P, x).cpu().numpy()
-    _, s = oracle.spmv(A, x.cpu().numpy())
-    assert np.all(np.abs(a - b) <= 1e-15 * s)
+@pytest.mark.parametrize("name", ["st27_24", "banded_holes", "arrow", "sym_powerlaw", "sym_powerlaw_holes"])
+@pytest.mark.parametrize("k", [10, 11])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_sym_determinism(ctx, name, k, prec):
+    """The symmetric product is the same bit for bit on every run, in both
+    walks (sliced: the stencils, bands and the arrow; entry stream: the
+    power-law rows): every addition to a tile's accumulators happens in one
+    fixed order."""
+    A = SYM[name]
+    M = ctx.matrix_from_csr(A, with_f32=True)
+    P = ctx.plan_class(M, k)
+    xh = gen.uniform_vec(A.n, 1)
+    if prec == "f64":
+        x, kw = dev(xh), {}
+    else:
+        x, kw = dev(xh, torch.float32), {"ydtype": torch.float32, "acc": xab.F64}
+    ref = ctx.spmv(P, x, **kw)
+    for _ in range(20):
+        assert torch.equal(ctx.spmv(P, x, **kw), ref)
