@@ -38,6 +38,8 @@ def lib():
             "orc_plan_xcb": (None, [i64, i64, P, P, ci, P, P]),
             "orc_xcb_flag_heads": (None, [i64, ci, P, P]),
             "orc_plan_sym_colflags": (None, [i64, P, P, i64, P, i64, i64, P]),
+            "orc_plan_sym_slices": (i64, [i64, P, P, i64, P, i64, P, P, P, P, P, P]),
+            "orc_sym_walk_sliced": (ci, [i64, i64, i64]),
             "orc_plan_sell": (i64, [i64, P, P, P, ci, ci, P, P, P, P, P, P]),
             "orc_plan_bcsr": (i64, [i64, P, P, P, ci, P, P, P, P]),
             "orc_features": (None, [i64, P, P, ci, P, P]),
@@ -161,6 +163,26 @@ def plan_sym_colflags(A, b, lanes=64, J=8):
     bb = np.ascontiguousarray(b, dtype=np.int32)
     lib().orc_plan_sym_colflags(A.n, _p(rp), _p(ci), len(bb) - 1, _p(bb), lanes, J, _p(out))
     return out[:A.nnz]
+
+
+def plan_sym_slices(A, b, lanes=64):
+    """The symmetric product's sliced layout for tiles b: dict with ch0,
+    cw, coff, cols (bit 30 on an entry a lower lane of its slot meets) and
+    `sliced`, whether the product takes this walk."""
+    rp, ci, _ = _csr(A)
+    bb = np.ascontiguousarray(b, dtype=np.int32)
+    P = len(bb) - 1
+    nch, widest = ctypes.c_int64(), ctypes.c_int64()
+    tot = int(lib().orc_plan_sym_slices(A.n, _p(rp), _p(ci), P, _p(bb), lanes, None, None, None, None,
+                                        ctypes.byref(nch), ctypes.byref(widest)))
+    ch0 = np.empty(P + 1, dtype=np.int32)
+    cw = np.empty(max(nch.value, 1), dtype=np.int32)
+    coff = np.empty(nch.value + 1, dtype=np.int64)
+    cols = np.empty(max(tot, 1), dtype=np.int32)
+    lib().orc_plan_sym_slices(A.n, _p(rp), _p(ci), P, _p(bb), lanes, _p(ch0), _p(cw), _p(coff), _p(cols),
+                              ctypes.byref(nch), ctypes.byref(widest))
+    return dict(ch0=ch0, cw=cw[:nch.value], coff=coff, cols=cols[:tot], widest=widest.value,
+                sliced=bool(lib().orc_sym_walk_sliced(A.nnz, tot, widest.value)))
 
 
 def plan_xcb(A, nb=8, flagged=False):

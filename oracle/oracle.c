@@ -351,6 +351,64 @@ void orc_plan_sym_colflags(int64_t n, const int32_t *rowptr, const int32_t *coli
         if (rowptr[i + 1] > rowptr[i]) out[rowptr[i]] = (int32_t)((uint32_t)out[rowptr[i]] | 0x80000000u);
 }
 
+/* The symmetric product's sliced layout.  Tile p's rows [b_p, b_{p+1}) are
+ * cut into chunks of `lanes` rows (the last one shorter); chunk g holds
+ * rows rc .. rc + nr - 1 and has width w_g = its longest row.  Entry k of
+ * the chunk's row rc + l is stored at coff_g + k * nr + l (column-major
+ * with stride nr); slots past a row's end hold column -1 (value 0 in the
+ * value copy).  A stored entry gets bit 30 when a lower l' of the same
+ * chunk has the same column in the same slot k.  ch0[P + 1]: first chunk
+ * of each tile; cw[nch], coff[nch + 1]; cols[coff_nch].  Outputs may be
+ * null (sizes only).  Returns the padded size; *nch and *widest receive
+ * the chunk count and the longest row. */
+int64_t orc_plan_sym_slices(int64_t n, const int32_t *rowptr, const int32_t *colind, int64_t P, const int32_t *b,
+                            int64_t lanes, int32_t *ch0, int32_t *cw, int64_t *coff, int32_t *cols, int64_t *nch,
+                            int64_t *widest) {
+    (void)n;
+    int64_t g = 0, off = 0, most = 0;
+    for (int64_t p = 0; p < P; ++p) {
+        if (ch0) ch0[p] = (int32_t)g;
+        for (int64_t rc = b[p]; rc < b[p + 1]; rc += lanes) {
+            const int64_t nr = rc + lanes < b[p + 1] ? lanes : b[p + 1] - rc;
+            int64_t w = 0;
+            for (int64_t l = 0; l < nr; ++l) {
+                const int64_t len = rowptr[rc + l + 1] - rowptr[rc + l];
+                if (len > w) w = len;
+            }
+            if (w > most) most = w;
+            if (cw) cw[g] = (int32_t)w;
+            if (coff) coff[g] = off;
+            if (cols)
+                for (int64_t k = 0; k < w; ++k)
+                    for (int64_t l = 0; l < nr; ++l) {
+                        const int64_t i = rc + l, len = rowptr[i + 1] - rowptr[i];
+                        int32_t c = k < len ? colind[rowptr[i] + k] : -1;
+                        if (c >= 0)
+                            for (int64_t u = 0; u < l; ++u) {
+                                const int64_t iu = rc + u;
+                                if (k < rowptr[iu + 1] - rowptr[iu] && colind[rowptr[iu] + k] == colind[rowptr[i] + k])
+                                    c = (int32_t)((uint32_t)c | 0x40000000u);
+                            }
+                        cols[off + k * nr + l] = c;
+                    }
+            off += w * nr;
+            g++;
+        }
+    }
+    if (ch0) ch0[P] = (int32_t)g;
+    if (coff) coff[g] = off;
+    if (nch) *nch = g;
+    if (widest) *widest = most;
+    return off;
+}
+
+/* Which walk the symmetric product takes: the sliced one when its padding
+ * stays within a quarter of the entries and no row is longer than 4096,
+ * else the walk over the CSR entry stream. */
+int orc_sym_walk_sliced(int64_t nnz, int64_t padded, int64_t widest) {
+    return padded <= nnz + nnz / 4 && widest <= 4096;
+}
+
 /* Block CSR (orc_plan_bcsr in oracle.h): per block row, the block columns
  * of its entries are collected, sorted and made unique; each entry then
  * finds its block by binary search and adds its value to its position. */

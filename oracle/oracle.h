@@ -64,6 +64,10 @@ int64_t orc_plan_sym_touch(int64_t n, const int32_t *rowptr, const int32_t *coli
 void orc_plan_xcb(int64_t n, int64_t ncols, const int32_t *rowptr, const int32_t *colind, int nb, int32_t *rp,
                   int32_t *ci);
 void orc_xcb_flag_heads(int64_t n, int nb, const int32_t *rp, int32_t *ci);
+int64_t orc_plan_sym_slices(int64_t n, const int32_t *rowptr, const int32_t *colind, int64_t P, const int32_t *b,
+                            int64_t lanes, int32_t *ch0, int32_t *cw, int64_t *coff, int32_t *cols, int64_t *nch,
+                            int64_t *widest);
+int orc_sym_walk_sliced(int64_t nnz, int64_t padded, int64_t widest);
 void orc_plan_sym_colflags(int64_t n, const int32_t *rowptr, const int32_t *colind, int64_t P, const int32_t *b,
                            int64_t lanes, int64_t J, int32_t *out);
 int64_t orc_plan_sell(int64_t n, const int32_t *rowptr, const int32_t *colind, const double *val, int C,

@@ -532,3 +532,115 @@ def test_sym_colflags_make_slots_distinct(n, seed, band, pe):
                 groups.setdefault(key, []).append(int(f[q] & 0x3FFFFFFF))
         for cols in groups.values():
             assert len(cols) == len(set(cols))
+
+
+# ------------------------------------------------- symmetric walk: sliced layout
+def _slices_brute(A, b, lanes):
+    """Per tile, per chunk of `lanes` rows: a dense (width x rows) table of
+    columns (-1 past a row's end) read out slot-major; a column already seen
+    at the same slot of the chunk gets bit 30."""
+    rp = A.rowptr.astype(np.int64)
+    ch0, cw, coff, cols = [], [], [0], []
+    for p in range(len(b) - 1):
+        ch0.append(len(cw))
+        for rc in range(b[p], b[p + 1], lanes):
+            rows = list(range(rc, min(rc + lanes, b[p + 1])))
+            lens = [rp[i + 1] - rp[i] for i in rows]
+            w = max(lens)
+            cw.append(w)
+            for k in range(w):
+                seen = set()
+                for i, ln in zip(rows, lens):
+                    c = int(A.colind[rp[i] + k]) if k < ln else -1
+                    v = c
+                    if c >= 0:
+                        if c in seen:
+                            v = c | (1 << 30)
+                        seen.add(c)
+                    cols.append(v)
+            coff.append(coff[-1] + w * len(rows))
+    ch0.append(len(cw))
+    return dict(ch0=np.array(ch0), cw=np.array(cw, dtype=np.int64), coff=np.array(coff),
+                cols=np.array(cols, dtype=np.int64).astype(np.uint32).view(np.int32))
+
+
+@pytest.mark.parametrize("n,seed,band,pe", SYM_CASES)
+@pytest.mark.parametrize("lanes", [1, 3, 4, 64])
+def test_sym_slices_brute(n, seed, band, pe, lanes):
+    A = _mat_sym(n, seed, band, pe)
+    for T, Rmax in ((16, 8), (40, 1000), (7, 3)):
+        b = oracle.plan_sym(A, T, Rmax, 4)["b"]
+        got = oracle.plan_sym_slices(A, b, lanes)
+        want = _slices_brute(A, b, lanes)
+        for key in ("ch0", "cw", "coff", "cols"):
+            assert np.array_equal(got[key].astype(np.int64), want[key].astype(np.int64)), key
+
+
+def _eval_slices(A, x, b, lay, lanes):
+    """Walk the sliced layout the way the product does: per chunk, slot by
+    slot, each row adds its entry to its own sum and, below the diagonal,
+    the transposed product to row j; integer values make every order exact."""
+    y = np.zeros(A.n)
+    val = {}
+    rp = A.rowptr
+    for i in range(A.n):
+        for q in range(rp[i], rp[i + 1]):
+            val[(i, int(A.colind[q]))] = val.get((i, int(A.colind[q])), 0.0) + A.val[q]
+    g = 0
+    for p in range(len(b) - 1):
+        for rc in range(b[p], b[p + 1], lanes):
+            nr = min(lanes, b[p + 1] - rc)
+            w, o = lay["cw"][g], lay["coff"][g]
+            cnt = {}
+            for k in range(w):
+                for l in range(nr):
+                    c = int(lay["cols"][o + k * nr + l])
+                    if c == -1:
+                        continue
+                    j, i = c & 0x3FFFFFFF, rc + l
+                    kk = cnt.get((i, j), 0)  # the k-th stored (i, j) entry (duplicates are summed)
+                    cnt[(i, j)] = kk + 1
+                    ks = [q for q in range(rp[i], rp[i + 1]) if A.colind[q] == j]
+                    a = A.val[ks[kk]]
+                    y[i] += a * x[j]
+                    if j < i:
+                        y[j] += a * x[i]
+            g += 1
+    return y
+
+
+@pytest.mark.parametrize("n,seed,band,pe", SYM_CASES[:3])
+def test_sym_slices_walk_is_exact(n, seed, band, pe):
+    A = _mat_sym(n, seed, band, pe)
+    x = gen.int_vec(A.n, 8)
+    y, _ = oracle.spmv(A, x)
+    for T, Rmax, lanes in ((16, 8, 4), (40, 1000, 64), (7, 3, 3)):
+        b = oracle.plan_sym(A, T, Rmax, 4)["b"]
+        lay = oracle.plan_sym_slices(A, b, lanes)
+        assert np.array_equal(_eval_slices(A, x, b, lay, lanes), y)
+
+
+def test_sym_slices_slots_distinct_and_walk_rule():
+    """Unflagged entries of one chunk and slot have distinct columns; the
+    27-point stencil takes the sliced walk (little padding), a lower
+    triangle with rows of very different lengths does not."""
+    A = gen.stencil27(12, lower=True)
+    b = oracle.plan_sym(A, 2048, 512, 64)["b"]
+    lay = oracle.plan_sym_slices(A, b)
+    assert lay["sliced"]
+    cols = lay["cols"].view(np.uint32)
+    for g in range(len(lay["cw"])):
+        o, w = lay["coff"][g], lay["cw"][g]
+        nr = (lay["coff"][g + 1] - o) // max(w, 1) if w else 0
+        for k in range(w):
+            s = cols[o + k * nr:o + (k + 1) * nr]
+            live = s[(s != 0xFFFFFFFF) & ((s >> 30) & 1 == 0)] & 0x3FFFFFFF
+            assert len(live) == len(set(live.tolist()))
+    rng = np.random.default_rng(3)
+    rows = [np.unique(np.r_[rng.integers(0, i + 1, int(rng.integers(1, 60)) if i % 9 == 0 else 1), i])
+            for i in range(400)]
+    rp = _rp([r.size for r in rows])
+    ci = np.concatenate(rows).astype(np.int32)
+    B = gen.CSR(400, 400, rp, ci, np.ones(ci.size), sym_lower=True)
+    bb = oracle.plan_sym(B, 2048, 512, 64)["b"]
+    assert not oracle.plan_sym_slices(B, bb)["sliced"]
