@@ -15,9 +15,13 @@ Extra fields on the same JSON line: the FP32-value SpMV rate, the
 time-to-1e-10 of GMRES(30) in FP64 and in mixed precision with FP64
 refinement (median of 3), the same pair plus the symmetric SpMV rates on the
 128^3 27-point stencil stored as its lower triangle, the batched SpMV and
-BiCGStab over 512 uneven systems, the selector's choices
-(TIME and LEARNED) and timings, the roofline of the dominant kernel and the
-CPU oracle baseline.
+BiCGStab over 512 uneven systems, the trans4-shaped segment-length sweep,
+the selector's choices (TIME and LEARNED) and timings, the roofline of the
+dominant kernel and the CPU oracle leg.  The oracle leg runs in a thread
+pinned to one host core beside the GPU legs: the oracle's SpMV rate (the
+baseline), its GMRES(30) time to 1e-10 on both matrices, and the error of
+the GPU's FP64 and FP32-value products stated per result (max over rows of
+abs(dy) / sum abs(a x)) on both matrices, in both accumulations.
 
 Hardware-counter traffic: before the timed region the script runs a plain
 streaming copy of known size (torch.neg over 256 MiB, read once, written
@@ -63,7 +67,7 @@ VARIANT_KERNELS = {
     "NNZ": ("k_spmv_nnz",),
     "BSS": ("k_spmv_bss", "k_bss_fixup"),
     "XCB": ("k_spmv_xcb", "k_xcb_fixup", "k_xcb_combine"),
-    "SYM_S3": ("k_spmv_sym_s3", "k_sym_block_reduce"),
+    "SYM_S3": ("k_spmv_sym_sliced", "k_spmv_sym_s3", "k_sym_block_reduce"),
     "SYM_ATOMIC": ("k_zero", "k_spmv_sym_atomic"),
 }
 
@@ -199,28 +203,135 @@ def recorded_traffic(variant, n):
     return round(rep["traffic_bytes_per_spmv"]["total"]), os.path.relpath(path, ROOT)
 
 
-def cpu_baseline(A, x, budget_s=10.0):
-    """The CPU oracle (serial, FP64, compensated row sums) timed on the host:
-    repeated full SpMVs of the same matrix until about budget_s elapsed."""
-    import oracle
-    reps = 0
-    t0 = time.perf_counter()
-    while True:
-        oracle.spmv(A, x)
-        reps += 1
-        el = time.perf_counter() - t0
-        if el >= budget_s:
-            break
-    by = alg_bytes(A.n, A.nnz, 8, 8, 8)
-    host = "unknown"
+def host_cpu_info():
+    """The host CPU as /proc/cpuinfo and sysfs describe it."""
+    info = {"model_name": "unknown"}
     try:
         with open("/proc/cpuinfo") as fh:
-            host = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), host)
+            first = fh.read().split("\n\n")[0]
+        for ln in first.splitlines():
+            k, _, v = ln.partition(":")
+            k, v = k.strip(), v.strip()
+            if k == "model name":
+                info["model_name"] = v
+            elif k in ("cpu family", "model", "stepping", "cpu MHz", "cache size"):
+                info[k.replace(" ", "_")] = v
     except OSError:
         pass
-    return {"value": round(by * reps / el / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
-            "sample": f"{reps} full FP64 SpMVs of the n=2M power-law matrix ({el:.1f} s, 1 thread)",
-            "host_cpu": host, "host_nproc": os.cpu_count()}
+    try:
+        with open("/sys/devices/system/cpu/cpu0/cpufreq/cpuinfo_max_freq") as fh:
+            info["max_mhz"] = round(int(fh.read().strip()) / 1000)
+    except (OSError, ValueError):
+        pass
+    info["nproc"] = os.cpu_count()
+    try:
+        info["usable_cores"] = len(os.sched_getaffinity(0))
+    except OSError:
+        pass
+    return info
+
+
+class OracleLeg:
+    """The CPU oracle's part of the run, in a thread of its own that runs
+    beside the GPU legs (the oracle's C calls release the interpreter lock),
+    pinned to one host core:
+      - the baseline: full serial FP64 SpMVs of the power-law matrix for
+        about budget_s;
+      - the oracle's GMRES(30) + Jacobi to 1e-10 (MGS, b = 1) on the
+        power-law matrix and on the 27-point stencil 128^3 (full storage);
+      - the per-result error of the GPU's products handed over by check():
+        max over rows of abs(y - y_oracle) / sum abs(a x), against the
+        oracle on the FP64 inputs and on the FP32-rounded inputs."""
+
+    def __init__(self, A, x, budget_s=10.0, gmres=True):
+        import queue
+        import threading
+        self.A, self.x, self.budget_s, self.gmres = A, x, budget_s, gmres
+        self.result, self.error, self.errors = None, None, {}
+        self.q = queue.Queue()
+        self.thread = threading.Thread(target=self._run, daemon=True)
+        self.thread.start()
+
+    def check(self, name, A, x64, ys):
+        """Queue the GPU results ys = {label: (y, inputs)} of A x for
+        comparison; inputs is "f64" or "f32" (values and x rounded)."""
+        self.q.put((name, A, x64, ys))
+
+    def _run(self):
+        try:
+            self.result = self._measure()
+            while True:
+                item = self.q.get()
+                if item is None:
+                    break
+                self._compare(*item)
+        except Exception as e:  # reported, not fatal to the GPU legs
+            self.error = repr(e)
+
+    def _compare(self, name, A, x64, ys):
+        import gen
+        import oracle
+        ref = {"f64": oracle.spmv(A, x64)}
+        if any(inp == "f32" for _, inp in ys.values()):
+            A32 = gen.CSR(A.n, A.ncols, A.rowptr, A.colind, A.val.astype(np.float32).astype(np.float64),
+                          sym_lower=A.sym_lower)
+            ref["f32"] = oracle.spmv(A32, x64.astype(np.float32).astype(np.float64))
+        res = {}
+        for label, (y, inp) in ys.items():
+            yo, so = ref["f64"]
+            e = fp32_error_per_result(y, yo, so)
+            if inp == "f32":
+                yr, sr = ref["f32"]
+                e["vs_rounded_inputs"] = fp32_error_per_result(y, yr, sr)["max_abs_dy_over_s"]
+            res[label] = e
+        self.errors[name] = res
+
+    def _measure(self):
+        import gen
+        import oracle
+        host = host_cpu_info()
+        core = max(os.sched_getaffinity(0))
+        os.sched_setaffinity(0, {core})  # this thread only
+        A, x = self.A, self.x
+        reps = 0
+        t0 = time.perf_counter()
+        while True:
+            oracle.spmv(A, x)
+            reps += 1
+            el = time.perf_counter() - t0
+            if el >= self.budget_s:
+                break
+        by = alg_bytes(A.n, A.nnz, 8, 8, 8)
+        out = {"value": round(by * reps / el / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+               "sample": f"{reps} full FP64 SpMVs of the n={A.n} power-law matrix ({el:.1f} s, 1 thread)",
+               "pinned_core": core, "host": host}
+        if self.gmres:
+            for name, M in (("gmres_powerlaw", A), ("gmres_sym27", None)):
+                if M is None:
+                    L = gen.stencil27(128, lower=True)
+                    rp, ci, v = oracle.sym_expand(L)
+                    M = gen.CSR(L.n, L.n, rp, ci, v)
+                t0 = time.perf_counter()
+                r = oracle.gmres(M, np.ones(M.n), m=30, tol=1e-10, precond=1)
+                out[name] = {"s": round(time.perf_counter() - t0, 3), "iters": r["iters"], "cycles": r["cycles"],
+                             "relres": r["relres"], "status": r["status"],
+                             "what": "oracle GMRES(30), MGS, right Jacobi, b = 1, x0 = 0, to 1e-10, 1 core"}
+        return out
+
+    def join(self):
+        self.q.put(None)
+        self.thread.join()
+        if self.error:
+            return {"error": self.error}, self.errors
+        return self.result, self.errors
+
+
+def fp32_error_per_result(y, yo, s):
+    """max over rows of abs(y - yo) / s, and whether the rows with s = 0
+    are exactly 0."""
+    nz = s > 0
+    return {"max_abs_dy_over_s": float(np.max(np.abs(y[nz] - yo[nz]) / s[nz])) if nz.any() else 0.0,
+            "zero_rows_exact": bool(np.all(y[~nz] == 0))}
 
 
 def gmres_pair(ctx, xab, torch, plan, n, reps=3):
@@ -422,7 +533,7 @@ def shard_leg(ctx, xab, torch, gen, A):
     return out
 
 
-def sym_stencil_leg(ctx, xab, torch, gen, gmres=True, eig=True):
+def sym_stencil_leg(ctx, xab, torch, gen, gmres=True, eig=True, oracle_leg=None):
     """Symmetric SpMV from lower storage on the 128^3 27-point stencil:
     TIME-selected implementation, FP64 and FP32 values (FP64 accumulation),
     then GMRES(30) FP64 vs mixed precision on it, and the Lanczos leg."""
@@ -435,6 +546,14 @@ def sym_stencil_leg(ctx, xab, torch, gen, gmres=True, eig=True):
     cold64 = cold_spmv_us(ctx, torch, plan, x, y)
     x32, y32 = x.float(), y.float()
     ms32 = ctx.time_spmv(plan, x32, y32, acc=xab.F64, warmup=5, reps=100)
+    if oracle_leg:
+        xh = x.cpu().numpy()
+        ys = {"fp64": (ctx.spmv(plan, x).cpu().numpy(), "f64"),
+              "fp32_values_acc_fp64": (ctx.spmv(plan, x32, ydtype=torch.float32, acc=xab.F64).double().cpu().numpy(),
+                                       "f32"),
+              "fp32_values_acc_fp32": (ctx.spmv(plan, x32, ydtype=torch.float32, acc=xab.F32).double().cpu().numpy(),
+                                       "f32")}
+        oracle_leg.check("sym27", L, xh, ys)
     by64, by32 = alg_bytes(L.n, L.nnz, 8, 8, 8), alg_bytes(L.n, L.nnz, 4, 4, 4)
     out = {"workload": f"27-point stencil 128^3, lower triangle stored: n={L.n} nnz_L={L.nnz}",
            "selected": plan.describe(), "chosen_class": int(info.chosen),
@@ -507,6 +626,33 @@ def batch_leg(ctx, xab, torch, gen):
     return out
 
 
+def trans4_leg(ctx, xab, torch, gen):
+    """The very unbalanced trans4 shape of the paper's segment-length sweep
+    (one row of 114,910 entries among 116,835 rows, 749,800 entries):
+    device time per FP64 SpMV (HIP events, 100 launches) of the branchless
+    segmented scan at J = 1 .. 32 entries per lane against the row-based
+    split at 1, 8 and 64 lanes per row and the nnz-based split."""
+    A = gen.trans4_like()
+    M = ctx.matrix_from_csr(A)
+    x = torch.from_numpy(gen.uniform_vec(A.n, 22)).cuda()
+    y = torch.empty(A.n, dtype=torch.float64, device="cuda")
+    out = {"workload": f"trans4-shaped CSR n={A.n} nnz={A.nnz}, longest row {int(np.diff(A.rowptr).max())}"}
+
+    def t(variant, **kw):
+        P = ctx.plan(M, variant, **kw)
+        ms = ctx.time_spmv(P, x, y, warmup=5, reps=100)
+        P.close()
+        return round(ms * 1e3, 2)
+    out["bss_us_by_j"] = {j: t(xab.BSS, j_per_lane=j) for j in (1, 2, 4, 8, 16, 32)}
+    out["row_us_by_lanes"] = {sl: t(xab.ROW, lanes_per_row=sl) for sl in (1, 8, 64)}
+    out["nnz_us_by_tile"] = {tt: t(xab.NNZ, tile_nnz=tt) for tt in (2048, 8192)}
+    best_bss = min(out["bss_us_by_j"].values())
+    out["bss_best_vs_row1"] = round(out["row_us_by_lanes"][1] / best_bss, 2)
+    out["bss_best_vs_best_row"] = round(min(out["row_us_by_lanes"].values()) / best_bss, 2)
+    M.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -540,6 +686,7 @@ def main():
     log("generating the power-law matrix")
     A = gen.powerlaw(args.n, seed=2)
     x64 = gen.uniform_vec(A.n, 12)
+    oracle_leg = None if args.no_cpu else OracleLeg(A, x64, gmres=not args.no_gmres)
     ctx = xab.Context(0)
     M = ctx.matrix_from_csr(A, with_f32=True)
     xd = torch.from_numpy(x64).cuda()
@@ -606,6 +753,14 @@ def main():
     by32 = alg_bytes(A.n, A.nnz, 4, 4, 4)
     fp32 = {"gbs": round(by32 / (ev32 * 1e-3) / 1e9, 1), "us": round(ev32 * 1e3, 2),
             "frac": round(by32 / (ev32 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "speedup_vs_fp64": round(ev_ms / ev32, 3)}
+    if oracle_leg:
+        # results handed to the oracle leg for the per-result error
+        ys = {"fp64": (ctx.spmv(plan, xd).cpu().numpy(), "f64"),
+              "fp32_values_acc_fp64": (ctx.spmv(plan32, xd32, ydtype=torch.float32, acc=xab.F64).double().cpu().numpy(),
+                                       "f32"),
+              "fp32_values_acc_fp32": (ctx.spmv(plan32, xd32, ydtype=torch.float32, acc=xab.F32).double().cpu().numpy(),
+                                       "f32")}
+        oracle_leg.check("powerlaw", A, x64, ys)
 
     gm = None
     if not args.no_gmres:
@@ -621,7 +776,8 @@ def main():
     c3 = None
     if not args.no_c3:
         log("symmetric 27-point stencil 128^3 (lower storage)")
-        c3 = sym_stencil_leg(ctx, xab, torch, gen, gmres=not args.no_gmres, eig=not args.no_eig)
+        c3 = sym_stencil_leg(ctx, xab, torch, gen, gmres=not args.no_gmres, eig=not args.no_eig,
+                             oracle_leg=oracle_leg)
     shard = None
     if not args.no_shard:
         log("one GPU's share of an 8-way row decomposition")
@@ -631,10 +787,16 @@ def main():
         log("batch of 512 systems: batched SpMV and BiCGStab")
         c4 = batch_leg(ctx, xab, torch, gen)
 
-    cpu = None
-    if not args.no_cpu:
-        log("CPU oracle baseline")
-        cpu = cpu_baseline(A, x64)
+    stress = trans4_leg(ctx, xab, torch, gen)
+
+    cpu, errs = None, {}
+    if oracle_leg:
+        log("waiting for the CPU oracle leg")
+        cpu, errs = oracle_leg.join()
+        if "powerlaw" in errs:
+            fp32["error_per_result"] = errs["powerlaw"]
+        if c3 is not None and "sym27" in errs:
+            c3["error_per_result"] = errs["sym27"]
 
     out = {
         "metric": "SpMV GB/s & % HBM peak (FP64 vs FP32-val); GMRES s to 1e-10 residual",
@@ -662,6 +824,7 @@ def main():
                      "plan_mb_per_class": plan_mb, "memory_policy": memory},
         "gmres": gm,
         "sym27": c3,
+        "trans4_stress": stress,
         "batch512": c4,
         "shard_of_8": shard,
         "arnoldi": arn,
