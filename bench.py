@@ -190,6 +190,37 @@ def pmc_summary(fetch_dir, write_dir, out, variant, n, cmd_fetch, cmd_write):
     print(json.dumps(rep["traffic_bytes_per_spmv"]))
 
 
+def counter_summary(dirs, out, variant, n, nnz, cmds):
+    """Reduce counter runs (one directory each) to a markdown table: per
+    kernel of one SpMV of `variant`, each counter's mean per dispatch; with
+    the L2 (TCC) hit and miss counts, the hit ratio, and the L2 requests
+    per stored entry."""
+    pers = [_counter_csv(d) for d in dirs]
+    names = sorted({k for per in pers for k, _ in per})
+    lines = [f"# {variant} SpMV (FP64) on the power-law CSR n={n}, nnz={nnz}: L2 and request counters", "",
+             "Commands (repository root, one counter set per run):", "", "```"] + list(cmds) + ["```", ""]
+    for frag in VARIANT_KERNELS[variant]:
+        cand = [k for k in names if f"::{frag}<" in k and "float" not in k]
+        if len(cand) != 1:
+            raise SystemExit(f"kernel {frag}: {len(cand)} FP64 instances found")
+        vals = {}
+        for per in pers:
+            for (kn, ctr), v in per.items():
+                if kn == cand[0]:
+                    vals[ctr] = sum(v) / len(v)
+        lines += [f"## `{frag}`", "", "| Counter | Mean per dispatch |", "|---|---|"]
+        lines += [f"| {c} | {v:,.0f} |" for c, v in sorted(vals.items())]
+        hit, miss = vals.get("TCC_HIT_sum"), vals.get("TCC_MISS_sum")
+        if hit is not None and miss is not None and hit + miss > 0:
+            lines += [f"| L2 hit ratio (TCC_HIT / (TCC_HIT + TCC_MISS)) | {hit / (hit + miss):.4f} |"]
+        if "TCC_REQ_sum" in vals:
+            lines += [f"| L2 requests per stored entry | {vals['TCC_REQ_sum'] / nnz:.3f} |"]
+        lines.append("")
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines))
+    print("\n".join(lines))
+
+
 def recorded_traffic(variant, n):
     """HBM bytes per SpMV from the committed counter summary, if it still
     describes the current kernels; (value, note)."""
@@ -626,6 +657,30 @@ def batch_leg(ctx, xab, torch, gen):
     return out
 
 
+def xcb_gather_reference(ctx, xab, torch, gen, A, ev_ms, j_per_lane):
+    """What the random x gathers cost the column-blocked SpMV: the same
+    matrix with every column moved into the first 2048 columns of its own
+    column block (same rows, lengths, values and blocks, so the same entry
+    stream, tiles and partial sums, but each XCD gathers from a 16 KB slice
+    of x that stays in its CUs' L1 caches), timed with the same entries per
+    lane."""
+    k = (A.colind.astype(np.int64) * 8) // A.ncols
+    lo = (k * A.ncols) // 8
+    ci = (lo + A.colind.astype(np.int64) % 2048).astype(np.int32)
+    L = gen.CSR(A.n, A.ncols, A.rowptr, ci, A.val, name="powerlaw_local_columns")
+    M = ctx.matrix_from_csr(L)
+    P = ctx.plan(M, xab.XCB, j_per_lane=j_per_lane)
+    x = torch.from_numpy(gen.uniform_vec(A.n, 12)).cuda()
+    y = torch.empty(A.n, dtype=torch.float64, device="cuda")
+    ms = ctx.time_spmv(P, x, y, warmup=5, reps=100)
+    P.close()
+    M.close()
+    return {"random_columns_us": round(ev_ms * 1e3, 2), "local_columns_us": round(ms * 1e3, 2),
+            "random_gather_share": round(1.0 - ms / ev_ms, 4),
+            "gathers_per_s": round(A.nnz / (ev_ms * 1e-3) / 1e9, 1), "unit_gathers": "G/s",
+            "what": "same matrix, each column moved into the first 2048 columns of its XCD column block"}
+
+
 def trans4_leg(ctx, xab, torch, gen):
     """The very unbalanced trans4 shape of the paper's segment-length sweep
     (one row of 114,910 entries among 116,835 rows, 749,800 entries):
@@ -664,8 +719,14 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 512-system batch leg")
     ap.add_argument("--no-eig", action="store_true", help="skip the Lanczos and Arnoldi legs")
     ap.add_argument("--no-shard", action="store_true", help="skip the one-GPU-share leg")
+    ap.add_argument("--no-gather-ref", action="store_true",
+                    help="skip the local-column XCB reference (counter runs: keeps its dispatches out of the means)")
     ap.add_argument("--n", type=int, default=2_000_000)
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
+    ap.add_argument("--counter-summary", nargs="+", metavar="DIR",
+                    help="reduce counter runs (L2 hits, misses, requests) to a markdown table at --out")
+    ap.add_argument("--nnz", type=int, default=0, help="stored entries of the workload (--counter-summary)")
+    ap.add_argument("--cmds", nargs="*", default=[], help="the counter runs' commands (--counter-summary)")
     ap.add_argument("--variant", default="XCB")
     ap.add_argument("--out")
     ap.add_argument("--cmd-fetch", default="")
@@ -673,6 +734,9 @@ def main():
     args = ap.parse_args()
     if args.pmc_summary:
         pmc_summary(*args.pmc_summary, args.out, args.variant, args.n, args.cmd_fetch, args.cmd_write)
+        return
+    if args.counter_summary:
+        counter_summary(args.counter_summary, args.out, args.variant, args.n, args.nnz, args.cmds)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding "
@@ -746,6 +810,9 @@ def main():
 
     cold = cold_spmv_us(ctx, torch, plan, xd, y)
     stream = stream_rates(torch)
+    gather_ref = None
+    if variant == "XCB" and not args.no_gather_ref:
+        gather_ref = xcb_gather_reference(ctx, xab, torch, gen, A, ev_ms, plan.describe()["j_per_lane"])
 
     # FP32 values and x, FP64 accumulation, FP32 y (the inner SpMV of GMRES-IR)
     plan32 = ctx.plan_class(M, chosen)
@@ -817,6 +884,7 @@ def main():
         "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
         "cold_us_per_step": cold,
         "stream": dict(stream, frac_of_read=round(gbs / stream["read_gbs"], 4)),
+        "xcb_gather_reference": gather_ref,
         "gflops": round(2 * A.nnz / (wall / args.steps) / 1e9, 1),
         "fp32_values": fp32,
         "selector": {"chosen_class": chosen, "us_per_class": times, "select_ms": round(float(info.select_ms), 2),

@@ -133,7 +133,9 @@ typedef enum {
 typedef struct {
     int32_t lanes_per_row; /* ROW, SYM_ATOMIC: 1, 2, 4, ..., 64 */
     int32_t tile_nnz;      /* NNZ, SYM_S3: target entries per tile (>= 256) */
-    int32_t j_per_lane;    /* BSS: entries per lane, 1..32 */
+    int32_t j_per_lane;    /* BSS, XCB: entries per lane, a power of two in 1..32; XCB also
+                              takes 0: the largest of 4, 8, 16, 32 that leaves at least
+                              4096 tiles of 256 * j_per_lane entries (xab_plan_info reports it) */
     int32_t col_block;     /* SYM_S3: column block size C of the touch map (power of two) */
     int32_t tile_rows;     /* SYM_S3: maximum rows per tile (<= 2048); SELL: sorting window
                               (a multiple of 64, at most 1024) */
@@ -198,8 +200,10 @@ void xab_plan_destroy(xab_plan *plan);
 /* Read back plan arrays (for checking).  which: 0 nnz-split b / sym tiles b,
  * 1 BSS row_lo, 2 BSS tile_row, 3 BSS carry_row, 4 tm_ptr, 5 tm_tile,
  * 6 tile_ptr, 7 tile_blk, 8 tile_slot, 9 XCB per-block row pointers
- * (8 x (nrows+1), block-major), 10 XCB column indices in block order,
- * bit 31 set on the first entry of each row within its block, 11 SELL
+ * (8 x (nrows+1), block-major), 10 XCB column indices in block order
+ * (the device copy stores each full tile in 16-byte groups interleaved
+ * over the lanes; this reports the plain order), bit 31 set on the first
+ * entry of each row within its block, 11 SELL
  * row order (original row of each ordered row), 12 SELL ordered row
  * lengths, 13 SELL chunk widths, 14 SELL padded column indices, 15 BCSR
  * block row pointers, 16 BCSR block columns, 17 BCSR position masks, 18

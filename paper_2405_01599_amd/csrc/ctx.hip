@@ -153,7 +153,7 @@ const char *xab_status_str(int s) {
 // The selector's action space.  General: row-split with 1, 8 or 64 lanes
 // per row; nnz-split with 2048 or 8192 entries per workgroup; segmented scan
 // with 4, 8, 16 or 32 entries per lane; column-blocked segmented scan with
-// 4 entries per lane; sliced ELLPACK with chunks of 64 rows sorted in
+// its entries per lane chosen from the matrix size; sliced ELLPACK with chunks of 64 rows sorted in
 // windows of 1024.  Symmetric: atomic transpose (baseline) and
 // zero-block-omitted reduction with 64- or 256-row blocks (tiles of about
 // 8192 entries and at most 1024 rows).
@@ -178,7 +178,7 @@ int xab_class_params(int32_t k, xab_variant *v, xab_params *p) {
         case 9: *v = XAB_SYM_ATOMIC; q.lanes_per_row = 8; break;
         case 10: *v = XAB_SYM_S3; q.col_block = 64; q.tile_nnz = 8192; q.tile_rows = 1024; break;
         case 11: *v = XAB_SYM_S3; q.col_block = 256; q.tile_nnz = 8192; q.tile_rows = 1024; break;
-        case 12: *v = XAB_XCB; q.j_per_lane = 4; break;
+        case 12: *v = XAB_XCB; q.j_per_lane = 0; break;
         case 13: *v = XAB_SELL; q.tile_rows = 1024; break;
         case 14: *v = XAB_BCSR; break;
         default: return XAB_E_SHAPE;

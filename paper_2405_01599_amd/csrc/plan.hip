@@ -9,6 +9,7 @@
 
 #include "internal.h"
 #include "sym_layout.h"
+#include <type_traits>
 
 namespace {
 
@@ -424,6 +425,27 @@ __global__ __launch_bounds__(64) void k_sym_slice_fill(const int32_t *rowptr, co
             }
         }
     }
+}
+
+// The column-blocked copy's full tiles are stored in 16-byte groups
+// interleaved over the lanes: with G = min(J, 16 / element size) entries
+// per group, entry q of lane t of a tile of T = 256 J entries (block
+// position tile T + t J + q) moves to tile T + (q / G) 256 G + t G + q % G,
+// so each wide load of the SpMV reads 256 consecutive groups (G = J keeps
+// the plain order); a block's last, partial tile keeps its order
+template <class T>
+__global__ void k_xcb_interleave(const T *in, T *out, int64_t nnz, int32_t J) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nnz) return;
+    const int64_t TT = 256 * (int64_t)J;
+    const int64_t G = std::min<int64_t>(J, 16 / (int64_t)sizeof(T));
+    const int64_t tile = i / TT;
+    int64_t dst = i;
+    if (tile < nnz / TT) {
+        const int64_t r = i - tile * TT, t = r / J, q = r % J;
+        dst = tile * TT + (q / G) * 256 * G + t * G + q % G;
+    }
+    out[dst] = in[i];
 }
 
 // dense[p] = 1 when every row of tile p (rows [b[p], b[p+1])) has an entry
@@ -873,6 +895,13 @@ int xab_build_plan(xab_ctx *ctx, const xab_matrix *A, xab_variant v, const xab_p
             break;
         case XAB_BSS:
         case XAB_XCB:
+            if (v == XAB_XCB && p.j_per_lane == 0) {
+                // entries per lane from the size: the largest of 4, 8, 16 and
+                // 32 that still cuts the matrix into at least 4096 tiles (16
+                // per CU); more entries per lane keep more gathers in flight
+                p.j_per_lane = 4;
+                while (p.j_per_lane < 32 && A->nnz >= (int64_t)4096 * 256 * (2 * p.j_per_lane)) p.j_per_lane *= 2;
+            }
             if (p.j_per_lane < 1 || p.j_per_lane > 32 || !pow2(p.j_per_lane))
                 return xab_fail(ctx, XAB_E_UNSUPPORTED, "j_per_lane must be a power of two in [1, 32]");
             break;
@@ -1149,6 +1178,28 @@ int xab_build_plan(xab_ctx *ctx, const xab_matrix *A, xab_variant v, const xab_p
         if (e == hipSuccess) e = hipStreamSynchronize(st);  // crowptr is freed next
         xab_dfree(ctx, crowptr);
         CHECKED(hip_ok(ctx, e, "column-block tiles"));
+        // full tiles in lane-interleaved 16-byte groups (columns and each value copy)
+        auto interleave = [&](auto *&arr) -> hipError_t {
+            using E = std::remove_reference_t<decltype(*arr)>;
+            if (!arr || nnz == 0 || p.j_per_lane <= (int)(16 / sizeof(E))) return hipSuccess;
+            E *out = (E *)xab_dalloc(ctx, sizeof(E) * (size_t)nnz);
+            if (!out) return hipErrorOutOfMemory;
+            for (int k = 0; k < KB; ++k) {
+                const int64_t b = pl->xcb_base[k], m = pl->xcb_base[k + 1] - b;
+                if (m > 0)
+                    hipLaunchKernelGGL((k_xcb_interleave<E>), dim3(grid_for(m, 256)), dim3(256), 0, st, arr + b, out + b,
+                                       m, p.j_per_lane);
+            }
+            hipError_t ee = hipGetLastError();
+            if (ee == hipSuccess) ee = hipStreamSynchronize(st);
+            xab_dfree(ctx, arr);
+            arr = out;
+            return ee;
+        };
+        e = interleave(pl->xcb_colind);
+        if (e == hipSuccess) e = interleave(pl->xcb_val64);
+        if (e == hipSuccess) e = interleave(pl->xcb_val32);
+        CHECKED(hip_ok(ctx, e, "interleaved tiles"));
     } else {  // XAB_SYM_S3
         const int32_t C = p.col_block;
         const int32_t bmax = xab::sym::kExtCap / C;
@@ -1423,6 +1474,22 @@ int xab_plan_array(const xab_plan *pl, int32_t which, int32_t *h_out, int64_t *l
     xab_ctx *ctx = pl->ctx;
     XAB_HIP(ctx, hipMemcpyAsync(h_out, src, sizeof(int32_t) * m, hipMemcpyDeviceToHost, ctx->stream));
     XAB_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (which == 10 && pl->params.j_per_lane > 4) {
+        // the copy keeps full tiles in lane-interleaved groups of 4: report block order
+        const int64_t TT = 256 * (int64_t)pl->params.j_per_lane, J = pl->params.j_per_lane, G = 4;
+        std::vector<int32_t> t((size_t)TT);
+        for (int k = 0; k < xab_plan::kXcb; ++k) {
+            const int64_t b = pl->xcb_base[k], nk = pl->xcb_base[k + 1] - b;
+            for (int64_t tile = 0; tile < nk / TT; ++tile) {
+                int32_t *blk = h_out + b + tile * TT;
+                for (int64_t r = 0; r < TT; ++r) {
+                    const int64_t lt = r / J, q = r % J;
+                    t[(size_t)r] = blk[(q / G) * 256 * G + lt * G + q % G];
+                }
+                std::copy(t.begin(), t.end(), blk);
+            }
+        }
+    }
     return XAB_OK;
 }
 

@@ -19,7 +19,8 @@ unsigned grid_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 // dealt round-robin to the XCDs; giving block k every id with
 // id % kXcds == k keeps its gathers on one XCD, whose private L2 then holds
 // that block's slice of x.
-// Tile t of block k covers entries [tT, tT + T).  Its first entry lies in
+// Tile t of block k covers entries [tT, tT + T) (a full tile is stored in
+// lane-interleaved 16-byte groups, see load_tile_grouped).  Its first entry lies in
 // compressed row row0[t], so entry e lies in row
 // row0[t] - head(tT) + (heads in [tT, e]).  A block writes one partial per
 // compressed row into its slice of Y; the combine kernel adds, for every
@@ -37,11 +38,33 @@ struct XcbArgs {
     int64_t P[kXcds];
 };
 
+// A full tile stores each lane's J entries in groups of G = min(J, 16 /
+// element size) consecutive entries, group c of lane t at (c 256 + t) G:
+// each 16-byte (or narrower) load of the workgroup reads one contiguous run
+template <class T, int J>
+__device__ __forceinline__ void load_tile_grouped(const T *__restrict__ p, int tid, T (&out)[J]) {
+    constexpr int G = J < 16 / (int)sizeof(T) ? J : 16 / (int)sizeof(T);
+    if constexpr (G == 1) {
+#pragma unroll
+        for (int q = 0; q < J; ++q) out[q] = __builtin_nontemporal_load(p + q * kNT + tid);
+    } else {
+        typedef T V __attribute__((ext_vector_type(G)));
+        const V *vp = reinterpret_cast<const V *>(p);
+#pragma unroll
+        for (int c = 0; c < J / G; ++c) {
+            const V w = __builtin_nontemporal_load(vp + c * kNT + tid);
+#pragma unroll
+            for (int i = 0; i < G; ++i) out[c * G + i] = w[i];
+        }
+    }
+}
+
 template <class VT, class XT, class AT, int J>
 __global__ __launch_bounds__(kNT) void k_spmv_xcb(XcbArgs a, const XT *__restrict__ x) {
     constexpr int T = kNT * J;
     constexpr int NW = kNT / kWave;
     __shared__ CSeg<AT> wave_tot[NW];
+    __shared__ AT ys[T];  // partials of the rows that start in the tile
     const int k = blockIdx.x % kXcds;
     const int64_t t = blockIdx.x / kXcds;
     const int64_t nnz = a.nnz[k];
@@ -55,9 +78,9 @@ __global__ __launch_bounds__(kNT) void k_spmv_xcb(XcbArgs a, const XT *__restric
     int32_t cr[J];
     VT v[J];
     const int64_t base = A0 + (int64_t)tid * J;
-    if (base + J <= c1) {
-        load_run_full<int32_t, J>(ci, base, cr);
-        load_run_full<VT, J>(va, base, v);
+    if (A0 + T <= nnz) {
+        load_tile_grouped<int32_t, J>(ci + A0, tid, cr);
+        load_tile_grouped<VT, J>(va + A0, tid, v);
     } else {
 #pragma unroll
         for (int q = 0; q < J; ++q) {
@@ -101,13 +124,14 @@ __global__ __launch_bounds__(kNT) void k_spmv_xcb(XcbArgs a, const XT *__restric
     const CSeg<AT> in = lane == 0 ? pre : cseg_combine(pre, ex);
 
     // pass 2: a head closes the open segment: a row of this tile (heads
-    // before it > 0) or the carried-in row's part in this tile
+    // before it > 0), staged in LDS so that the tile's rows leave in one
+    // contiguous run, or the carried-in row's part in this tile
     AT acc = in.v;
     int cnt = in.c;
 #pragma unroll
     for (int q = 0; q < J; ++q) {
         if (hd[q]) {
-            if (cnt > 0) Y[r0 + cnt] = acc;
+            if (cnt > 0) ys[cnt - 1] = acc;
             else if (!h0) ((AT *)a.carry_val[k])[t] = acc;
             acc = p[q];
             ++cnt;
@@ -115,19 +139,24 @@ __global__ __launch_bounds__(kNT) void k_spmv_xcb(XcbArgs a, const XT *__restric
             acc += p[q];
         }
     }
+    // rows r0 + 1 .. r0 + total.c start in the tile; the last one is
+    // complete here only when the next tile starts a row
+    const int nrows = total.c > 0 ? total.c - 1 + hnext : 0;
     if (tid == 0) {
         int32_t tr = -1;
         if (total.c == 0) {
             // no row starts in the tile: all of it belongs to the carried row
             ((AT *)a.carry_val[k])[t] = total.v;
         } else if (hnext) {
-            Y[r0 + total.c] = total.v;
+            ys[total.c - 1] = total.v;
         } else {
             tr = r0 + total.c;
             ((AT *)a.tail_val[k])[t] = total.v;
         }
         a.tail_row[k][t] = tr;
     }
+    __syncthreads();
+    for (int i = tid; i < nrows; i += kNT) Y[r0 + 1 + i] = ys[i];
 }
 
 // rows cut by a tile end: their start partial plus the carries of the

@@ -62,7 +62,7 @@ def test_class_table():
     assert [s[0] for s in seen[3:5]] == [xab.NNZ] * 2 and [s[2] for s in seen[3:5]] == [2048, 8192]
     assert [s[0] for s in seen[5:9]] == [xab.BSS] * 4 and [s[3] for s in seen[5:9]] == [4, 8, 16, 32]
     assert seen[9][0] == xab.SYM_ATOMIC and seen[10][0] == seen[11][0] == xab.SYM_S3
-    assert seen[12][0] == xab.XCB and seen[12][3] == 4
+    assert seen[12][0] == xab.XCB and seen[12][3] == 0  # entries per lane chosen from the size
     assert seen[13][0] == xab.SELL and xab.class_params(13)[1].tile_rows == 1024
     assert seen[14][0] == xab.BCSR
     with pytest.raises(xab.XabError):

@@ -46,7 +46,8 @@ def test_c2_spmv_fp64_and_fp32_values(ctx, c2):
     x = gen.uniform_vec(A.n, 12)
     yo, s = oracle.spmv(A, x)
     M = ctx.matrix_from_csr(A, with_f32=True)
-    P = ctx.plan_class(M, 12)  # XCB J=4, the class the selector picks here
+    P = ctx.plan_class(M, 12)  # XCB, the class the selector picks here
+    assert P.describe()["j_per_lane"] == 32  # 40.2M entries: 4908 tiles of 8192
     y = ctx.spmv(P, dev(x)).cpu().numpy()
     assert np.all(np.abs(y - yo) <= 1e-12 * s)
     # FP32 values and x, FP64 accumulation and y: against the rounded inputs

@@ -234,22 +234,43 @@ def test_bss_plan_bitexact(ctx):
 
 
 def test_xcb_plan_bitexact(ctx):
+    # J = 16 and 32 store full tiles interleaved in groups; the read-back is
+    # in block order whatever the device layout
     for name, A in GENERAL.items():
         M = ctx.matrix_from_csr(A)
-        P = ctx.plan(M, xab.XCB, j_per_lane=4)
         rp, ci = oracle.plan_xcb(A, 8, flagged=True)
-        assert np.array_equal(P.array(9), rp.reshape(-1)), name
-        assert np.array_equal(P.array(10), ci), name
+        for J in (4, 16, 32):
+            P = ctx.plan(M, xab.XCB, j_per_lane=J)
+            assert np.array_equal(P.array(9), rp.reshape(-1)), (name, J)
+            assert np.array_equal(P.array(10), ci), (name, J)
 
 
-@pytest.mark.parametrize("J", [1, 4, 8, 32])
+@pytest.mark.parametrize("J", [1, 2, 4, 8, 16, 32])
 def test_xcb_all_lane_widths(ctx, J):
+    # about 125k entries per column block: many full tiles and a ragged
+    # last tile in each block at every J
     A = _int_version(gen.powerlaw(50_000, seed=2))
     x = gen.int_vec(A.ncols, 2)
     yo, _ = oracle.spmv(A, x)
-    M = ctx.matrix_from_csr(A)
+    M = ctx.matrix_from_csr(A, with_f32=True)
     P = ctx.plan(M, xab.XCB, j_per_lane=J)
     assert np.array_equal(ctx.spmv(P, dev(x)).cpu().numpy(), yo)
+    # FP32 values and x (integers, sums below 2^24: exact in either accumulation)
+    for acc in (xab.F32, xab.F64):
+        y32 = ctx.spmv(P, dev(x, torch.float32), ydtype=torch.float32, acc=acc).double().cpu().numpy()
+        assert np.array_equal(y32, yo), acc
+
+
+def test_xcb_size_chosen_lane_width(ctx):
+    # class 12 leaves the entries per lane to the plan: the largest of 4, 8,
+    # 16, 32 that keeps at least 4096 tiles of 256 J entries
+    A = gen.powerlaw(50_000, seed=2)
+    M = ctx.matrix_from_csr(A)
+    P = ctx.plan_class(M, 12)
+    assert P.variant == xab.XCB and P.describe()["j_per_lane"] == 4
+    x = gen.uniform_vec(A.ncols, 3)
+    yo, s = oracle.spmv(A, x)
+    assert np.all(np.abs(ctx.spmv(P, dev(x)).cpu().numpy() - yo) <= 1e-12 * s)
 
 
 @pytest.mark.parametrize("J", [1, 2, 4, 8, 16, 32])
