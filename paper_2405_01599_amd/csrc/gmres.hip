@@ -12,6 +12,16 @@
 // computed in FP64 at every restart: the recurrence estimate only ends a
 // cycle (the accuracy policy's outer check against "fault convergence",
 // section 3.3.2).
+//
+// The Hessenberg column, the Givens rotations and the residual recurrence
+// of each Arnoldi step run on the device (one small kernel at the end of
+// the step), so a cycle's steps are queued back to back: the host never
+// waits for the step the GPU is running.  It waits on the event of the
+// step before that one (to stop queueing once a step has met the
+// threshold or broken down), and on the running step too only when the
+// recurrence is about to meet the threshold.  A step queued after the
+// stopping one computes into the next basis slot and leaves the rotated
+// system alone.  The host reads the rotated system back once per cycle.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -24,6 +34,26 @@ namespace {
 
 constexpr double kEta = 0.70710678118654752440;  // DGKS threshold 1/sqrt(2)
 
+// What the step kernel leaves where the host can read it without a copy
+// (coherent pinned memory): the last step done, the stop flag and the
+// recurrence residuals |g_0| .. |g_k|.
+struct Mirror {
+    int done;
+    int k;
+    int stop;
+    int breakdown;
+    int by_rec;
+    double absg[64];
+};
+
+// Device state of one cycle: the rotated Hessenberg matrix (row i, column
+// j at H[i ld + j]), the rotations, the rotated right-hand side g.
+struct CycleState {
+    int k;
+    int stop;
+    double tol_abs;
+};
+
 struct Work {
     xab_ctx *ctx = nullptr;
     void *base = nullptr;
@@ -33,13 +63,89 @@ struct Work {
     int *gate = nullptr;
     void *V = nullptr, *w = nullptr, *z = nullptr;
     int64_t ldv = 0;
-    size_t small_bytes = 0;  // h1 .. gate, read back in one copy per step
-    double *host = nullptr;  // pinned mirror of that region
+    double *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr;  // rotated system (device)
+    CycleState *st = nullptr;
+    size_t sys_bytes = 0;    // H .. g, read back once per cycle
+    double *host = nullptr;  // pinned: the rotated system's read-back, then y
+    Mirror *mir = nullptr;   // coherent pinned, written by the step kernel
+    Mirror *mir_dev = nullptr;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     ~Work() {
         if (base) xab_dfree(ctx, base);
         if (host) (void)hipHostFree(host);
+        if (mir) (void)hipHostFree(mir);
+        for (auto e : ev)
+            if (e) (void)hipEventDestroy(e);
     }
 };
+
+// Step j's Hessenberg column from the Gram-Schmidt coefficients (h1, plus
+// h2 when the DGKS gate fired) and the new norm; the earlier rotations
+// applied to it, the rotation that zeroes h_{j+1,j}, g updated, and the
+// step's stop decision (breakdown, or |g_{j+1}| at the threshold).  One
+// wave: the lanes stage the column and the rotations in LDS, lane 0 runs
+// the chain of at most 63 rotations (row i + 1 carried in a register).
+__global__ __launch_bounds__(64) void k_gmres_givens(int j, int ld, int dgks, const double *__restrict__ h1,
+                                                     const double *__restrict__ h2, const double *__restrict__ sc,
+                                                     const int *__restrict__ gate_p, double *__restrict__ H,
+                                                     double *__restrict__ cs, double *__restrict__ sn,
+                                                     double *__restrict__ g, CycleState *__restrict__ st, Mirror *mir) {
+    __shared__ double col[64], rc[64], rs[64];
+    const int t = threadIdx.x;
+    if (st->stop) {
+        // queued after the stopping step: leave the rotated system alone
+        if (t == 0) mir->done = j;
+        return;
+    }
+    const int gate = dgks ? *gate_p : 0;
+    if (t <= j) col[t] = h1[t] + (gate ? h2[t] : 0.0);
+    if (t < j) {
+        rc[t] = cs[t];
+        rs[t] = sn[t];
+    }
+    __syncthreads();
+    if (t == 0) {
+        const double hn = sqrt(!dgks ? h1[j + 1] : (gate ? sc[0] : h2[j + 1]));
+        double cur = col[0];  // row i of the column after rotations 0 .. i - 1
+        for (int i = 0; i < j; ++i) {
+            const double a = cur, c = col[i + 1];
+            col[i] = rc[i] * a + rs[i] * c;
+            cur = -rs[i] * a + rc[i] * c;
+        }
+        const double rr = hypot(cur, hn);
+        const double cj = rr == 0.0 ? 1.0 : cur / rr, sj = rr == 0.0 ? 0.0 : hn / rr;
+        cs[j] = cj;
+        sn[j] = sj;
+        col[j] = rr;
+        H[(size_t)(j + 1) * ld + j] = 0.0;
+        const double gj = g[j];
+        g[j + 1] = -sj * gj;
+        g[j] = cj * gj;
+        st->k = j + 1;
+        mir->k = j + 1;
+        const double ag = fabs(sj * gj);
+        const int brk = hn == 0.0, rec = !brk && ag <= st->tol_abs;
+        st->stop = brk || rec;
+        mir->absg[j + 1] = ag;
+        mir->breakdown = brk;
+        mir->by_rec = rec;
+        mir->stop = brk || rec;
+    }
+    __syncthreads();
+    if (t <= j) H[(size_t)t * ld + j] = col[t];
+    if (t == 0) {
+        __threadfence_system();
+        mir->done = j;
+    }
+}
+
+__global__ void k_gmres_cycle_init(double beta, double tol_abs, double *__restrict__ g, CycleState *__restrict__ st) {
+    if (threadIdx.x != 0) return;
+    g[0] = beta;
+    st->k = 0;
+    st->stop = 0;
+    st->tol_abs = tol_abs;
+}
 
 int alloc_work(xab_ctx *ctx, Work &W, int64_t n, int m, size_t tsize) {
     W.ctx = ctx;
@@ -47,7 +153,10 @@ int alloc_work(xab_ctx *ctx, Work &W, int64_t n, int m, size_t tsize) {
     auto al = [](size_t b) { return (b + 255) / 256 * 256; };
     size_t off_r = 0, off_part = off_r + al(sizeof(double) * n);
     size_t off_small = off_part + al(sizeof(double) * xab::kRedBlocks * xab::kPartLd);
-    size_t off_V = off_small + al(sizeof(double) * (3 * (m + 2) + 16) + 64);
+    size_t off_sys = off_small + al(sizeof(double) * (3 * (m + 2) + 16) + 64);
+    size_t sys_bytes = sizeof(double) * ((size_t)(m + 1) * m + 2 * (size_t)m + (m + 1));
+    size_t off_st = off_sys + al(sys_bytes);
+    size_t off_V = off_st + al(sizeof(CycleState));
     size_t off_w = off_V + al(tsize * (size_t)(m + 1) * W.ldv);
     size_t off_z = off_w + al(tsize * W.ldv);
     size_t total = off_z + al(tsize * W.ldv);
@@ -63,11 +172,27 @@ int alloc_work(xab_ctx *ctx, Work &W, int64_t n, int m, size_t tsize) {
     W.V = b + off_V;
     W.w = b + off_w;
     W.z = b + off_z;
-    W.small_bytes = sizeof(double) * (3 * (size_t)(m + 2) + 8) + sizeof(int);
-    if (hipHostMalloc((void **)&W.host, W.small_bytes, hipHostMallocDefault) != hipSuccess) {
+    W.H = (double *)(b + off_sys);
+    W.cs = W.H + (size_t)(m + 1) * m;
+    W.sn = W.cs + m;
+    W.g = W.sn + m;
+    W.sys_bytes = sys_bytes;
+    W.st = (CycleState *)(b + off_st);
+    if (hipHostMalloc((void **)&W.host, sys_bytes, hipHostMallocDefault) != hipSuccess) {
         W.host = nullptr;
         return xab_fail(ctx, XAB_E_NOMEM, "pinned host buffer");
     }
+    if (hipHostMalloc((void **)&W.mir, sizeof(Mirror), hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess) {
+        W.mir = nullptr;
+        return xab_fail(ctx, XAB_E_NOMEM, "pinned host buffer");
+    }
+    if (hipHostGetDevicePointer((void **)&W.mir_dev, W.mir, 0) != hipSuccess)
+        return xab_fail(ctx, XAB_E_DEVICE, "device address of the step mirror");
+    for (auto &e : W.ev)
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+            e = nullptr;
+            return xab_fail(ctx, XAB_E_DEVICE, "step events");
+        }
     return XAB_OK;
 }
 
@@ -105,15 +230,38 @@ int cycle(xab_ctx *ctx, const xab_plan *pl, xab_matrix *A, Work &W, int m, doubl
     int s;
     // v0 = r / beta, z = M^-1 v0
     if ((s = xab::scale_from<double, T>(ctx, W.r, 1.0 / beta, V, z, d, n)) != XAB_OK) return s;
-    std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), g(m + 1, 0.0);
-    g[0] = beta;
-    out.samp.assign(1, beta);
-    int k = 0;
+    if (m > 63) return xab_fail(ctx, XAB_E_SHAPE, "restart length above 63");
+    Mirror *mir = W.mir;
+    mir->done = -1;
+    mir->k = 0;
+    mir->stop = 0;
+    mir->breakdown = 0;
+    mir->by_rec = 0;
+    mir->absg[0] = beta;
+    hipLaunchKernelGGL(k_gmres_cycle_init, dim3(1), dim3(64), 0, ctx->stream, beta, tol_abs, W.g, W.st);
+    XAB_LAUNCH_CHECK(ctx, "k_gmres_cycle_init");
     out.breakdown = false;
+    auto wait_step = [&](int q) -> int {
+        XAB_HIP(ctx, hipEventSynchronize(W.ev[q & 3]));
+        return XAB_OK;
+    };
     for (int j = 0; j < m && j < max_steps; ++j) {
+        if (j >= 2) {
+            // the GPU is on step j - 1 (or earlier): stop queueing once a
+            // finished step has stopped the cycle
+            if ((s = wait_step(j - 2)) != XAB_OK) return s;
+            if (mir->stop) break;
+            // the recurrence near the threshold: let step j - 1 finish too
+            // rather than queue a step past the stop
+            const double a = mir->absg[j - 1], b = mir->absg[j - 2];
+            const double pred = b > 0.0 ? a * std::min(1.0, a / b) : 0.0;
+            if (pred <= 100.0 * tol_abs) {
+                if ((s = wait_step(j - 1)) != XAB_OK) return s;
+                if (mir->stop) break;
+            }
+        }
         // w = A z (FP64 accumulation in every mode)
         if ((s = xab_spmv_dispatch(ctx, pl, z, tt, w, tt, XAB_F64)) != XAB_OK) return s;
-        const size_t oh2 = (size_t)(W.h2 - W.h1), osc = (size_t)(W.sc - W.h1);  // layout of the small region
         bool dgks = false;
         if (ortho == XAB_ORTHO_DGKS) {
             // pass 1: h1 = V^T w, ||w||^2; then one sweep: w' = w - V h1 with
@@ -160,40 +308,19 @@ int cycle(xab_ctx *ctx, const xab_plan *pl, xab_matrix *A, Work &W, int m, doubl
         } else {
             if ((s = xab::scale_precond<T>(ctx, w, W.h1 + j + 1, vn, z, d, n)) != XAB_OK) return s;
         }
-        // one read-back of the coefficients, the norms and the DGKS gate (contiguous)
-        XAB_HIP(ctx, hipMemcpyAsync(W.host, W.h1, W.small_bytes, hipMemcpyDeviceToHost, ctx->stream));
-        XAB_HIP(ctx, hipStreamSynchronize(ctx->stream));
-        const double *hh = W.host;
-        int gate = 0;
-        if (dgks) memcpy(&gate, (const char *)W.gate - (const char *)W.h1 + (const char *)W.host, sizeof(int));
-        for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hh[i] + (gate ? hh[oh2 + i] : 0.0);
-        const double hn = std::sqrt(!dgks ? hh[j + 1] : (gate ? hh[osc] : hh[oh2 + j + 1]));
-        H[(size_t)(j + 1) * m + j] = hn;
-        // earlier rotations on column j, then a new one
-        for (int i = 0; i < j; ++i) {
-            double a = H[(size_t)i * m + j], c = H[(size_t)(i + 1) * m + j];
-            H[(size_t)i * m + j] = cs[i] * a + sn[i] * c;
-            H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * c;
-        }
-        double a = H[(size_t)j * m + j], c = hn;
-        double rr = std::hypot(a, c);
-        cs[j] = rr == 0.0 ? 1.0 : a / rr;
-        sn[j] = rr == 0.0 ? 0.0 : c / rr;
-        H[(size_t)j * m + j] = rr;
-        H[(size_t)(j + 1) * m + j] = 0.0;
-        g[j + 1] = -sn[j] * g[j];
-        g[j] = cs[j] * g[j];
-        k = j + 1;
-        out.samp.push_back(std::fabs(g[j + 1]));
-        if (hn == 0.0) {
-            out.breakdown = true;
-            break;
-        }
-        if (std::fabs(g[j + 1]) <= tol_abs) {
-            out.by_recurrence = true;
-            break;
-        }
+        hipLaunchKernelGGL(k_gmres_givens, dim3(1), dim3(64), 0, ctx->stream, j, m, dgks ? 1 : 0, W.h1, W.h2, W.sc,
+                           W.gate, W.H, W.cs, W.sn, W.g, W.st, W.mir_dev);
+        XAB_LAUNCH_CHECK(ctx, "k_gmres_givens");
+        XAB_HIP(ctx, hipEventRecord(W.ev[j & 3], ctx->stream));
     }
+    // one read-back of the rotated system per cycle
+    XAB_HIP(ctx, hipMemcpyAsync(W.host, W.H, W.sys_bytes, hipMemcpyDeviceToHost, ctx->stream));
+    XAB_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    const int k = mir->k;  // steps before the stop (steps queued after it left no trace)
+    const double *H = W.host, *g = W.host + (W.g - W.H);
+    out.samp.assign(mir->absg, mir->absg + k + 1);
+    out.breakdown = mir->breakdown != 0;
+    out.by_recurrence = mir->by_rec != 0;
     // back substitution on the rotated triangle
     std::vector<double> y(k > 0 ? k : 1, 0.0);
     for (int i = k - 1; i >= 0; --i) {
@@ -204,7 +331,9 @@ int cycle(xab_ctx *ctx, const xab_plan *pl, xab_matrix *A, Work &W, int m, doubl
     out.k = k;
     out.est = std::fabs(g[k]);
     if (k > 0) {
-        XAB_HIP(ctx, hipMemcpyAsync(W.h2, y.data(), sizeof(double) * k, hipMemcpyHostToDevice, ctx->stream));
+        // y through the pinned buffer (the rotated system there is consumed)
+        std::copy(y.begin(), y.end(), W.host);
+        XAB_HIP(ctx, hipMemcpyAsync(W.h2, W.host, sizeof(double) * k, hipMemcpyHostToDevice, ctx->stream));
         if ((s = xab::combine<T>(ctx, V, W.ldv, k, W.h2, 1.0, d, x, n)) != XAB_OK) return s;
     }
     return XAB_OK;
