@@ -154,8 +154,28 @@ def _counter_csv(d):
     return per
 
 
-def pmc_summary(fetch_dir, write_dir, out, variant, n, cmd_fetch, cmd_write):
-    """Reduce the two counter runs to bytes per SpMV (FP64 instances)."""
+def _pick_instance(names, frag, precision, instance):
+    """The one instantiation of kernel `frag` asked for: FP64 (no float
+    template argument) or FP32 (a float argument where one exists, else the
+    shared instance), narrowed by the substring `instance` when given."""
+    cand = [k for k in names if f"::{frag}<" in k or f"::{frag}(" in k]
+    if instance:
+        narrowed = [k for k in cand if instance in k]
+        cand = narrowed or cand
+    if precision == "f32":
+        c32 = [k for k in cand if "float" in k]
+        cand = c32 or cand
+    else:
+        cand = [k for k in cand if "float" not in k]
+    if len(cand) != 1:
+        raise SystemExit(f"kernel {frag}: {len(cand)} {precision} instances found: {[c[:100] for c in cand]}")
+    return cand[0]
+
+
+def pmc_summary(fetch_dir, write_dir, out, variant, n, cmd_fetch, cmd_write, kernels=None, precision="f64",
+                instance="", workload=""):
+    """Reduce the two counter runs to bytes per launch group (by default one
+    FP64 SpMV of `variant`)."""
     F, W = _counter_csv(fetch_dir), _counter_csv(write_dir)
     def mean(per, name, ctr):
         v = per.get((name, ctr))
@@ -169,46 +189,43 @@ def pmc_summary(fetch_dir, write_dir, out, variant, n, cmd_fetch, cmd_write):
     ff, fw = CAL_BYTES / (cf * 1024.0), CAL_BYTES / (cw * 1024.0)
     ker = {}
     rd = wr = 0.0
-    for frag in VARIANT_KERNELS[variant]:
-        cand = [k for k in names if f"::{frag}<" in k and "float" not in k]
-        if len(cand) != 1:
-            raise SystemExit(f"kernel {frag}: {len(cand)} FP64 instances found")
-        f, nf = mean(F, cand[0], "FETCH_SIZE")
-        w, nw = mean(W, cand[0], "WRITE_SIZE")
-        ker[frag] = {"name": cand[0][:160], "fetch_kib_per_dispatch": f, "write_kib_per_dispatch": w,
+    for frag in kernels or VARIANT_KERNELS[variant]:
+        name = _pick_instance(names, frag, precision, instance)
+        f, nf = mean(F, name, "FETCH_SIZE")
+        w, nw = mean(W, name, "WRITE_SIZE")
+        ker[frag] = {"name": name[:160], "fetch_kib_per_dispatch": f, "write_kib_per_dispatch": w,
                      "dispatches": [nf, nw], "read_bytes": f * 1024 * ff, "write_bytes": w * 1024 * fw}
         rd += f * 1024 * ff
         wr += w * 1024 * fw
-    rep = {"workload": f"power-law CSR n={n}, FP64 SpMV", "variant": variant,
+    rep = {"workload": workload or f"power-law CSR n={n}, FP64 SpMV", "variant": variant, "precision": precision,
            "command_fetch": cmd_fetch, "command_write": cmd_write,
            "calibration": {"kernel": cal[0][:160], "bytes_read": CAL_BYTES, "bytes_written": CAL_BYTES,
                            "fetch_kib": cf, "write_kib": cw, "fetch_factor": ff, "write_factor": fw},
            "kernels": ker, "traffic_bytes_per_spmv": {"read": rd, "write": wr, "total": rd + wr},
-           "source_sha256": spmv_source_hash(variant)}
+           "source_sha256": spmv_source_hash(variant) if variant in VARIANT_SOURCES else None}
     with open(out, "w") as fh:
         json.dump(rep, fh, indent=1)
     print(json.dumps(rep["traffic_bytes_per_spmv"]))
 
 
-def counter_summary(dirs, out, variant, n, nnz, cmds):
+def counter_summary(dirs, out, variant, n, nnz, cmds, kernels=None, precision="f64", instance="", workload=""):
     """Reduce counter runs (one directory each) to a markdown table: per
-    kernel of one SpMV of `variant`, each counter's mean per dispatch; with
-    the L2 (TCC) hit and miss counts, the hit ratio, and the L2 requests
-    per stored entry."""
+    kernel of one launch group (by default one FP64 SpMV of `variant`),
+    each counter's mean per dispatch; with the L2 (TCC) hit and miss
+    counts, the hit ratio, and the L2 requests per stored entry."""
     pers = [_counter_csv(d) for d in dirs]
     names = sorted({k for per in pers for k, _ in per})
-    lines = [f"# {variant} SpMV (FP64) on the power-law CSR n={n}, nnz={nnz}: L2 and request counters", "",
+    title = workload or f"{variant} SpMV (FP64) on the power-law CSR n={n}, nnz={nnz}"
+    lines = [f"# {title}: counters per dispatch", "",
              "Commands (repository root, one counter set per run):", "", "```"] + list(cmds) + ["```", ""]
-    for frag in VARIANT_KERNELS[variant]:
-        cand = [k for k in names if f"::{frag}<" in k and "float" not in k]
-        if len(cand) != 1:
-            raise SystemExit(f"kernel {frag}: {len(cand)} FP64 instances found")
+    for frag in kernels or VARIANT_KERNELS[variant]:
+        name = _pick_instance(names, frag, precision, instance)
         vals = {}
         for per in pers:
             for (kn, ctr), v in per.items():
-                if kn == cand[0]:
+                if kn == name:
                     vals[ctr] = sum(v) / len(v)
-        lines += [f"## `{frag}`", "", "| Counter | Mean per dispatch |", "|---|---|"]
+        lines += [f"## `{frag}`", "", f"`{name[:150]}`", "", "| Counter | Mean per dispatch |", "|---|---|"]
         lines += [f"| {c} | {v:,.0f} |" for c, v in sorted(vals.items())]
         hit, miss = vals.get("TCC_HIT_sum"), vals.get("TCC_MISS_sum")
         if hit is not None and miss is not None and hit + miss > 0:
@@ -728,15 +745,21 @@ def main():
     ap.add_argument("--nnz", type=int, default=0, help="stored entries of the workload (--counter-summary)")
     ap.add_argument("--cmds", nargs="*", default=[], help="the counter runs' commands (--counter-summary)")
     ap.add_argument("--variant", default="XCB")
+    ap.add_argument("--kernels", nargs="*", default=None, help="kernel names to summarise (default: the variant's)")
+    ap.add_argument("--precision", choices=("f64", "f32"), default="f64", help="which instances to summarise")
+    ap.add_argument("--instance", default="", help="substring that picks one of several instances")
+    ap.add_argument("--workload", default="", help="workload text of the summary")
     ap.add_argument("--out")
     ap.add_argument("--cmd-fetch", default="")
     ap.add_argument("--cmd-write", default="")
     args = ap.parse_args()
     if args.pmc_summary:
-        pmc_summary(*args.pmc_summary, args.out, args.variant, args.n, args.cmd_fetch, args.cmd_write)
+        pmc_summary(*args.pmc_summary, args.out, args.variant, args.n, args.cmd_fetch, args.cmd_write,
+                    args.kernels, args.precision, args.instance, args.workload)
         return
     if args.counter_summary:
-        counter_summary(args.counter_summary, args.out, args.variant, args.n, args.nnz, args.cmds)
+        counter_summary(args.counter_summary, args.out, args.variant, args.n, args.nnz, args.cmds,
+                        args.kernels, args.precision, args.instance, args.workload)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding "
