@@ -280,6 +280,19 @@ typedef struct {
  * only precision the matrix holds).  info may be NULL.  Synchronous. */
 int xab_select(xab_ctx *ctx, const xab_matrix *A, xab_policy policy, xab_plan **plan, xab_select_info *info);
 
+/* The decision rule TIME and MEMORY apply to their measurements (section
+ * 3.1: the fastest implementation is kept): over the n classes with
+ * valid[k] != 0 and a finite time_ms[k] >= 0, the least time, the lowest
+ * index among equal times.  *chosen receives the class, -1 when none
+ * qualifies (return XAB_E_UNSUPPORTED).  Host only, no device work; for
+ * checking the rule on given tables.  Errors: XAB_E_NULL, XAB_E_SHAPE
+ * (n < 0). */
+int xab_select_rule(const float *time_ms, const int32_t *valid, int32_t n, int32_t *chosen);
+/* 1 if selector class k applies to a matrix with (sym != 0) or without
+ * lower symmetric storage, 0 if not, XAB_E_SHAPE for k outside the
+ * classes.  Host only. */
+int xab_class_applies(int32_t k, int32_t sym);
+
 /* Device memory held by a plan (its own arrays: partitions, descriptors,
  * partials and any re-laid-out copy of the matrix), in bytes; -1 for NULL.
  * The matrix's own arrays are the caller's and not counted. */

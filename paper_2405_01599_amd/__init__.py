@@ -105,6 +105,8 @@ _PP = ctypes.POINTER(ctypes.c_void_p)
 # symbol -> (restype, argtypes); every symbol declared in include/xab.h
 SIGNATURES = {
     "xab_class_params": (ctypes.c_int, [_I32, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(Params)]),
+    "xab_select_rule": (ctypes.c_int, [_P, _P, _I32, ctypes.POINTER(_I32)]),
+    "xab_class_applies": (ctypes.c_int, [_I32, _I32]),
     "xab_init": (ctypes.c_int, [_PP, ctypes.POINTER(InitOpts)]),
     "xab_finalize": (None, [_P]),
     "xab_set_stream": (ctypes.c_int, [_P, _P]),
@@ -180,6 +182,21 @@ def _dt(t):
     if t.dtype == torch.float32:
         return F32
     raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+def select_rule(time_ms, valid):
+    """The TIME policy's decision on a given table: (status, chosen class)."""
+    t = np.ascontiguousarray(time_ms, dtype=np.float32)
+    v = np.ascontiguousarray(valid, dtype=np.int32)
+    if t.shape != v.shape:
+        raise ValueError("time_ms and valid differ in length")
+    c = _I32()
+    s = lib().xab_select_rule(t.ctypes.data_as(_P), v.ctypes.data_as(_P), t.size, ctypes.byref(c))
+    return s, c.value
+
+
+def class_applies(k, sym):
+    return lib().xab_class_applies(k, 1 if sym else 0)
 
 
 def class_params(k):

@@ -31,6 +31,10 @@ __global__ void k_fill_f32(float *p, int64_t n, float v) {
 
 bool class_applies(int k, bool sym) { return sym ? (k >= 9 && k <= 11) : (k < 9 || k >= 12); }
 
+// class k with time t displaces the best so far (kb, tb): faster, or as
+// fast with a lower index
+bool displaces(float t, int k, float tb, int kb) { return kb < 0 || t < tb || (t == tb && k < kb); }
+
 constexpr int kStableGeneral = 3, kStableSym = 11, kStableSymFallback = 9;
 
 }  // namespace
@@ -173,7 +177,7 @@ extern "C" int xab_select(xab_ctx *ctx, const xab_matrix *A, xab_policy policy, 
             break;
         }
         inf.time_ms[k] = tmin;
-        if (best < 0 || tmin < inf.time_ms[best]) {
+        if (displaces(tmin, k, best < 0 ? 0.f : inf.time_ms[best], best)) {
             if (best_plan) xab_plan_destroy(best_plan);
             best_plan = pl;
             best = k;
@@ -190,4 +194,24 @@ extern "C" int xab_select(xab_ctx *ctx, const xab_matrix *A, xab_policy policy, 
     }
     if (!best_plan) return xab_fail(ctx, XAB_E_UNSUPPORTED, "no applicable SpMV class");
     return finish(best_plan, best);
+}
+
+extern "C" int xab_select_rule(const float *time_ms, const int32_t *valid, int32_t n, int32_t *chosen) {
+    if (!chosen) return XAB_E_NULL;
+    *chosen = -1;
+    if (n < 0) return XAB_E_SHAPE;
+    if (n > 0 && (!time_ms || !valid)) return XAB_E_NULL;
+    int best = -1;
+    for (int k = 0; k < n; ++k) {
+        const float t = time_ms[k];
+        if (!valid[k] || !(t >= 0.f) || std::isinf(t)) continue;
+        if (displaces(t, k, best < 0 ? 0.f : time_ms[best], best)) best = k;
+    }
+    *chosen = best;
+    return best < 0 ? XAB_E_UNSUPPORTED : XAB_OK;
+}
+
+extern "C" int xab_class_applies(int32_t k, int32_t sym) {
+    if (k < 0 || k >= XAB_NCLASSES) return XAB_E_SHAPE;
+    return class_applies(k, sym != 0) ? 1 : 0;
 }
