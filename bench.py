@@ -698,6 +698,29 @@ def xcb_gather_reference(ctx, xab, torch, gen, A, ev_ms, j_per_lane):
             "what": "same matrix, each column moved into the first 2048 columns of its XCD column block"}
 
 
+def c1_leg(ctx, xab, torch, gen):
+    """The small case: the 64 x 64 Laplacian, general and lower-stored:
+    device time per FP64 SpMV (HIP events, 100 launches) of every class
+    that applies (launch-latency bound at this size)."""
+    out = {}
+    for key, lower, classes in (("general", False, xab.GENERAL_CLASSES), ("lower", True, xab.SYM_CLASSES)):
+        A = gen.laplacian2d(64, lower=lower)
+        M = ctx.matrix_from_csr(A)
+        x = torch.from_numpy(gen.uniform_vec(A.n, 1)).cuda()
+        y = torch.empty(A.n, dtype=torch.float64, device="cuda")
+        us = {}
+        for k in classes:
+            try:
+                P = ctx.plan_class(M, k)
+            except xab.XabError:
+                continue
+            us[k] = round(ctx.time_spmv(P, x, y, warmup=5, reps=100) * 1e3, 2)
+            P.close()
+        out[key] = {"n": A.n, "nnz": A.nnz, "us_per_class": us}
+        M.close()
+    return out
+
+
 def trans4_leg(ctx, xab, torch, gen):
     """The very unbalanced trans4 shape of the paper's segment-length sweep
     (one row of 114,910 entries among 116,835 rows, 749,800 entries):
@@ -878,6 +901,7 @@ def main():
         c4 = batch_leg(ctx, xab, torch, gen)
 
     stress = trans4_leg(ctx, xab, torch, gen)
+    c1 = c1_leg(ctx, xab, torch, gen)
 
     cpu, errs = None, {}
     if oracle_leg:
@@ -916,6 +940,7 @@ def main():
         "gmres": gm,
         "sym27": c3,
         "trans4_stress": stress,
+        "c1_laplacian64": c1,
         "batch512": c4,
         "shard_of_8": shard,
         "arnoldi": arn,

@@ -4,7 +4,7 @@ and the scripts that measure its training set and train it on the GPU.
 model.bin   weights + feature standardisation (xab_selector_save format)
 collect.py  times every selector class on the generated training / held-out
             matrices (run on the GPU)
-train.py    trains the 12-64-64-13 MLP with the library's own kernels and
+train.py    trains the 12-64-64-15 MLP with the library's own kernels and
             scores it by regret against the measured timings
 report.json held-out regret of model.bin, of the exhaustive TIME policy
             and of the untuned STABLE default
