@@ -132,7 +132,9 @@ typedef enum {
 
 typedef struct {
     int32_t lanes_per_row; /* ROW, SYM_ATOMIC: 1, 2, 4, ..., 64 */
-    int32_t tile_nnz;      /* NNZ, SYM_S3: target entries per tile (>= 256) */
+    int32_t tile_nnz;      /* NNZ, SYM_S3: target entries per tile (>= 256); SYM_S3 with
+                              tile_rows >= 256 moves each tile boundary to the nearest
+                              multiple of 256 rows (whole rounds of the four-wave walk) */
     int32_t j_per_lane;    /* BSS, XCB: entries per lane, a power of two in 1..32; XCB also
                               takes 0: the largest of 4, 8, 16, 32 that leaves at least
                               4096 tiles of 256 * j_per_lane entries (xab_plan_info reports it) */

@@ -185,37 +185,53 @@ void orc_plan_bss(int64_t n, const int32_t *rowptr, int64_t T, int64_t P, int32_
 }
 
 /* Symmetric tiles: the nnz-based split of the stored lower triangle into
- * P0 = ceil(nnz/T) parts, then every part with more than Rmax rows cut into
- * k = ceil(R/Rmax) pieces at b + floor(i*R/k). */
-int64_t orc_plan_sym_ntiles(int64_t n, const int32_t *rowptr, int64_t T, int64_t Rmax) {
+ * P0 = ceil(nnz/T) parts; when Rmax >= 256 every inner part boundary moves
+ * to the nearest multiple of 256 rows (at most n), parts left empty by that
+ * are dropped (unless the split has a single part), and a part of R rows is
+ * cut into k = ceil(u/g) pieces of whole 256-row groups (u = ceil(R/256)
+ * groups, at most g = floor(Rmax/256) per piece) starting at
+ * b + 256 floor(i u / k); when Rmax < 256 the boundaries stay where the
+ * split put them and a part is cut into k = ceil(R/Rmax) pieces at
+ * b + floor(i R / k).  Returns the tile count; b (P + 1 entries) may be
+ * null. */
+static int64_t sym_tiles(int64_t n, const int32_t *rowptr, int64_t T, int64_t Rmax, int32_t *b) {
     int64_t nnz = n > 0 ? rowptr[n] : 0;
     int64_t P0 = orc_nparts(nnz, T);
     int32_t *b0 = (int32_t *)malloc(sizeof(int32_t) * (size_t)(P0 + 1));
     orc_plan_nnz(n, rowptr, P0, b0);
-    int64_t P = 0;
-    for (int64_t p = 0; p < P0; ++p) {
-        int64_t R = b0[p + 1] - b0[p];
-        int64_t k = (R + Rmax - 1) / Rmax;
-        P += k < 1 ? 1 : k;
-    }
-    free(b0);
-    return P;
-}
-
-void orc_plan_sym_tiles(int64_t n, const int32_t *rowptr, int64_t T, int64_t Rmax, int32_t *b) {
-    int64_t nnz = n > 0 ? rowptr[n] : 0;
-    int64_t P0 = orc_nparts(nnz, T);
-    int32_t *b0 = (int32_t *)malloc(sizeof(int32_t) * (size_t)(P0 + 1));
-    orc_plan_nnz(n, rowptr, P0, b0);
+    const int64_t g = Rmax / 256;
+    if (g >= 1)
+        for (int64_t p = 1; p < P0; ++p) {
+            int64_t r = (((int64_t)b0[p] + 128) / 256) * 256;
+            b0[p] = (int32_t)(r < n ? r : n);
+        }
     int64_t q = 0;
     for (int64_t p = 0; p < P0; ++p) {
         int64_t R = b0[p + 1] - b0[p];
-        int64_t k = (R + Rmax - 1) / Rmax;
-        if (k < 1) k = 1;
-        for (int64_t i = 0; i < k; ++i) b[q++] = (int32_t)(b0[p] + (i * R) / k);
+        if (R == 0 && P0 > 1) continue;
+        if (g >= 1) {
+            int64_t u = (R + 255) / 256, k = (u + g - 1) / g;
+            if (k < 1) k = 1;
+            for (int64_t i = 0; i < k; ++i, ++q)
+                if (b) b[q] = (int32_t)(b0[p] + 256 * ((i * u) / k));
+        } else {
+            int64_t k = (R + Rmax - 1) / Rmax;
+            if (k < 1) k = 1;
+            for (int64_t i = 0; i < k; ++i, ++q)
+                if (b) b[q] = (int32_t)(b0[p] + (i * R) / k);
+        }
     }
-    b[q] = (int32_t)n;
+    if (b) b[q] = (int32_t)n;
     free(b0);
+    return q;
+}
+
+int64_t orc_plan_sym_ntiles(int64_t n, const int32_t *rowptr, int64_t T, int64_t Rmax) {
+    return sym_tiles(n, rowptr, T, Rmax, NULL);
+}
+
+void orc_plan_sym_tiles(int64_t n, const int32_t *rowptr, int64_t T, int64_t Rmax, int32_t *b) {
+    (void)sym_tiles(n, rowptr, T, Rmax, b);
 }
 
 /* Zero-element omission for the transpose reduction.  Tile p's transposed

@@ -67,27 +67,46 @@ __global__ void k_split_bss(const int32_t *rowptr, int32_t n, int64_t T, int64_t
     carry_row[t] = (n > 0 && rowptr[tr] < e) ? tr : -1;
 }
 
-// symmetric tiles, step 1: pieces of each nnz part (rows capped at Rmax)
+// Symmetric tiles in whole 256-row groups (four 64-row chunks, one round
+// of the sliced walk's four waves): with Rmax >= 256 the inner boundaries
+// of the nnz split move to the nearest multiple of 256 rows (at most n)
+__global__ void k_sym_round(int32_t *b0, int64_t P0, int32_t n, int32_t Rmax) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < 1 || p >= P0 || Rmax < 256) return;
+    const int64_t r = (((int64_t)b0[p] + 128) / 256) * 256;
+    b0[p] = (int32_t)(r < n ? r : n);
+}
+
+// step 1: pieces per part.  An empty part is dropped (unless it is the
+// only one); with Rmax >= 256 a part of R rows is cut into ceil(u / g)
+// pieces of whole groups (u = ceil(R / 256) groups, at most g = Rmax / 256
+// per piece), else into ceil(R / Rmax) pieces
 __global__ void k_sym_pieces(const int32_t *b0, int64_t P0, int32_t Rmax, int32_t *cnt) {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= P0) return;
-    int32_t R = b0[p + 1] - b0[p];
-    int32_t k = (R + Rmax - 1) / Rmax;
-    cnt[p] = k < 1 ? 1 : k;
+    const int64_t R = b0[p + 1] - b0[p];
+    int64_t k;
+    if (R == 0 && P0 > 1) k = 0;
+    else if (Rmax >= 256) k = (((R + 255) / 256) + Rmax / 256 - 1) / (Rmax / 256);
+    else k = (R + Rmax - 1) / Rmax;
+    cnt[p] = (int32_t)(R == 0 && P0 > 1 ? 0 : (k < 1 ? 1 : k));
 }
 
-// step 2: boundaries b0[p] + floor(i * R / k)
+// step 2: piece i of part p starts at b0[p] + 256 floor(i u / k) (whole
+// groups) or b0[p] + floor(i R / k)
 __global__ void k_sym_fill(const int32_t *b0, const int32_t *cnt, const int32_t *off, int64_t P0, int32_t n,
-                           int32_t *b) {
+                           int32_t Rmax, int32_t *b) {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p > P0) return;
     if (p == P0) {
         b[off[P0]] = n;
         return;
     }
-    int64_t R = b0[p + 1] - b0[p];
-    int32_t k = cnt[p];
-    for (int32_t i = 0; i < k; ++i) b[off[p] + i] = (int32_t)(b0[p] + (i * R) / k);
+    const int64_t R = b0[p + 1] - b0[p];
+    const int32_t k = cnt[p];
+    const int64_t u = (R + 255) / 256;
+    for (int32_t i = 0; i < k; ++i)
+        b[off[p] + i] = (int32_t)(b0[p] + (Rmax >= 256 ? 256 * ((i * u) / k) : (i * R) / k));
 }
 
 // Exclusive scan of a small int array in one workgroup: out[0..m] (out[m] = total).
@@ -1218,6 +1237,7 @@ int xab_build_plan(xab_ctx *ctx, const xab_matrix *A, xab_variant v, const xab_p
             return xab_fail(ctx, XAB_E_NOMEM, "plan allocation");
         }
         hipLaunchKernelGGL(k_split_nnz, dim3(grid_for(P0 + 1, 256)), dim3(256), 0, st, A->rowptr, n, nnz, P0, b0);
+        hipLaunchKernelGGL(k_sym_round, dim3(grid_for(P0 + 1, 256)), dim3(256), 0, st, b0, P0, n, p.tile_rows);
         hipLaunchKernelGGL(k_sym_pieces, dim3(grid_for(P0, 256)), dim3(256), 0, st, b0, P0, p.tile_rows, cnt0);
         hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, st, cnt0, P0, off0);
         int32_t P = 0;
@@ -1235,7 +1255,8 @@ int xab_build_plan(xab_ctx *ctx, const xab_matrix *A, xab_variant v, const xab_p
             delete pl;
             return xab_fail(ctx, XAB_E_NOMEM, "plan allocation");
         }
-        hipLaunchKernelGGL(k_sym_fill, dim3(grid_for(P0 + 1, 256)), dim3(256), 0, st, b0, cnt0, off0, P0, n, pl->b);
+        hipLaunchKernelGGL(k_sym_fill, dim3(grid_for(P0 + 1, 256)), dim3(256), 0, st, b0, cnt0, off0, P0, n,
+                           p.tile_rows, pl->b);
         (void)hipStreamSynchronize(st);
         free_tmp();
         CHECKED(hip_ok(ctx, hipGetLastError(), "sym tiles"));

@@ -147,16 +147,37 @@ def _mat_sym(n, seed, band, p_empty=0.0):
     return gen.CSR(n, n, rp, ci, v, sym_lower=True)
 
 
+def brute_tiles(A, T, Rmax):
+    """Tile starts: the nnz split; with Rmax >= 256 its inner boundaries
+    rounded to the nearest multiple of 256 rows (capped at n), empty parts
+    dropped, parts cut into pieces of whole 256-row groups as even as the
+    groups allow; with Rmax < 256 parts cut into ceil(R / Rmax) even pieces."""
+    rp = A.rowptr
+    P0 = max(1, -(-A.nnz // T))
+    b0 = list(brute_nnz(rp, P0))
+    g = Rmax // 256
+    if g:
+        b0 = [b0[0]] + [min(A.n, 256 * ((v + 128) // 256)) for v in b0[1:-1]] + [b0[-1]]
+    parts = [(b0[p], b0[p + 1]) for p in range(P0)]
+    if P0 > 1:
+        parts = [(lo, hi) for lo, hi in parts if hi > lo]
+    b = []
+    for lo, hi in parts:
+        R = hi - lo
+        if g:
+            u = -(-R // 256)
+            k = max(1, -(-u // g))
+            b.extend(lo + 256 * ((i * u) // k) for i in range(k))
+        else:
+            k = max(1, -(-R // Rmax))
+            b.extend(lo + (i * R) // k for i in range(k))
+    b.append(A.n)
+    return [int(v) for v in b]
+
+
 def brute_sym(A, T, Rmax, C):
     rp, ci = A.rowptr, A.colind
-    P0 = max(1, -(-A.nnz // T))
-    b0 = brute_nnz(rp, P0)
-    b = []
-    for p in range(P0):
-        R = b0[p + 1] - b0[p]
-        k = max(1, -(-R // Rmax))
-        b.extend(int(b0[p] + (i * R) // k) for i in range(k))
-    b.append(A.n)
+    b = brute_tiles(A, T, Rmax)
     P = len(b) - 1
     pairs = set()
     for p in range(P):
@@ -194,6 +215,44 @@ def test_plan_sym_brute(n, seed, band, pe, T, Rmax, C):
     want = brute_sym(A, T, Rmax, C)
     for key in want:
         assert np.array_equal(got[key].astype(np.int64), want[key].astype(np.int64)), key
+
+
+@pytest.mark.parametrize("n,band,pe", [(3000, 20, 0.0), (5000, 3, 0.3), (700, 60, 0.1), (256, 5, 0.0), (2, 1, 0.0)])
+@pytest.mark.parametrize("T,Rmax", [(512, 256), (2000, 1024), (4096, 300), (100, 2048), (64, 700)])
+def test_plan_sym_whole_groups(n, band, pe, T, Rmax):
+    """With Rmax >= 256 every tile but the last holds a multiple of 256 rows
+    (the sliced walk's rounds of four 64-row chunks are full), no tile holds
+    more than Rmax rows, none is empty, and the tiles cover the rows in
+    order; the tile starts are the brute-force ones."""
+    A = _mat_sym(n, 11, band, pe)
+    b = oracle.plan_sym(A, T, Rmax, 16)["b"].astype(np.int64)
+    assert b[0] == 0 and b[-1] == A.n
+    sizes = np.diff(b)
+    assert np.all(sizes > 0) and np.all(sizes <= Rmax)
+    assert np.all(sizes[:-1] % 256 == 0)
+    assert list(b) == brute_tiles(A, T, Rmax)
+
+
+def test_plan_sym_tiles_hand_case():
+    """A hand-worked split: 1000 rows of 3 entries (3000 entries), T = 700
+    gives 5 parts with boundaries at rows 233, 466, 700, 933 (entry counts
+    699/700, 1398/1400, 2100, 2799/2800); rounded to 256 multiples: 256,
+    512, 768, 1000 (933 rounds to 1024, capped at n); Rmax = 512 (two
+    groups per piece) keeps them; Rmax = 256 cuts nothing further either."""
+    lens = [1] + [2] + [3] * 998
+    rows = []
+    for i, L in enumerate(lens):
+        rows.append(np.arange(i - L + 1, i + 1, dtype=np.int32))
+    rp = _rp([r.size for r in rows])
+    A = gen.CSR(1000, 1000, rp, np.concatenate(rows), np.ones(int(rp[-1])), sym_lower=True)
+    assert A.nnz == 2997
+    b = oracle.plan_sym(A, 700, 512, 16)["b"]
+    assert list(b) == [0, 256, 512, 768, 1000]
+    b = oracle.plan_sym(A, 700, 256, 16)["b"]
+    assert list(b) == [0, 256, 512, 768, 1000]
+    # one part of 1000 rows cut into pieces of at most 3 groups: u = 4, k = 2
+    b = oracle.plan_sym(A, 1 << 20, 768, 16)["b"]
+    assert list(b) == [0, 512, 1000]
 
 
 def _eval_sym(A, x, plan, C):
