@@ -64,7 +64,11 @@ __global__ __launch_bounds__(kNT) void k_spmv_xcb(XcbArgs a, const XT *__restric
     constexpr int T = kNT * J;
     constexpr int NW = kNT / kWave;
     __shared__ CSeg<AT> wave_tot[NW];
-    __shared__ AT ys[T];  // partials of the rows that start in the tile
+    // partials of the rows that start in the tile: the first YS of them
+    // (all, on matrices whose compressed rows average two entries or more)
+    // are staged, any further ones written directly
+    constexpr int YS = T < 4096 ? T : 4096;
+    __shared__ AT ys[YS];
     const int k = blockIdx.x % kXcds;
     const int64_t t = blockIdx.x / kXcds;
     const int64_t nnz = a.nnz[k];
@@ -131,8 +135,12 @@ __global__ __launch_bounds__(kNT) void k_spmv_xcb(XcbArgs a, const XT *__restric
 #pragma unroll
     for (int q = 0; q < J; ++q) {
         if (hd[q]) {
-            if (cnt > 0) ys[cnt - 1] = acc;
-            else if (!h0) ((AT *)a.carry_val[k])[t] = acc;
+            if (cnt > 0) {
+                if (cnt <= YS) ys[cnt - 1] = acc;
+                else Y[r0 + cnt] = acc;
+            } else if (!h0) {
+                ((AT *)a.carry_val[k])[t] = acc;
+            }
             acc = p[q];
             ++cnt;
         } else {
@@ -148,7 +156,8 @@ __global__ __launch_bounds__(kNT) void k_spmv_xcb(XcbArgs a, const XT *__restric
             // no row starts in the tile: all of it belongs to the carried row
             ((AT *)a.carry_val[k])[t] = total.v;
         } else if (hnext) {
-            ys[total.c - 1] = total.v;
+            if (total.c <= YS) ys[total.c - 1] = total.v;
+            else Y[r0 + total.c] = total.v;
         } else {
             tr = r0 + total.c;
             ((AT *)a.tail_val[k])[t] = total.v;
@@ -156,7 +165,8 @@ __global__ __launch_bounds__(kNT) void k_spmv_xcb(XcbArgs a, const XT *__restric
         a.tail_row[k][t] = tr;
     }
     __syncthreads();
-    for (int i = tid; i < nrows; i += kNT) Y[r0 + 1 + i] = ys[i];
+    const int staged = nrows < YS ? nrows : YS;
+    for (int i = tid; i < staged; i += kNT) Y[r0 + 1 + i] = ys[i];
 }
 
 // rows cut by a tile end: their start partial plus the carries of the

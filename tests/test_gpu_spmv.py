@@ -261,6 +261,30 @@ def test_xcb_all_lane_widths(ctx, J):
         assert np.array_equal(y32, yo), acc
 
 
+@pytest.mark.parametrize("J", [16, 32])
+def test_xcb_tiles_with_more_rows_than_staged(ctx, J):
+    # one or two entries per row at random columns: a block's compressed rows
+    # hold about one entry each, so a tile of 256 J entries starts up to
+    # 256 J rows, more than the 4096 the kernel stages in LDS at J = 32
+    rng = np.random.default_rng(21)
+    n = 300_000
+    lens = rng.integers(1, 3, n)
+    rp = np.zeros(n + 1, dtype=np.int32)
+    rp[1:] = np.cumsum(lens)
+    first = rng.integers(0, n - 1, n)
+    second = first + 1 + rng.integers(0, 1 << 30, n) % (n - 1 - first)  # in (first, n)
+    ci = np.empty(int(rp[-1]), dtype=np.int32)
+    ci[rp[:-1]] = first
+    two = lens == 2
+    ci[rp[:-1][two] + 1] = second[two]
+    A = gen.CSR(n, n, rp, ci, rng.integers(-8, 9, ci.size).astype(np.float64))
+    x = gen.int_vec(n, 4)
+    yo, _ = oracle.spmv(A, x)
+    M = ctx.matrix_from_csr(A)
+    P = ctx.plan(M, xab.XCB, j_per_lane=J)
+    assert np.array_equal(ctx.spmv(P, dev(x)).cpu().numpy(), yo)
+
+
 def test_xcb_size_chosen_lane_width(ctx):
     # class 12 leaves the entries per lane to the plan: the largest of 4, 8,
     # 16, 32 that keeps at least 4096 tiles of 256 J entries
