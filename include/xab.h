@@ -220,6 +220,16 @@ void xab_plan_destroy(xab_plan *plan);
  * *len receives the length; h_out may be NULL to query it.  Synchronous. */
 int xab_plan_array(const xab_plan *plan, int32_t which, int32_t *h_out, int64_t *len);
 int xab_plan_info(const xab_plan *plan, xab_variant *v, xab_params *p);
+/* After the caller has changed the values of the plan's matrix in place
+ * (same rowptr and colind, same value arrays), re-read them into the
+ * plan's own copies: the column-blocked copy (XCB), the padded copy
+ * (SELL), the 4 x 4 blocks (BCSR) and the sliced copy (SYM_S3's sliced
+ * walk), keeping the plan's structure (tiles, orders, masks); the other
+ * plans read the caller's values directly and need nothing.  The
+ * matrix's cached Jacobi diagonal is dropped (the next solve recomputes
+ * it).  Waits for the context stream first.  Errors: XAB_E_NULL,
+ * XAB_E_NOMEM, XAB_E_DEVICE.  Synchronous. */
+int xab_plan_refresh(xab_plan *plan);
 
 /* -------------------------------------------------------------------- SpMV */
 /* y = A x for a general matrix.  Value precision = xt (the matrix must hold

@@ -106,6 +106,7 @@ _PP = ctypes.POINTER(ctypes.c_void_p)
 SIGNATURES = {
     "xab_class_params": (ctypes.c_int, [_I32, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(Params)]),
     "xab_select_rule": (ctypes.c_int, [_P, _P, _I32, ctypes.POINTER(_I32)]),
+    "xab_plan_refresh": (ctypes.c_int, [_P]),
     "xab_class_applies": (ctypes.c_int, [_I32, _I32]),
     "xab_init": (ctypes.c_int, [_PP, ctypes.POINTER(InitOpts)]),
     "xab_finalize": (None, [_P]),
@@ -513,6 +514,10 @@ class Plan:
             self.ctx._check(lib().xab_plan_array(self.h, which, out.ctypes.data_as(_P), ctypes.byref(n)),
                             "xab_plan_array")
         return out
+
+    def refresh(self):
+        """Re-read the matrix's values (changed in place) into the plan's copies."""
+        self.ctx._check(lib().xab_plan_refresh(self.h), "xab_plan_refresh")
 
     def describe(self):
         p = self.params

@@ -438,7 +438,7 @@ __global__ __launch_bounds__(64) void k_sym_slice_fill(const int32_t *rowptr, co
             __syncthreads();
             if (on) {
                 const int64_t q = o + (int64_t)k * nr + lane;
-                cols[q] = later ? (int32_t)((uint32_t)c | xab::sym::kDeferBit) : c;
+                if (cols) cols[q] = later ? (int32_t)((uint32_t)c | xab::sym::kDeferBit) : c;
                 if (o64) o64[q] = k < len ? v64[s + k] : 0.0;
                 if (o32) o32[q] = k < len ? v32[s + k] : 0.0f;
             }
@@ -505,10 +505,16 @@ __global__ void k_xcb_scatter(const int32_t *rowptr, const int32_t *colind, cons
 #pragma unroll
         for (int q = 0; q < xab_plan::kXcb; ++q)
             if (q == k) p = pos[q]++;
-        ci_out[p] = col;
+        if (ci_out) ci_out[p] = col;
         if (v64) v64_out[p] = v64[e];
         if (v32) v32_out[p] = v32[e];
     }
+}
+
+template <class T>
+__global__ void k_fill_zero(T *p, int64_t m) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < m) p[i] = T(0);
 }
 
 __global__ void k_zero_i32(int32_t *p, int64_t m) {
@@ -724,7 +730,7 @@ __global__ void k_sell_fill(const int32_t *rowptr, const int32_t *colind, const 
     for (int32_t k = 0; k < w; ++k) {
         const int64_t dst = cptr[c] + (int64_t)k * xab_plan::kSellC + l;
         const bool live = k < len;
-        cols[dst] = live ? colind[src + k] : 0;
+        if (cols) cols[dst] = live ? colind[src + k] : 0;
         if (o64) o64[dst] = live ? v64[src + k] : 0.0;
         if (o32) o32[dst] = live ? v32[src + k] : 0.0f;
     }
@@ -1452,6 +1458,86 @@ void xab_plan_destroy(xab_plan *pl) {
     (void)hipStreamSynchronize(pl->ctx->stream);
     free_plan_arrays(pl->ctx, pl);
     delete pl;
+}
+
+int xab_plan_refresh(xab_plan *pl) {
+    if (!pl) return XAB_E_NULL;
+    xab_ctx *ctx = pl->ctx;
+    xab_matrix *A = const_cast<xab_matrix *>(pl->A);
+    hipStream_t st = ctx->stream;
+    const int32_t n = A->n;
+    const int64_t nnz = A->nnz;
+    XAB_HIP(ctx, hipSetDevice(ctx->device));
+    XAB_HIP(ctx, hipStreamSynchronize(st));  // no product of this plan still reads the copies
+    // the cached Jacobi diagonal follows the values (the next solve recomputes it)
+    xab_dfree(ctx, A->diag64);
+    xab_dfree(ctx, A->diag32);
+    A->diag64 = nullptr;
+    A->diag32 = nullptr;
+    const double *v64 = A->has64 ? A->val64 : nullptr;
+    const float *v32 = A->has32 ? A->val32 : nullptr;
+    hipError_t e = hipSuccess;
+    if (pl->variant == XAB_XCB && nnz > 0) {
+        // values into block order (the plan's per-block row pointers and
+        // block bases), then into the stored tile layout
+        constexpr int KB = xab_plan::kXcb;
+        ColBlocks cbk;
+        for (int k = 0; k <= KB; ++k) cbk.cb[k] = (int32_t)((int64_t)k * A->ncols / KB);
+        int64_t *dbase = (int64_t *)xab_dalloc(ctx, sizeof(int64_t) * (KB + 1));
+        double *t64 = pl->xcb_val64 ? (double *)xab_dalloc(ctx, sizeof(double) * (size_t)nnz) : nullptr;
+        float *t32 = pl->xcb_val32 ? (float *)xab_dalloc(ctx, sizeof(float) * (size_t)nnz) : nullptr;
+        if (!dbase || (pl->xcb_val64 && !t64) || (pl->xcb_val32 && !t32)) e = hipErrorOutOfMemory;
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(dbase, pl->xcb_base, sizeof(int64_t) * (KB + 1), hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(k_xcb_scatter, dim3(grid_for(n, 256)), dim3(256), 0, st, A->rowptr, A->colind,
+                               t64 ? v64 : nullptr, t32 ? v32 : nullptr, n, cbk, pl->xcb_rowptr, dbase, nullptr, t64,
+                               t32);
+            for (int k = 0; k < KB; ++k) {
+                const int64_t b = pl->xcb_base[k], m = pl->xcb_base[k + 1] - b;
+                if (m <= 0) continue;
+                if (t64)
+                    hipLaunchKernelGGL((k_xcb_interleave<double>), dim3(grid_for(m, 256)), dim3(256), 0, st, t64 + b,
+                                       pl->xcb_val64 + b, m, pl->params.j_per_lane);
+                if (t32)
+                    hipLaunchKernelGGL((k_xcb_interleave<float>), dim3(grid_for(m, 256)), dim3(256), 0, st, t32 + b,
+                                       pl->xcb_val32 + b, m, pl->params.j_per_lane);
+            }
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        xab_dfree(ctx, dbase);
+        xab_dfree(ctx, t64);
+        xab_dfree(ctx, t32);
+    } else if (pl->variant == XAB_SELL && pl->sell.nch > 0) {
+        const xab_sell &S = pl->sell;
+        hipLaunchKernelGGL(k_sell_fill, dim3(grid_for(S.nch * xab_plan::kSellC, 256)), dim3(256), 0, st, A->rowptr,
+                           A->colind, S.val64 ? v64 : nullptr, S.val32 ? v32 : nullptr, n, S.nch, S.perm, S.rlen,
+                           S.cptr, S.clen, nullptr, S.val64, S.val32);
+        e = hipGetLastError();
+    } else if (pl->variant == XAB_BCSR && pl->bcsr_nb > 0) {
+        // the blocks are sums of their entries: cleared, then refilled (the
+        // block columns and position masks come out as before)
+        constexpr int B = xab_plan::kBcsrB;
+        const int64_t nb = pl->bcsr_nb, nbr = pl->bcsr_nbr;
+        if (pl->bcsr_val64) hipLaunchKernelGGL((k_fill_zero<double>), dim3(grid_for(nb * B * B, 256)), dim3(256), 0, st,
+                                               pl->bcsr_val64, nb * B * B);
+        if (pl->bcsr_val32) hipLaunchKernelGGL((k_fill_zero<float>), dim3(grid_for(nb * B * B, 256)), dim3(256), 0, st,
+                                               pl->bcsr_val32, nb * B * B);
+        if (nbr > 0)
+            hipLaunchKernelGGL(k_bcsr_fill, dim3((unsigned)nbr), dim3(kBcsrNT), 0, st, A->rowptr, A->colind,
+                               pl->bcsr_val64 ? v64 : nullptr, pl->bcsr_val32 ? v32 : nullptr, n, pl->bcsr_brp,
+                               pl->bcsr_bci, pl->bcsr_mask, pl->bcsr_val64, pl->bcsr_val32);
+        e = hipGetLastError();
+    } else if (pl->variant == XAB_SYM_S3 && pl->s3_walk && pl->P > 0) {
+        hipLaunchKernelGGL(k_sym_slice_fill, dim3((unsigned)pl->P), dim3(64), 0, st, A->rowptr, A->colind,
+                           pl->s3_v64 ? v64 : nullptr, pl->s3_v32 ? v32 : nullptr, pl->b, pl->s3_ch0, pl->s3_cw,
+                           pl->s3_coff, nullptr, pl->s3_v64, pl->s3_v32);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e == hipErrorOutOfMemory) return xab_fail(ctx, XAB_E_NOMEM, "plan refresh buffers");
+    return e == hipSuccess ? XAB_OK : xab_hip_check(ctx, e, "plan refresh");
 }
 
 int xab_plan_info(const xab_plan *pl, xab_variant *v, xab_params *p) {

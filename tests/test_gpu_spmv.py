@@ -526,3 +526,56 @@ def test_sym_determinism(ctx, name, k, prec):
     ref = ctx.spmv(P, x, **kw)
     for _ in range(20):
         assert torch.equal(ctx.spmv(P, x, **kw), ref)
+
+
+# ----------------------------------------------------------------- value refresh
+REFRESH_CASES = [("powerlaw", k) for k in GENERAL_CLASSES] + [("blockdiag_ragged", 14), ("kron4", 14)] + \
+    [("st27_24", k) for k in SYM_CLASSES] + [("banded_holes", 10), ("arrow", 10)]
+
+
+@pytest.mark.parametrize("name,k", REFRESH_CASES)
+def test_plan_refresh_after_value_change(ctx, name, k):
+    # the plan built on one set of values, then the matrix's values changed
+    # in place and the plan refreshed: the product is the oracle's for the
+    # new values (integers: exact, FP64 and FP32 values), and bit-equal to a
+    # plan built afresh on the new values
+    A = GENERAL[name] if name in GENERAL else SYM[name]
+    A1, A2 = _int_version(A, seed=5), _int_version(A, seed=9)
+    x = gen.int_vec(A.ncols, 3)
+    M = ctx.matrix_from_csr(A1, with_f32=True)
+    P = _plan_class(ctx, M, A1, k) if name in GENERAL else ctx.plan_class(M, k)
+    if P is None:
+        return
+    assert np.array_equal(ctx.spmv(P, dev(x)).cpu().numpy(), oracle.spmv(A1, x)[0])
+    M.val.copy_(dev(A2.val))
+    M.val32.copy_(dev(A2.val, torch.float32))
+    P.refresh()
+    yo, _ = oracle.spmv(A2, x)
+    y = ctx.spmv(P, dev(x)).cpu().numpy()
+    assert np.array_equal(y, yo)
+    y32 = ctx.spmv(P, dev(x, torch.float32), ydtype=torch.float64, acc=xab.F64).cpu().numpy()
+    assert np.array_equal(y32, yo)
+    Q = ctx.plan_class(M, k)
+    assert torch.equal(ctx.spmv(Q, dev(x)), ctx.spmv(P, dev(x)))
+
+
+def test_plan_refresh_drops_the_jacobi_diagonal(ctx):
+    # GMRES with Jacobi after a value change and refresh solves the new
+    # system (the cached diagonal of the old values is not reused)
+    A = gen.laplacian2d(32)
+    M = ctx.matrix_from_csr(A)
+    P = ctx.plan_class(M, 12)
+    b = torch.ones(A.n, dtype=torch.float64, device="cuda")
+    ctx.gmres(P, b, tol=1e-10, precond=xab.PRECOND_JACOBI)
+    A2 = gen.CSR(A.n, A.ncols, A.rowptr, A.colind, A.val * np.where(A.colind == np.repeat(np.arange(A.n), np.diff(A.rowptr)), 2.0, 1.0))
+    M.val.copy_(dev(A2.val))
+    P.refresh()
+    x, inf, st = ctx.gmres(P, b, tol=1e-10, precond=xab.PRECOND_JACOBI)
+    assert st == 0
+    r = oracle.spmv(A2, x.cpu().numpy())[0] - 1.0
+    assert np.linalg.norm(r) <= 1e-9 * np.sqrt(A.n)
+
+
+def test_plan_refresh_errors():
+    import ctypes
+    assert xab.lib().xab_plan_refresh(None) == -1
