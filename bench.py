@@ -179,8 +179,11 @@ def pmc_summary(fetch_dir, write_dir, out, variant, n, cmd_fetch, cmd_write, ker
     F, W = _counter_csv(fetch_dir), _counter_csv(write_dir)
     def mean(per, name, ctr):
         v = per.get((name, ctr))
-        return (sum(v) / len(v), len(v)) if v else (None, 0)
-    names = sorted({k for k, _ in F} | {k for k, _ in W})
+        if not v:
+            raise SystemExit(f"no {ctr} reading for {name[:120]}")
+        return sum(v) / len(v), len(v)
+    # kernels read in both runs
+    names = sorted({k for k, _ in F} & {k for k, _ in W})
     cal = [k for k in names if "neg" in k.lower() and "elementwise" in k.lower()]
     if len(cal) != 1:
         raise SystemExit(f"calibration kernel not found once: {cal}")
@@ -759,6 +762,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 512-system batch leg")
     ap.add_argument("--no-eig", action="store_true", help="skip the Lanczos and Arnoldi legs")
     ap.add_argument("--no-shard", action="store_true", help="skip the one-GPU-share leg")
+    ap.add_argument("--no-c1", action="store_true", help="skip the 64 x 64 Laplacian leg")
     ap.add_argument("--no-gather-ref", action="store_true",
                     help="skip the local-column XCB reference (counter runs: keeps its dispatches out of the means)")
     ap.add_argument("--n", type=int, default=2_000_000)
@@ -901,7 +905,7 @@ def main():
         c4 = batch_leg(ctx, xab, torch, gen)
 
     stress = trans4_leg(ctx, xab, torch, gen)
-    c1 = c1_leg(ctx, xab, torch, gen)
+    c1 = None if args.no_c1 else c1_leg(ctx, xab, torch, gen)
 
     cpu, errs = None, {}
     if oracle_leg:
