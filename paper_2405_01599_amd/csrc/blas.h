@@ -21,6 +21,24 @@ int update_mdot(xab_ctx *ctx, const T *Vu, int nvu, const double *h, const T *Vd
                 int64_t n, double *part, int nb);
 int reduce_parts(xab_ctx *ctx, const double *part, int nb, int ldp, int m, double *out, int add, const int *gate);
 int dgks_gate(xab_ctx *ctx, const double *wn2, const double *wpn2, double eta, int *gate);
+// reduce_parts (m slots, no accumulate) and, from its last slot (the
+// squared norm after the first pass), the DGKS decision against *wn2
+int reduce_parts_dgks(xab_ctx *ctx, const double *part, int nb, int ldp, int m, double *out, const double *wn2,
+                      double eta, int *gate);
+
+// row r of v = w / ||w||, z = M^-1 v, the squared norm being *nrm2_gated
+// when a gate is given and set, else *nrm2
+template <class T>
+__device__ __forceinline__ void scale_precond_row(const T *__restrict__ w, const double *__restrict__ nrm2,
+                                                  const double *__restrict__ nrm2_gated, const int *__restrict__ gate,
+                                                  T *__restrict__ v, T *__restrict__ z, const T *__restrict__ d,
+                                                  int64_t r) {
+    const double s = sqrt((gate && *gate) ? *nrm2_gated : *nrm2);
+    const double inv = s > 0.0 ? 1.0 / s : 0.0;
+    const T vr = (T)((double)w[r] * inv);
+    v[r] = vr;
+    if (z) z[r] = d ? (T)((double)vr / (double)d[r]) : vr;
+}
 // v = w / ||w||, z = M^-1 v; the squared norm is *nrm2_gated when gate is
 // non-null and set, else *nrm2
 template <class T>

@@ -257,12 +257,10 @@ __global__ __launch_bounds__(kNT) void k_mdot_gated(const T *__restrict__ V, int
 // lane t sums slots t, t + 256, ... in ascending order, then a fixed LDS
 // tree joins the lanes.  Optional accumulate: out[i] += ... when add != 0.
 // When `gate` is non-null and *gate == 0 nothing happens.
-__global__ __launch_bounds__(kNT) void k_reduce_parts(const double *__restrict__ part, int nb, int ldp, int m,
-                                                      double *__restrict__ out, int add,
-                                                      const int *__restrict__ gate) {
-    __shared__ double sh[kNT];
-    if (gate && *gate == 0) return;
-    const int i = blockIdx.x;
+// slot i of the partials summed over the nb workgroups (every thread of
+// the block returns the sum)
+__device__ __forceinline__ double reduce_slot(const double *__restrict__ part, int nb, int ldp, int i,
+                                              double *sh) {
     // the thread's partials in ascending b, their loads issued 8 at a time
     double a = 0.0;
     int b = threadIdx.x;
@@ -281,7 +279,33 @@ __global__ __launch_bounds__(kNT) void k_reduce_parts(const double *__restrict__
         if (threadIdx.x < d) sh[threadIdx.x] += sh[threadIdx.x + d];
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[i] = add ? out[i] + sh[0] : sh[0];
+    return sh[0];
+}
+
+__global__ __launch_bounds__(kNT) void k_reduce_parts(const double *__restrict__ part, int nb, int ldp, int m,
+                                                      double *__restrict__ out, int add,
+                                                      const int *__restrict__ gate) {
+    __shared__ double sh[kNT];
+    if (gate && *gate == 0) return;
+    const int i = blockIdx.x;
+    const double t = reduce_slot(part, nb, ldp, i, sh);
+    if (threadIdx.x == 0) out[i] = add ? out[i] + t : t;
+}
+
+// k_reduce_parts (no accumulate, no gate) whose last slot is the squared
+// norm of w' after the first Gram-Schmidt pass: its workgroup also takes
+// the DGKS decision against the squared norm of w before the pass
+__global__ __launch_bounds__(kNT) void k_reduce_parts_dgks(const double *__restrict__ part, int nb, int ldp, int m,
+                                                           double *__restrict__ out,
+                                                           const double *__restrict__ wnorm2, double eta,
+                                                           int *__restrict__ gate) {
+    __shared__ double sh[kNT];
+    const int i = blockIdx.x;
+    const double t = reduce_slot(part, nb, ldp, i, sh);
+    if (threadIdx.x == 0) {
+        out[i] = t;
+        if (i == m - 1) *gate = (sqrt(t) < eta * sqrt(*wnorm2)) ? 1 : 0;
+    }
 }
 
 // DGKS test: *gate = ||w'|| < eta ||w|| given squared norms (one thread).
@@ -298,11 +322,7 @@ __global__ void k_scale_precond(const T *__restrict__ w, const double *__restric
                                 T *__restrict__ v, T *__restrict__ z, const T *__restrict__ d, int64_t n) {
     int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n) return;
-    double s = sqrt((gate && *gate) ? *nrm2_gated : *nrm2);
-    double inv = s > 0.0 ? 1.0 / s : 0.0;
-    T vr = (T)((double)w[r] * inv);
-    v[r] = vr;
-    if (z) z[r] = d ? (T)((double)vr / (double)d[r]) : vr;
+    scale_precond_row(w, nrm2, nrm2_gated, gate, v, z, d, r);
 }
 
 // v = r * scale (scale given on the host), z = v / d or v
@@ -436,6 +456,14 @@ int reduce_parts(xab_ctx *ctx, const double *part, int nb, int ldp, int m, doubl
     if (m <= 0) return XAB_OK;
     hipLaunchKernelGGL(k_reduce_parts, dim3(m), dim3(kNT), 0, ctx->stream, part, nb, ldp, m, out, add, gate);
     XAB_LAUNCH_CHECK(ctx, "k_reduce_parts");
+    return XAB_OK;
+}
+
+int reduce_parts_dgks(xab_ctx *ctx, const double *part, int nb, int ldp, int m, double *out, const double *wn2,
+                      double eta, int *gate) {
+    if (m <= 0) return XAB_OK;
+    hipLaunchKernelGGL(k_reduce_parts_dgks, dim3(m), dim3(kNT), 0, ctx->stream, part, nb, ldp, m, out, wn2, eta, gate);
+    XAB_LAUNCH_CHECK(ctx, "k_reduce_parts_dgks");
     return XAB_OK;
 }
 

@@ -79,19 +79,34 @@ struct Work {
     }
 };
 
-// Step j's Hessenberg column from the Gram-Schmidt coefficients (h1, plus
-// h2 when the DGKS gate fired) and the new norm; the earlier rotations
-// applied to it, the rotation that zeroes h_{j+1,j}, g updated, and the
-// step's stop decision (breakdown, or |g_{j+1}| at the threshold).  One
-// wave: the lanes stage the column and the rotations in LDS, lane 0 runs
-// the chain of at most 63 rotations (row i + 1 carried in a register).
-__global__ __launch_bounds__(64) void k_gmres_givens(int j, int ld, int dgks, const double *__restrict__ h1,
-                                                     const double *__restrict__ h2, const double *__restrict__ sc,
-                                                     const int *__restrict__ gate_p, double *__restrict__ H,
-                                                     double *__restrict__ cs, double *__restrict__ sn,
-                                                     double *__restrict__ g, CycleState *__restrict__ st, Mirror *mir) {
-    __shared__ double col[64], rc[64], rs[64];
+// The end of Arnoldi step j in one launch.  Every workgroup but the last
+// forms 256 rows of v_{j+1} = w / ||w|| and z = M^-1 v_{j+1} (the squared
+// norm h2[j+1], or sc when the DGKS gate fired; h1[j+1] without DGKS).
+// The last workgroup takes the step's Hessenberg column (h1, plus h2 when
+// the gate fired) and its norm, applies the earlier rotations to it, forms
+// the rotation that zeroes h_{j+1,j}, updates g and decides whether the
+// cycle stops (breakdown, or |g_{j+1}| at the threshold): its lanes stage
+// the column and the rotations in LDS and lane 0 runs the chain of at most
+// 63 rotations, row i + 1 carried in a register.
+template <class T>
+__global__ __launch_bounds__(256) void k_gmres_step_end(int j, int ld, int dgks, const double *__restrict__ h1,
+                                                        const double *__restrict__ h2, const double *__restrict__ sc,
+                                                        const int *__restrict__ gate_p, const T *__restrict__ w,
+                                                        T *__restrict__ v, T *__restrict__ z, const T *__restrict__ d,
+                                                        int64_t n, int nblk, double *__restrict__ H,
+                                                        double *__restrict__ cs, double *__restrict__ sn,
+                                                        double *__restrict__ g, CycleState *__restrict__ st,
+                                                        Mirror *mir) {
     const int t = threadIdx.x;
+    if ((int)blockIdx.x < nblk) {
+        const int64_t r = (int64_t)blockIdx.x * 256 + t;
+        if (r < n) {
+            if (dgks) xab::scale_precond_row(w, h2 + j + 1, sc, gate_p, v, z, d, r);
+            else xab::scale_precond_row<T>(w, h1 + j + 1, nullptr, nullptr, v, z, d, r);
+        }
+        return;
+    }
+    __shared__ double col[64], rc[64], rs[64];
     if (st->stop) {
         // queued after the stopping step: leave the rotated system alone
         if (t == 0) mir->done = j;
@@ -270,9 +285,11 @@ int cycle(xab_ctx *ctx, const xab_plan *pl, xab_matrix *A, Work &W, int m, doubl
             if ((s = xab::mdot<T>(ctx, V, W.ldv, j + 1, w, n, W.part, nb, nullptr)) != XAB_OK) return s;
             if ((s = xab::reduce_parts(ctx, W.part, nb, xab::kPartLd, j + 2, W.h1, 0, nullptr)) != XAB_OK) return s;
             if ((s = xab::update_mdot<T>(ctx, V, j + 1, W.h1, V, j + 1, W.ldv, w, n, W.part, nb)) != XAB_OK) return s;
-            if ((s = xab::reduce_parts(ctx, W.part, nb, xab::kPartLd, j + 2, W.h2, 0, nullptr)) != XAB_OK) return s;
-            // the second update only when cancellation was severe
-            if ((s = xab::dgks_gate(ctx, W.h1 + j + 1, W.h2 + j + 1, kEta, W.gate)) != XAB_OK) return s;
+            // h2 and the DGKS decision: the second update only when
+            // cancellation was severe
+            if ((s = xab::reduce_parts_dgks(ctx, W.part, nb, xab::kPartLd, j + 2, W.h2, W.h1 + j + 1, kEta, W.gate)) !=
+                XAB_OK)
+                return s;
             if ((s = xab::update_norm<T>(ctx, V, W.ldv, j + 1, W.h2, w, n, W.part, nb, W.gate)) != XAB_OK) return s;
             if ((s = xab::reduce_parts(ctx, W.part, nb, 1, 1, W.sc, 0, W.gate)) != XAB_OK) return s;
         } else if (ortho == XAB_ORTHO_CGS) {
@@ -301,16 +318,13 @@ int cycle(xab_ctx *ctx, const xab_plan *pl, xab_matrix *A, Work &W, int m, doubl
                     return s;
             }
         }
-        // v_{j+1} = w / ||w||, z = M^-1 v_{j+1}
+        // v_{j+1} = w / ||w||, z = M^-1 v_{j+1}, and the step's rotation
         T *vn = V + (int64_t)(j + 1) * W.ldv;
-        if (dgks) {
-            if ((s = xab::scale_precond<T>(ctx, w, W.h2 + j + 1, vn, z, d, n, W.sc, W.gate)) != XAB_OK) return s;
-        } else {
-            if ((s = xab::scale_precond<T>(ctx, w, W.h1 + j + 1, vn, z, d, n)) != XAB_OK) return s;
-        }
-        hipLaunchKernelGGL(k_gmres_givens, dim3(1), dim3(64), 0, ctx->stream, j, m, dgks ? 1 : 0, W.h1, W.h2, W.sc,
-                           W.gate, W.H, W.cs, W.sn, W.g, W.st, W.mir_dev);
-        XAB_LAUNCH_CHECK(ctx, "k_gmres_givens");
+        const int nblk = (int)((n + 255) / 256);
+        hipLaunchKernelGGL((k_gmres_step_end<T>), dim3((unsigned)nblk + 1), dim3(256), 0, ctx->stream, j, m,
+                           dgks ? 1 : 0, W.h1, W.h2, W.sc, W.gate, w, vn, z, d, n, nblk, W.H, W.cs, W.sn, W.g, W.st,
+                           W.mir_dev);
+        XAB_LAUNCH_CHECK(ctx, "k_gmres_step_end");
         XAB_HIP(ctx, hipEventRecord(W.ev[j & 3], ctx->stream));
     }
     // one read-back of the rotated system per cycle
