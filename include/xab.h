@@ -137,7 +137,9 @@ typedef struct {
                               multiple of 256 rows (whole rounds of the four-wave walk) */
     int32_t j_per_lane;    /* BSS, XCB: entries per lane, a power of two in 1..32; XCB also
                               takes 0: the largest of 4, 8, 16, 32 that leaves at least
-                              4096 tiles of 256 * j_per_lane entries (xab_plan_info reports it) */
+                              4096 tiles of 256 * j_per_lane entries (xab_plan_info reports it);
+                              FP32 values then take the same rule capped at 16, with their own
+                              copy of the columns when that differs */
     int32_t col_block;     /* SYM_S3: column block size C of the touch map (power of two) */
     int32_t tile_rows;     /* SYM_S3: maximum rows per tile (<= 2048); SELL: sorting window
                               (a multiple of 64, at most 1024) */

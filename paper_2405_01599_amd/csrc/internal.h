@@ -120,6 +120,16 @@ struct xab_plan {
     void *xcb_Y = nullptr;              // compressed partial products, acc-type, ybase[kXcb] slots
     int64_t xcb_G = 0;                  // row groups of 256 (the combine's workgroups)
     int32_t *xcb_gbase = nullptr;       // kXcb * (G + 1): compressed index of group g's first row in block k
+    // FP32 values walked with fewer entries per lane than FP64 ones (when
+    // the plan chose J from the size): their own lane-interleaved copy of
+    // the columns and their own tiles; partials, mask and group offsets
+    // are shared.  xcb_j32 = 0: the FP32 values use the FP64 walk.
+    int32_t xcb_j32 = 0;
+    int32_t *xcb_colind32 = nullptr;
+    int64_t xcb_P32[kXcb] = {0};
+    int64_t xcb_toff32[kXcb + 1] = {0};
+    int32_t *xcb_row_lo32 = nullptr, *xcb_carry_row32 = nullptr, *xcb_tail_row32 = nullptr, *xcb_tile_row32 = nullptr;
+    void *xcb_carry_val32 = nullptr, *xcb_tail_val32 = nullptr;
     // SELL: chunks of kSellC ordered rows, column-major, padded to the chunk's longest row
     static constexpr int kSellC = 64;
     static constexpr int kSellMaxRow = 4096;

@@ -782,6 +782,13 @@ static void free_plan_arrays(xab_ctx *ctx, xab_plan *pl) {
     xab_dfree(ctx, pl->xcb_carry_val);
     xab_dfree(ctx, pl->xcb_tail_val);
     xab_dfree(ctx, pl->xcb_Y);
+    xab_dfree(ctx, pl->xcb_colind32);
+    xab_dfree(ctx, pl->xcb_row_lo32);
+    xab_dfree(ctx, pl->xcb_tile_row32);
+    xab_dfree(ctx, pl->xcb_carry_row32);
+    xab_dfree(ctx, pl->xcb_tail_row32);
+    xab_dfree(ctx, pl->xcb_carry_val32);
+    xab_dfree(ctx, pl->xcb_tail_val32);
 }
 
 // device bytes of the plan's own arrays
@@ -795,7 +802,9 @@ static size_t plan_device_bytes(const xab_plan *pl) {
                             pl->sell.val64, pl->sell.val32, pl->bcsr_brp, pl->bcsr_bci, pl->bcsr_mask,
                             pl->bcsr_val64, pl->bcsr_val32, pl->xcb_mask, pl->xcb_colind, pl->xcb_val64,
                             pl->xcb_val32, pl->xcb_row_lo, pl->xcb_tile_row, pl->xcb_carry_row, pl->xcb_tail_row,
-                            pl->xcb_carry_val, pl->xcb_tail_val, pl->xcb_Y};
+                            pl->xcb_carry_val, pl->xcb_tail_val, pl->xcb_Y, pl->xcb_colind32, pl->xcb_row_lo32,
+                            pl->xcb_tile_row32, pl->xcb_carry_row32, pl->xcb_tail_row32, pl->xcb_carry_val32,
+                            pl->xcb_tail_val32};
     size_t t = 0;
     for (const void *p : arrays) t += xab_dbytes(c, p);
     return t;
@@ -1107,9 +1116,23 @@ int xab_build_plan(xab_ctx *ctx, const xab_matrix *A, xab_variant v, const xab_p
             delete pl;
             return xab_hip_check(ctx, e, "column-block counts");
         }
+        // FP32 values: the size rule capped at 16 entries per lane (their
+        // products then keep more workgroups per CU); only when the plan
+        // chose J from the size and that gives a different J
+        if (pp->j_per_lane == 0 && A->has32) {
+            int32_t j32 = 4;
+            while (j32 < 16 && nnz >= (int64_t)4096 * 256 * (2 * j32)) j32 *= 2;
+            pl->xcb_j32 = j32 < p.j_per_lane ? j32 : 0;
+        }
+        const int64_t T32 = 256 * (int64_t)pl->xcb_j32;
         pl->xcb_base[0] = 0;
         pl->xcb_toff[0] = 0;
+        pl->xcb_toff32[0] = 0;
         for (int k = 0; k < KB; ++k) {
+            if (T32 > 0) {
+                pl->xcb_P32[k] = std::max<int64_t>(1, (tot[k] + T32 - 1) / T32);
+                pl->xcb_toff32[k + 1] = pl->xcb_toff32[k] + pl->xcb_P32[k] + 1;
+            }
             pl->xcb_base[k + 1] = pl->xcb_base[k] + tot[k];
             pl->xcb_P[k] = std::max<int64_t>(1, (tot[k] + T - 1) / T);
             pl->xcb_toff[k + 1] = pl->xcb_toff[k] + pl->xcb_P[k] + 1;
@@ -1185,8 +1208,21 @@ int xab_build_plan(xab_ctx *ctx, const xab_matrix *A, xab_variant v, const xab_p
         pl->xcb_carry_val = xab_dalloc(ctx, sizeof(double) * (size_t)tt);
         pl->xcb_tail_val = xab_dalloc(ctx, sizeof(double) * (size_t)tt);
         pl->xcb_Y = xab_dalloc(ctx, sizeof(double) * (size_t)std::max<int64_t>(1, pl->xcb_ybase[KB]));
+        if (pl->xcb_j32) {
+            const int64_t t32 = pl->xcb_toff32[KB];
+            pl->xcb_row_lo32 = (int32_t *)xab_dalloc(ctx, sizeof(int32_t) * (size_t)t32);
+            pl->xcb_tile_row32 = (int32_t *)xab_dalloc(ctx, sizeof(int32_t) * (size_t)t32);
+            pl->xcb_carry_row32 = (int32_t *)xab_dalloc(ctx, sizeof(int32_t) * (size_t)t32);
+            pl->xcb_tail_row32 = (int32_t *)xab_dalloc(ctx, sizeof(int32_t) * (size_t)t32);
+            pl->xcb_carry_val32 = xab_dalloc(ctx, sizeof(double) * (size_t)t32);
+            pl->xcb_tail_val32 = xab_dalloc(ctx, sizeof(double) * (size_t)t32);
+            pl->xcb_colind32 = (int32_t *)xab_dalloc(ctx, sizeof(int32_t) * (size_t)std::max<int64_t>(1, nnz));
+        }
+        const bool miss32 = pl->xcb_j32 && (!pl->xcb_row_lo32 || !pl->xcb_tile_row32 || !pl->xcb_carry_row32 ||
+                                            !pl->xcb_tail_row32 || !pl->xcb_carry_val32 || !pl->xcb_tail_val32 ||
+                                            !pl->xcb_colind32);
         if (!pl->xcb_row_lo || !pl->xcb_tile_row || !pl->xcb_carry_row || !pl->xcb_tail_row || !pl->xcb_carry_val ||
-            !pl->xcb_tail_val || !pl->xcb_Y) {
+            !pl->xcb_tail_val || !pl->xcb_Y || miss32) {
             xab_dfree(ctx, crowptr);
             free_plan_arrays(ctx, pl);
             delete pl;
@@ -1198,22 +1234,34 @@ int xab_build_plan(xab_ctx *ctx, const xab_matrix *A, xab_variant v, const xab_p
                                crowptr + (int64_t)k * (n + 1), (int32_t)pl->xcb_m[k], T, pl->xcb_P[k],
                                pl->xcb_row_lo + o, pl->xcb_tile_row + o, pl->xcb_carry_row + o);
             pl->P = std::max(pl->P, pl->xcb_P[k]);
+            if (pl->xcb_j32) {
+                const int64_t o32 = pl->xcb_toff32[k];
+                hipLaunchKernelGGL(k_split_bss, dim3(grid_for(pl->xcb_P32[k] + 1, 256)), dim3(256), 0, st,
+                                   crowptr + (int64_t)k * (n + 1), (int32_t)pl->xcb_m[k], T32, pl->xcb_P32[k],
+                                   pl->xcb_row_lo32 + o32, pl->xcb_tile_row32 + o32, pl->xcb_carry_row32 + o32);
+            }
         }
         e = hipGetLastError();
         if (e == hipSuccess) e = hipStreamSynchronize(st);  // crowptr is freed next
         xab_dfree(ctx, crowptr);
         CHECKED(hip_ok(ctx, e, "column-block tiles"));
-        // full tiles in lane-interleaved 16-byte groups (columns and each value copy)
-        auto interleave = [&](auto *&arr) -> hipError_t {
+        // full tiles in lane-interleaved 16-byte groups (columns and each
+        // value copy; the FP32 walk's columns and values by its own J)
+        if (pl->xcb_j32 && nnz > 0) {
+            e = hipMemcpyAsync(pl->xcb_colind32, pl->xcb_colind, sizeof(int32_t) * (size_t)nnz,
+                               hipMemcpyDeviceToDevice, st);
+            CHECKED(hip_ok(ctx, e, "FP32 walk columns"));
+        }
+        auto interleave = [&](auto *&arr, int32_t J) -> hipError_t {
             using E = std::remove_reference_t<decltype(*arr)>;
-            if (!arr || nnz == 0 || p.j_per_lane <= (int)(16 / sizeof(E))) return hipSuccess;
+            if (!arr || nnz == 0 || J <= (int)(16 / sizeof(E))) return hipSuccess;
             E *out = (E *)xab_dalloc(ctx, sizeof(E) * (size_t)nnz);
             if (!out) return hipErrorOutOfMemory;
             for (int k = 0; k < KB; ++k) {
                 const int64_t b = pl->xcb_base[k], m = pl->xcb_base[k + 1] - b;
                 if (m > 0)
                     hipLaunchKernelGGL((k_xcb_interleave<E>), dim3(grid_for(m, 256)), dim3(256), 0, st, arr + b, out + b,
-                                       m, p.j_per_lane);
+                                       m, J);
             }
             hipError_t ee = hipGetLastError();
             if (ee == hipSuccess) ee = hipStreamSynchronize(st);
@@ -1221,9 +1269,11 @@ int xab_build_plan(xab_ctx *ctx, const xab_matrix *A, xab_variant v, const xab_p
             arr = out;
             return ee;
         };
-        e = interleave(pl->xcb_colind);
-        if (e == hipSuccess) e = interleave(pl->xcb_val64);
-        if (e == hipSuccess) e = interleave(pl->xcb_val32);
+        const int32_t j32 = pl->xcb_j32 ? pl->xcb_j32 : p.j_per_lane;
+        e = interleave(pl->xcb_colind, p.j_per_lane);
+        if (e == hipSuccess) e = interleave(pl->xcb_val64, p.j_per_lane);
+        if (e == hipSuccess) e = interleave(pl->xcb_val32, j32);
+        if (e == hipSuccess && pl->xcb_j32) e = interleave(pl->xcb_colind32, j32);
         CHECKED(hip_ok(ctx, e, "interleaved tiles"));
     } else {  // XAB_SYM_S3
         const int32_t C = p.col_block;
@@ -1501,7 +1551,7 @@ int xab_plan_refresh(xab_plan *pl) {
                                        pl->xcb_val64 + b, m, pl->params.j_per_lane);
                 if (t32)
                     hipLaunchKernelGGL((k_xcb_interleave<float>), dim3(grid_for(m, 256)), dim3(256), 0, st, t32 + b,
-                                       pl->xcb_val32 + b, m, pl->params.j_per_lane);
+                                       pl->xcb_val32 + b, m, pl->xcb_j32 ? pl->xcb_j32 : pl->params.j_per_lane);
             }
             e = hipGetLastError();
         }

@@ -227,8 +227,17 @@ __global__ __launch_bounds__(kNT) void k_xcb_combine(XcbArgs a, const uint8_t *_
 
 }  // namespace
 
+// The arrays of one walk of the blocked copy: the FP64 one, or the FP32
+// values' own when the plan made one
+struct XcbWalk {
+    const int32_t *colind;
+    const int64_t *P, *toff;
+    int32_t *tile_row, *carry_row, *tail_row;
+    void *carry_val, *tail_val;
+};
+
 template <class VT, class XT, class YT, class AT, int J>
-static int launch_xcb_j(xab_ctx *ctx, const xab_plan *pl, const XT *x, YT *y) {
+static int launch_xcb_j(xab_ctx *ctx, const xab_plan *pl, const XcbWalk &wk, const XT *x, YT *y) {
     const xab_matrix *A = pl->A;
     constexpr int KB = xab_plan::kXcb;
     static_assert(KB == kXcds, "one column block per XCD");
@@ -238,19 +247,19 @@ static int launch_xcb_j(xab_ctx *ctx, const xab_plan *pl, const XT *x, YT *y) {
     int64_t pmax = 1;
     AT *Y = (AT *)pl->xcb_Y;
     for (int k = 0; k < KB; ++k) {
-        const int64_t b = pl->xcb_base[k], o = pl->xcb_toff[k];
-        a.colind[k] = pl->xcb_colind + b;
+        const int64_t b = pl->xcb_base[k], o = wk.toff[k];
+        a.colind[k] = wk.colind + b;
         if constexpr (sizeof(VT) == 8) a.val[k] = pl->xcb_val64 + b;
         else a.val[k] = pl->xcb_val32 + b;
-        a.row0[k] = pl->xcb_tile_row + o;
-        a.carry_row[k] = pl->xcb_carry_row + o;
-        a.tail_row[k] = pl->xcb_tail_row + o;
-        a.carry_val[k] = (AT *)pl->xcb_carry_val + o;
-        a.tail_val[k] = (AT *)pl->xcb_tail_val + o;
+        a.row0[k] = wk.tile_row + o;
+        a.carry_row[k] = wk.carry_row + o;
+        a.tail_row[k] = wk.tail_row + o;
+        a.carry_val[k] = (AT *)wk.carry_val + o;
+        a.tail_val[k] = (AT *)wk.tail_val + o;
         a.Y[k] = Y + pl->xcb_ybase[k];
         a.nnz[k] = pl->xcb_base[k + 1] - b;
-        a.P[k] = pl->xcb_P[k];
-        pmax = std::max(pmax, pl->xcb_P[k]);
+        a.P[k] = wk.P[k];
+        pmax = std::max(pmax, wk.P[k]);
     }
     hipLaunchKernelGGL((k_spmv_xcb<VT, XT, AT, J>), dim3((unsigned)(KB * pmax)), dim3(kNT), 0, ctx->stream, a, x);
     XAB_LAUNCH_CHECK(ctx, "k_spmv_xcb");
@@ -267,13 +276,19 @@ int launch_xcb(xab_ctx *ctx, const xab_plan *pl, const VT *val, const XT *x, YT 
     (void)val;  // the plan holds its own column-blocked copy of the values
     if ((sizeof(VT) == 8 && !pl->xcb_val64) || (sizeof(VT) == 4 && !pl->xcb_val32))
         return xab_fail(ctx, XAB_E_DTYPE, "column-blocked plan holds no values of this precision");
-    switch (pl->params.j_per_lane) {
-        case 1: return launch_xcb_j<VT, XT, YT, AT, 1>(ctx, pl, x, y);
-        case 2: return launch_xcb_j<VT, XT, YT, AT, 2>(ctx, pl, x, y);
-        case 4: return launch_xcb_j<VT, XT, YT, AT, 4>(ctx, pl, x, y);
-        case 8: return launch_xcb_j<VT, XT, YT, AT, 8>(ctx, pl, x, y);
-        case 16: return launch_xcb_j<VT, XT, YT, AT, 16>(ctx, pl, x, y);
-        case 32: return launch_xcb_j<VT, XT, YT, AT, 32>(ctx, pl, x, y);
+    const bool own32 = sizeof(VT) == 4 && pl->xcb_j32 > 0;
+    const XcbWalk wk = own32 ? XcbWalk{pl->xcb_colind32, pl->xcb_P32, pl->xcb_toff32, pl->xcb_tile_row32,
+                                       pl->xcb_carry_row32, pl->xcb_tail_row32, pl->xcb_carry_val32,
+                                       pl->xcb_tail_val32}
+                             : XcbWalk{pl->xcb_colind, pl->xcb_P, pl->xcb_toff, pl->xcb_tile_row, pl->xcb_carry_row,
+                                       pl->xcb_tail_row, pl->xcb_carry_val, pl->xcb_tail_val};
+    switch (own32 ? pl->xcb_j32 : pl->params.j_per_lane) {
+        case 1: return launch_xcb_j<VT, XT, YT, AT, 1>(ctx, pl, wk, x, y);
+        case 2: return launch_xcb_j<VT, XT, YT, AT, 2>(ctx, pl, wk, x, y);
+        case 4: return launch_xcb_j<VT, XT, YT, AT, 4>(ctx, pl, wk, x, y);
+        case 8: return launch_xcb_j<VT, XT, YT, AT, 8>(ctx, pl, wk, x, y);
+        case 16: return launch_xcb_j<VT, XT, YT, AT, 16>(ctx, pl, wk, x, y);
+        case 32: return launch_xcb_j<VT, XT, YT, AT, 32>(ctx, pl, wk, x, y);
         default: return xab_fail(ctx, XAB_E_UNSUPPORTED, "j_per_lane %d", pl->params.j_per_lane);
     }
 }

@@ -61,6 +61,30 @@ def test_c2_spmv_fp64_and_fp32_values(ctx, c2):
     assert np.all(np.abs(y32 - yo) <= (1e-12 + 2.01 * U32) * s)
 
 
+def test_c2_xcb_walks_integer_exact(ctx, c2):
+    """At this size the XCB plan walks FP64 values with 32 entries per lane
+    and FP32 values with 16 (their own interleaved columns and tiles): with
+    integer values and x (every partial sum exact) both products equal the
+    oracle's, before and after the values are changed in place and the
+    plan refreshed."""
+    rng = np.random.default_rng(31)
+    A1 = gen.CSR(c2.n, c2.ncols, c2.rowptr, c2.colind, rng.integers(-8, 9, c2.nnz).astype(np.float64))
+    A2 = gen.CSR(c2.n, c2.ncols, c2.rowptr, c2.colind, rng.integers(-8, 9, c2.nnz).astype(np.float64))
+    x = gen.int_vec(c2.n, 7)
+    M = ctx.matrix_from_csr(A1, with_f32=True)
+    P = ctx.plan_class(M, 12)
+    assert P.describe()["j_per_lane"] == 32
+    for A in (A1, A2):
+        if A is A2:
+            M.val.copy_(dev(A2.val))
+            M.val32.copy_(dev(A2.val, torch.float32))
+            P.refresh()
+        yo, _ = oracle.spmv(A, x)
+        assert np.array_equal(ctx.spmv(P, dev(x)).cpu().numpy(), yo)
+        y32 = ctx.spmv(P, dev(x, torch.float32), ydtype=torch.float64, acc=xab.F64).cpu().numpy()
+        assert np.array_equal(y32, yo)
+
+
 @pytest.mark.parametrize("mode", [0, 1])
 def test_c2_gmres_true_residual(ctx, c2, mode):
     """GMRES(30) + Jacobi to 1e-10 on the full power-law matrix, FP64 and
