@@ -20,7 +20,6 @@ template <class T>
 int update_mdot(xab_ctx *ctx, const T *Vu, int nvu, const double *h, const T *Vd, int nvd, int64_t ldv, T *w,
                 int64_t n, double *part, int nb);
 int reduce_parts(xab_ctx *ctx, const double *part, int nb, int ldp, int m, double *out, int add, const int *gate);
-int dgks_gate(xab_ctx *ctx, const double *wn2, const double *wpn2, double eta, int *gate);
 // reduce_parts (m slots, no accumulate) and, from its last slot (the
 // squared norm after the first pass), the DGKS decision against *wn2
 int reduce_parts_dgks(xab_ctx *ctx, const double *part, int nb, int ldp, int m, double *out, const double *wn2,

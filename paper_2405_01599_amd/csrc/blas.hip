@@ -308,12 +308,6 @@ __global__ __launch_bounds__(kNT) void k_reduce_parts_dgks(const double *__restr
     }
 }
 
-// DGKS test: *gate = ||w'|| < eta ||w|| given squared norms (one thread).
-__global__ void k_dgks_gate(const double *__restrict__ wnorm2, const double *__restrict__ wpnorm2, double eta,
-                            int *__restrict__ gate) {
-    if (threadIdx.x == 0) *gate = (sqrt(*wpnorm2) < eta * sqrt(*wnorm2)) ? 1 : 0;
-}
-
 // v = w / sqrt(nrm2) (stored as T), z = v / d (Jacobi) or v, where nrm2 is
 // *nrm2_gated when a gate is given and set, else *nrm2
 template <class T>
@@ -464,12 +458,6 @@ int reduce_parts_dgks(xab_ctx *ctx, const double *part, int nb, int ldp, int m, 
     if (m <= 0) return XAB_OK;
     hipLaunchKernelGGL(k_reduce_parts_dgks, dim3(m), dim3(kNT), 0, ctx->stream, part, nb, ldp, m, out, wn2, eta, gate);
     XAB_LAUNCH_CHECK(ctx, "k_reduce_parts_dgks");
-    return XAB_OK;
-}
-
-int dgks_gate(xab_ctx *ctx, const double *wn2, const double *wpn2, double eta, int *gate) {
-    hipLaunchKernelGGL(k_dgks_gate, dim3(1), dim3(64), 0, ctx->stream, wn2, wpn2, eta, gate);
-    XAB_LAUNCH_CHECK(ctx, "k_dgks_gate");
     return XAB_OK;
 }
 

@@ -174,8 +174,8 @@ int recurrence_step(xab_ctx *ctx, const xab_plan *pl, Work &W, int j, int mc, in
     if ((s = xab::mdot<double>(ctx, V, W.ldv, j + 1, W.w, n, W.part, nb, nullptr)) != XAB_OK) return s;
     if ((s = xab::reduce_parts(ctx, W.part, nb, xab::kPartLd, j + 2, h1, 0, nullptr)) != XAB_OK) return s;
     if ((s = xab::update_mdot<double>(ctx, V, j + 1, h1, V, j + 1, W.ldv, W.w, n, W.part, nb)) != XAB_OK) return s;
-    if ((s = xab::reduce_parts(ctx, W.part, nb, xab::kPartLd, j + 2, h2, 0, nullptr)) != XAB_OK) return s;
-    if ((s = xab::dgks_gate(ctx, h1 + j + 1, h2 + j + 1, kEta, gate)) != XAB_OK) return s;
+    if ((s = xab::reduce_parts_dgks(ctx, W.part, nb, xab::kPartLd, j + 2, h2, h1 + j + 1, kEta, gate)) != XAB_OK)
+        return s;
     if ((s = xab::update_norm<double>(ctx, V, W.ldv, j + 1, h2, W.w, n, W.part, nb, gate)) != XAB_OK) return s;
     if ((s = xab::reduce_parts(ctx, W.part, nb, 1, 1, sc, 0, gate)) != XAB_OK) return s;
     return xab::scale_precond<double>(ctx, W.w, h2 + j + 1, V + (int64_t)(j + 1) * W.ldv, nullptr, nullptr, n, sc,
