@@ -245,11 +245,14 @@ def test_xcb_plan_bitexact(ctx):
             assert np.array_equal(P.array(10), ci), (name, J)
 
 
+@pytest.mark.parametrize("name", ["powerlaw50k", "trans4", "one_long_row"])
 @pytest.mark.parametrize("J", [1, 2, 4, 8, 16, 32])
-def test_xcb_all_lane_widths(ctx, J):
-    # about 125k entries per column block: many full tiles and a ragged
-    # last tile in each block at every J
-    A = _int_version(gen.powerlaw(50_000, seed=2))
+def test_xcb_all_lane_widths(ctx, J, name):
+    # power-law: about 125k entries per column block, many full tiles and a
+    # ragged last tile in each block at every J; trans4: one row of 114,910
+    # entries whose part in each block spans many tiles (carries through
+    # interleaved full tiles); a 3000-entry row in a tiny matrix
+    A = _int_version(gen.powerlaw(50_000, seed=2) if name == "powerlaw50k" else GENERAL[name])
     x = gen.int_vec(A.ncols, 2)
     yo, _ = oracle.spmv(A, x)
     M = ctx.matrix_from_csr(A, with_f32=True)
