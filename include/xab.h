@@ -143,6 +143,10 @@ typedef struct {
     int32_t col_block;     /* SYM_S3: column block size C of the touch map (power of two) */
     int32_t tile_rows;     /* SYM_S3: maximum rows per tile (<= 2048); SELL: sorting window
                               (a multiple of 64, at most 1024) */
+    int32_t xcb_slices;    /* XCB: column slices walked one after another, each cut into 8
+                              blocks (one per XCD), a power of two in 1..64; 0: from the size,
+                              the fewest that keep every block under 262,144 columns (2 MB of
+                              FP64 x, half an XCD's L2) */
 } xab_params;
 
 /* Matrix flags */

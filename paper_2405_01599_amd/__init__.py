@@ -42,7 +42,7 @@ class XabError(RuntimeError):
 
 class Params(ctypes.Structure):
     _fields_ = [("lanes_per_row", ctypes.c_int32), ("tile_nnz", ctypes.c_int32), ("j_per_lane", ctypes.c_int32),
-                ("col_block", ctypes.c_int32), ("tile_rows", ctypes.c_int32)]
+                ("col_block", ctypes.c_int32), ("tile_rows", ctypes.c_int32), ("xcb_slices", ctypes.c_int32)]
 
 
 class InitOpts(ctypes.Structure):
@@ -522,7 +522,7 @@ class Plan:
     def describe(self):
         p = self.params
         return dict(variant=VARIANT_NAMES[self.variant], lanes_per_row=p.lanes_per_row, tile_nnz=p.tile_nnz,
-                    j_per_lane=p.j_per_lane, col_block=p.col_block, tile_rows=p.tile_rows)
+                    j_per_lane=p.j_per_lane, col_block=p.col_block, tile_rows=p.tile_rows, xcb_slices=p.xcb_slices)
 
     def close(self):
         if getattr(self, "h", None) and self.ctx.h:

@@ -120,6 +120,12 @@ struct xab_plan {
     void *xcb_Y = nullptr;              // compressed partial products, acc-type, ybase[kXcb] slots
     int64_t xcb_G = 0;                  // row groups of 256 (the combine's workgroups)
     int32_t *xcb_gbase = nullptr;       // kXcb * (G + 1): compressed index of group g's first row in block k
+    // column window of this plan's blocks (the whole matrix unless it is
+    // one slice of a sliced plan) and, for a sliced plan, one plan per
+    // slice plus the accumulation-type sum carried from slice to slice
+    int32_t xcb_c0 = 0, xcb_c1 = 0;
+    std::vector<xab_plan *> xcb_sub;
+    void *xcb_ysum = nullptr;
     // FP32 values walked with fewer entries per lane than FP64 ones (when
     // the plan chose J from the size): their own lane-interleaved copy of
     // the columns and their own tiles; partials, mask and group offsets

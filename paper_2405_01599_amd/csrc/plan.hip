@@ -228,7 +228,9 @@ struct ColBlocks {
     int32_t cb[xab_plan::kXcb + 1];  // block k = columns [cb[k], cb[k+1])
 };
 
+// the column block of col, -1 outside the window [cb[0], cb[kXcb])
 __device__ __forceinline__ int col_block_of(const ColBlocks &c, int32_t col) {
+    if (col < c.cb[0] || col >= c.cb[xab_plan::kXcb]) return -1;
     int k = 0;
 #pragma unroll
     for (int q = 1; q < xab_plan::kXcb; ++q) k += col >= c.cb[q];
@@ -501,6 +503,7 @@ __global__ void k_xcb_scatter(const int32_t *rowptr, const int32_t *colind, cons
     for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
         int32_t col = colind[e];
         int k = col_block_of(c, col);
+        if (k < 0) continue;
         int64_t p = 0;
 #pragma unroll
         for (int q = 0; q < xab_plan::kXcb; ++q)
@@ -741,6 +744,10 @@ unsigned grid_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 }  // namespace
 
 static void free_plan_arrays(xab_ctx *ctx, xab_plan *pl) {
+    for (xab_plan *q : pl->xcb_sub) xab_plan_destroy(q);
+    pl->xcb_sub.clear();
+    xab_dfree(ctx, pl->xcb_ysum);
+    pl->xcb_ysum = nullptr;
     xab_dfree(ctx, pl->b);
     xab_dfree(ctx, pl->row_lo);
     xab_dfree(ctx, pl->tile_row);
@@ -805,7 +812,8 @@ static size_t plan_device_bytes(const xab_plan *pl) {
                             pl->xcb_carry_val, pl->xcb_tail_val, pl->xcb_Y, pl->xcb_colind32, pl->xcb_row_lo32,
                             pl->xcb_tile_row32, pl->xcb_carry_row32, pl->xcb_tail_row32, pl->xcb_carry_val32,
                             pl->xcb_tail_val32};
-    size_t t = 0;
+    size_t t = xab_dbytes(c, pl->xcb_ysum);
+    for (const xab_plan *q : pl->xcb_sub) t += plan_device_bytes(q);
     for (const void *p : arrays) t += xab_dbytes(c, p);
     return t;
 }
@@ -909,7 +917,19 @@ void xab_launch_split_bss(hipStream_t st, const int32_t *rowptr, int32_t n, int6
                        carry_row);
 }
 
-int xab_build_plan(xab_ctx *ctx, const xab_matrix *A, xab_variant v, const xab_params *pp, xab_plan **out) {
+// XCB column slices: as asked, else the fewest (a power of two) that keep
+// every one of a slice's 8 blocks under 262,144 columns
+static int32_t xcb_slice_count(const xab_params &p, int32_t ncols) {
+    if (p.xcb_slices > 0) return p.xcb_slices;
+    int32_t S = 1;
+    while (S < 64 && ((int64_t)ncols + 8 * (int64_t)S - 1) / (8 * (int64_t)S) > 262144) S *= 2;
+    return S;
+}
+
+// A plan over the whole matrix; for XCB, of the column window [c0, c1)
+// (one slice of a sliced plan).
+static int build_plan(xab_ctx *ctx, const xab_matrix *A, xab_variant v, const xab_params *pp, int32_t c0, int32_t c1,
+                      xab_plan **out) {
     if (!ctx || !A || !pp || !out) return XAB_E_NULL;
     *out = nullptr;
     xab_params p = *pp;
@@ -929,12 +949,14 @@ int xab_build_plan(xab_ctx *ctx, const xab_matrix *A, xab_variant v, const xab_p
             break;
         case XAB_BSS:
         case XAB_XCB:
-            if (v == XAB_XCB && p.j_per_lane == 0) {
-                // entries per lane from the size: the largest of 4, 8, 16 and
-                // 32 that still cuts the matrix into at least 4096 tiles (16
-                // per CU); more entries per lane keep more gathers in flight
-                p.j_per_lane = 4;
-                while (p.j_per_lane < 32 && A->nnz >= (int64_t)4096 * 256 * (2 * p.j_per_lane)) p.j_per_lane *= 2;
+            if (v == XAB_XCB) {
+                // 0: entries per lane chosen from the size once the plan
+                // has counted its entries
+                if (p.j_per_lane != 0 && (p.j_per_lane < 1 || p.j_per_lane > 32 || !pow2(p.j_per_lane)))
+                    return xab_fail(ctx, XAB_E_UNSUPPORTED, "j_per_lane must be 0 or a power of two in [1, 32]");
+                if (p.xcb_slices != 0 && (!pow2(p.xcb_slices) || p.xcb_slices > 64))
+                    return xab_fail(ctx, XAB_E_UNSUPPORTED, "xcb_slices must be 0 or a power of two in [1, 64]");
+                break;
             }
             if (p.j_per_lane < 1 || p.j_per_lane > 32 || !pow2(p.j_per_lane))
                 return xab_fail(ctx, XAB_E_UNSUPPORTED, "j_per_lane must be a power of two in [1, 32]");
@@ -1064,20 +1086,35 @@ int xab_build_plan(xab_ctx *ctx, const xab_matrix *A, xab_variant v, const xab_p
             delete pl;
             return xab_hip_check(ctx, e, "BCSR fill");
         }
+    } else if (v == XAB_XCB && c0 == 0 && c1 == A->ncols && xcb_slice_count(p, A->ncols) > 1) {
+        // column slices walked one after another, each an XCB plan of its
+        // own over 8 blocks (one per XCD) of its columns; the products add
+        // up in slice order through an accumulation-type sum
+        const int32_t S = xcb_slice_count(p, A->ncols);
+        xab_params q = p;
+        q.xcb_slices = 1;
+        pl->xcb_sub.assign((size_t)S, nullptr);
+        for (int32_t i = 0; i < S; ++i) {
+            const int32_t s0 = (int32_t)((int64_t)A->ncols * i / S), s1 = (int32_t)((int64_t)A->ncols * (i + 1) / S);
+            CHECKED(build_plan(ctx, A, v, &q, s0, s1, &pl->xcb_sub[(size_t)i]));
+            pl->P = std::max(pl->P, pl->xcb_sub[(size_t)i]->P);
+        }
+        pl->params.j_per_lane = pl->xcb_sub[0]->params.j_per_lane;
+        pl->params.xcb_slices = S;
+        ALLOC(pl->xcb_ysum, double, std::max<int64_t>(1, n));
     } else if (v == XAB_XCB) {
         constexpr int KB = xab_plan::kXcb;
-        const int64_t T = 256 * (int64_t)p.j_per_lane;
+        pl->params.xcb_slices = 1;
+        pl->xcb_c0 = c0;
+        pl->xcb_c1 = c1;
         ColBlocks cbk;
-        for (int k = 0; k <= KB; ++k) cbk.cb[k] = (int32_t)((int64_t)k * A->ncols / KB);
+        for (int k = 0; k <= KB; ++k) cbk.cb[k] = (int32_t)(c0 + (int64_t)k * (c1 - c0) / KB);
         pl->P = 0;
         // per-row block counts -> per-block row pointers -> stable scatter
         int32_t *cnt = nullptr, *sums = nullptr, *offs = nullptr;
         int64_t *dbase = nullptr;
         const int64_t ntile = (n + kScanTile - 1) / kScanTile;
         ALLOC(pl->xcb_rowptr, int32_t, (int64_t)KB * (n + 1));
-        ALLOC(pl->xcb_colind, int32_t, std::max<int64_t>(1, nnz));
-        if (A->has64) ALLOC(pl->xcb_val64, double, std::max<int64_t>(1, nnz));
-        if (A->has32) ALLOC(pl->xcb_val32, float, std::max<int64_t>(1, nnz));
         cnt = (int32_t *)xab_dalloc(ctx, sizeof(int32_t) * (size_t)KB * std::max<int32_t>(1, n));
         // scans of up to max(1, ntile) tile sums write one slot past them
         sums = (int32_t *)xab_dalloc(ctx, sizeof(int32_t) * (ntile + 2));
@@ -1116,12 +1153,34 @@ int xab_build_plan(xab_ctx *ctx, const xab_matrix *A, xab_variant v, const xab_p
             delete pl;
             return xab_hip_check(ctx, e, "column-block counts");
         }
+        // the window's entries, and the copies of them
+        int64_t wnnz = 0;
+        for (int k = 0; k < KB; ++k) wnnz += tot[k];
+        pl->xcb_colind = (int32_t *)xab_dalloc(ctx, sizeof(int32_t) * (size_t)std::max<int64_t>(1, wnnz));
+        if (A->has64) pl->xcb_val64 = (double *)xab_dalloc(ctx, sizeof(double) * (size_t)std::max<int64_t>(1, wnnz));
+        if (A->has32) pl->xcb_val32 = (float *)xab_dalloc(ctx, sizeof(float) * (size_t)std::max<int64_t>(1, wnnz));
+        if (!pl->xcb_colind || (A->has64 && !pl->xcb_val64) || (A->has32 && !pl->xcb_val32)) {
+            free_tmp();
+            free_plan_arrays(ctx, pl);
+            delete pl;
+            return xab_fail(ctx, XAB_E_NOMEM, "plan allocation");
+        }
+        // entries per lane from the size (j_per_lane 0): the largest of 4,
+        // 8, 16 and 32 that still cuts the window into at least 4096 tiles
+        // (16 per CU); more entries per lane keep more gathers in flight
+        if (pp->j_per_lane == 0) {
+            int32_t J = 4;
+            while (J < 32 && wnnz >= (int64_t)4096 * 256 * (2 * J)) J *= 2;
+            pl->params.j_per_lane = J;
+        }
+        p.j_per_lane = pl->params.j_per_lane;
+        const int64_t T = 256 * (int64_t)p.j_per_lane;
         // FP32 values: the size rule capped at 16 entries per lane (their
         // products then keep more workgroups per CU); only when the plan
         // chose J from the size and that gives a different J
         if (pp->j_per_lane == 0 && A->has32) {
             int32_t j32 = 4;
-            while (j32 < 16 && nnz >= (int64_t)4096 * 256 * (2 * j32)) j32 *= 2;
+            while (j32 < 16 && wnnz >= (int64_t)4096 * 256 * (2 * j32)) j32 *= 2;
             pl->xcb_j32 = j32 < p.j_per_lane ? j32 : 0;
         }
         const int64_t T32 = 256 * (int64_t)pl->xcb_j32;
@@ -1216,7 +1275,7 @@ int xab_build_plan(xab_ctx *ctx, const xab_matrix *A, xab_variant v, const xab_p
             pl->xcb_tail_row32 = (int32_t *)xab_dalloc(ctx, sizeof(int32_t) * (size_t)t32);
             pl->xcb_carry_val32 = xab_dalloc(ctx, sizeof(double) * (size_t)t32);
             pl->xcb_tail_val32 = xab_dalloc(ctx, sizeof(double) * (size_t)t32);
-            pl->xcb_colind32 = (int32_t *)xab_dalloc(ctx, sizeof(int32_t) * (size_t)std::max<int64_t>(1, nnz));
+            pl->xcb_colind32 = (int32_t *)xab_dalloc(ctx, sizeof(int32_t) * (size_t)std::max<int64_t>(1, wnnz));
         }
         const bool miss32 = pl->xcb_j32 && (!pl->xcb_row_lo32 || !pl->xcb_tile_row32 || !pl->xcb_carry_row32 ||
                                             !pl->xcb_tail_row32 || !pl->xcb_carry_val32 || !pl->xcb_tail_val32 ||
@@ -1247,15 +1306,15 @@ int xab_build_plan(xab_ctx *ctx, const xab_matrix *A, xab_variant v, const xab_p
         CHECKED(hip_ok(ctx, e, "column-block tiles"));
         // full tiles in lane-interleaved 16-byte groups (columns and each
         // value copy; the FP32 walk's columns and values by its own J)
-        if (pl->xcb_j32 && nnz > 0) {
-            e = hipMemcpyAsync(pl->xcb_colind32, pl->xcb_colind, sizeof(int32_t) * (size_t)nnz,
+        if (pl->xcb_j32 && wnnz > 0) {
+            e = hipMemcpyAsync(pl->xcb_colind32, pl->xcb_colind, sizeof(int32_t) * (size_t)wnnz,
                                hipMemcpyDeviceToDevice, st);
             CHECKED(hip_ok(ctx, e, "FP32 walk columns"));
         }
         auto interleave = [&](auto *&arr, int32_t J) -> hipError_t {
             using E = std::remove_reference_t<decltype(*arr)>;
-            if (!arr || nnz == 0 || J <= (int)(16 / sizeof(E))) return hipSuccess;
-            E *out = (E *)xab_dalloc(ctx, sizeof(E) * (size_t)nnz);
+            if (!arr || wnnz == 0 || J <= (int)(16 / sizeof(E))) return hipSuccess;
+            E *out = (E *)xab_dalloc(ctx, sizeof(E) * (size_t)wnnz);
             if (!out) return hipErrorOutOfMemory;
             for (int k = 0; k < KB; ++k) {
                 const int64_t b = pl->xcb_base[k], m = pl->xcb_base[k + 1] - b;
@@ -1495,6 +1554,11 @@ int xab_build_plan(xab_ctx *ctx, const xab_matrix *A, xab_variant v, const xab_p
     return XAB_OK;
 }
 
+int xab_build_plan(xab_ctx *ctx, const xab_matrix *A, xab_variant v, const xab_params *pp, xab_plan **out) {
+    if (!A) return XAB_E_NULL;
+    return build_plan(ctx, A, v, pp, 0, A->ncols, out);
+}
+
 extern "C" {
 
 int xab_plan_fixed(xab_ctx *ctx, const xab_matrix *A, xab_variant v, const xab_params *p, xab_plan **plan) {
@@ -1527,12 +1591,17 @@ int xab_plan_refresh(xab_plan *pl) {
     const double *v64 = A->has64 ? A->val64 : nullptr;
     const float *v32 = A->has32 ? A->val32 : nullptr;
     hipError_t e = hipSuccess;
-    if (pl->variant == XAB_XCB && nnz > 0) {
+    for (xab_plan *q : pl->xcb_sub) {
+        const int s = xab_plan_refresh(q);
+        if (s != XAB_OK) return s;
+    }
+    if (pl->variant == XAB_XCB && nnz > 0 && pl->xcb_colind) {
         // values into block order (the plan's per-block row pointers and
         // block bases), then into the stored tile layout
         constexpr int KB = xab_plan::kXcb;
         ColBlocks cbk;
-        for (int k = 0; k <= KB; ++k) cbk.cb[k] = (int32_t)((int64_t)k * A->ncols / KB);
+        for (int k = 0; k <= KB; ++k)
+            cbk.cb[k] = (int32_t)(pl->xcb_c0 + (int64_t)k * (pl->xcb_c1 - pl->xcb_c0) / KB);
         int64_t *dbase = (int64_t *)xab_dalloc(ctx, sizeof(int64_t) * (KB + 1));
         double *t64 = pl->xcb_val64 ? (double *)xab_dalloc(ctx, sizeof(double) * (size_t)nnz) : nullptr;
         float *t32 = pl->xcb_val32 ? (float *)xab_dalloc(ctx, sizeof(float) * (size_t)nnz) : nullptr;
@@ -1612,7 +1681,7 @@ int xab_plan_array(const xab_plan *pl, int32_t which, int32_t *h_out, int64_t *l
         case 7: src = pl->tile_blk; m = pl->tile_blk ? pl->ntouch : 0; break;
         case 8: src = pl->tile_slot; m = pl->tile_slot ? pl->ntouch : 0; break;
         case 9: src = pl->xcb_rowptr; m = pl->xcb_rowptr ? (int64_t)xab_plan::kXcb * (pl->A->n + 1) : 0; break;
-        case 10: src = pl->xcb_colind; m = pl->xcb_colind ? pl->A->nnz : 0; break;
+        case 10: src = pl->xcb_colind; m = pl->xcb_colind ? pl->xcb_base[xab_plan::kXcb] : 0; break;
         case 11: src = pl->sell.perm; m = pl->sell.perm ? pl->A->n : 0; break;
         case 12: src = pl->sell.rlen; m = pl->sell.rlen ? pl->A->n : 0; break;
         case 13: src = pl->sell.clen; m = pl->sell.clen ? pl->sell.nch : 0; break;

@@ -189,10 +189,13 @@ __global__ void k_xcb_fixup(XcbArgs a, int64_t pmax) {
 // order.  Workgroup g covers rows [256g, 256g + 256); the compressed index
 // of row i in block k is gbase[k][g] plus the rows of the group before i
 // with bit k, counted with wave ballots.
+// A sliced plan runs one such product per column slice: the first starts
+// the accumulation-type sum ysum (mode 1), the middle ones add to it (2),
+// the last adds and writes y (3); an unsliced plan writes y directly (0).
 template <class YT, class AT>
 __global__ __launch_bounds__(kNT) void k_xcb_combine(XcbArgs a, const uint8_t *__restrict__ mask,
                                                      const int32_t *__restrict__ gbase, int64_t G, int64_t n,
-                                                     YT *__restrict__ y) {
+                                                     YT *__restrict__ y, AT *__restrict__ ysum, int mode) {
     constexpr int NW = kNT / kWave;
     __shared__ int wcnt[kXcds][NW];
     const int64_t g = blockIdx.x;
@@ -219,10 +222,11 @@ __global__ __launch_bounds__(kNT) void k_xcb_combine(XcbArgs a, const uint8_t *_
         for (int q = 0; q < w; ++q) off += wcnt[k][q];
         v[k] = ((m >> k) & 1u) ? ((const AT *)a.Y[k])[off] : AT(0);
     }
-    AT acc = AT(0);
+    AT acc = mode >= 2 ? ysum[i] : AT(0);
 #pragma unroll
     for (int k = 0; k < kXcds; ++k) acc = ((m >> k) & 1u) ? acc + v[k] : acc;
-    y[i] = (YT)acc;
+    if (mode == 1 || mode == 2) ysum[i] = acc;
+    else y[i] = (YT)acc;
 }
 
 }  // namespace
@@ -237,7 +241,8 @@ struct XcbWalk {
 };
 
 template <class VT, class XT, class YT, class AT, int J>
-static int launch_xcb_j(xab_ctx *ctx, const xab_plan *pl, const XcbWalk &wk, const XT *x, YT *y) {
+static int launch_xcb_j(xab_ctx *ctx, const xab_plan *pl, const XcbWalk &wk, const XT *x, YT *y, AT *ysum,
+                        int mode) {
     const xab_matrix *A = pl->A;
     constexpr int KB = xab_plan::kXcb;
     static_assert(KB == kXcds, "one column block per XCD");
@@ -266,14 +271,14 @@ static int launch_xcb_j(xab_ctx *ctx, const xab_plan *pl, const XcbWalk &wk, con
     hipLaunchKernelGGL((k_xcb_fixup<AT>), dim3(grid_for(KB * pmax, 256)), dim3(256), 0, ctx->stream, a, pmax);
     XAB_LAUNCH_CHECK(ctx, "k_xcb_fixup");
     hipLaunchKernelGGL((k_xcb_combine<YT, AT>), dim3((unsigned)pl->xcb_G), dim3(kNT), 0, ctx->stream, a,
-                       pl->xcb_mask, pl->xcb_gbase, pl->xcb_G, n, y);
+                       pl->xcb_mask, pl->xcb_gbase, pl->xcb_G, n, y, ysum, mode);
     XAB_LAUNCH_CHECK(ctx, "k_xcb_combine");
     return XAB_OK;
 }
 
+// One product of one XCB plan (the whole matrix, or one column slice).
 template <class VT, class XT, class YT, class AT>
-int launch_xcb(xab_ctx *ctx, const xab_plan *pl, const VT *val, const XT *x, YT *y) {
-    (void)val;  // the plan holds its own column-blocked copy of the values
+static int launch_xcb_plan(xab_ctx *ctx, const xab_plan *pl, const XT *x, YT *y, AT *ysum, int mode) {
     if ((sizeof(VT) == 8 && !pl->xcb_val64) || (sizeof(VT) == 4 && !pl->xcb_val32))
         return xab_fail(ctx, XAB_E_DTYPE, "column-blocked plan holds no values of this precision");
     const bool own32 = sizeof(VT) == 4 && pl->xcb_j32 > 0;
@@ -283,14 +288,29 @@ int launch_xcb(xab_ctx *ctx, const xab_plan *pl, const VT *val, const XT *x, YT 
                              : XcbWalk{pl->xcb_colind, pl->xcb_P, pl->xcb_toff, pl->xcb_tile_row, pl->xcb_carry_row,
                                        pl->xcb_tail_row, pl->xcb_carry_val, pl->xcb_tail_val};
     switch (own32 ? pl->xcb_j32 : pl->params.j_per_lane) {
-        case 1: return launch_xcb_j<VT, XT, YT, AT, 1>(ctx, pl, wk, x, y);
-        case 2: return launch_xcb_j<VT, XT, YT, AT, 2>(ctx, pl, wk, x, y);
-        case 4: return launch_xcb_j<VT, XT, YT, AT, 4>(ctx, pl, wk, x, y);
-        case 8: return launch_xcb_j<VT, XT, YT, AT, 8>(ctx, pl, wk, x, y);
-        case 16: return launch_xcb_j<VT, XT, YT, AT, 16>(ctx, pl, wk, x, y);
-        case 32: return launch_xcb_j<VT, XT, YT, AT, 32>(ctx, pl, wk, x, y);
+        case 1: return launch_xcb_j<VT, XT, YT, AT, 1>(ctx, pl, wk, x, y, ysum, mode);
+        case 2: return launch_xcb_j<VT, XT, YT, AT, 2>(ctx, pl, wk, x, y, ysum, mode);
+        case 4: return launch_xcb_j<VT, XT, YT, AT, 4>(ctx, pl, wk, x, y, ysum, mode);
+        case 8: return launch_xcb_j<VT, XT, YT, AT, 8>(ctx, pl, wk, x, y, ysum, mode);
+        case 16: return launch_xcb_j<VT, XT, YT, AT, 16>(ctx, pl, wk, x, y, ysum, mode);
+        case 32: return launch_xcb_j<VT, XT, YT, AT, 32>(ctx, pl, wk, x, y, ysum, mode);
         default: return xab_fail(ctx, XAB_E_UNSUPPORTED, "j_per_lane %d", pl->params.j_per_lane);
     }
+}
+
+template <class VT, class XT, class YT, class AT>
+int launch_xcb(xab_ctx *ctx, const xab_plan *pl, const VT *val, const XT *x, YT *y) {
+    (void)val;  // the plan holds its own column-blocked copy of the values
+    if (pl->xcb_sub.empty()) return launch_xcb_plan<VT, XT, YT, AT>(ctx, pl, x, y, nullptr, 0);
+    // column slices one after another, summed in slice order
+    AT *ysum = (AT *)pl->xcb_ysum;
+    const size_t S = pl->xcb_sub.size();
+    for (size_t s = 0; s < S; ++s) {
+        const int mode = s == 0 ? 1 : (s + 1 < S ? 2 : 3);
+        const int st = launch_xcb_plan<VT, XT, YT, AT>(ctx, pl->xcb_sub[s], x, y, ysum, mode);
+        if (st != XAB_OK) return st;
+    }
+    return XAB_OK;
 }
 
 XAB_INSTANTIATE_LAUNCHER(launch_xcb)

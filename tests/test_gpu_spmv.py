@@ -582,3 +582,64 @@ def test_plan_refresh_drops_the_jacobi_diagonal(ctx):
 def test_plan_refresh_errors():
     import ctypes
     assert xab.lib().xab_plan_refresh(None) == -1
+
+
+# ----------------------------------------------------------------- XCB column slices
+@pytest.mark.parametrize("S", [2, 4])
+@pytest.mark.parametrize("J", [0, 4, 32])
+def test_xcb_sliced_integer_exact(ctx, S, J):
+    # S column slices walked one after another (8 blocks each), summed in
+    # slice order: integer products exact in every precision combination,
+    # before and after a value refresh; J = 0 chooses each slice's entries
+    # per lane from its own size
+    A1 = _int_version(gen.powerlaw(50_000, seed=2), seed=5)
+    A2 = _int_version(gen.powerlaw(50_000, seed=2), seed=9)
+    x = gen.int_vec(A1.ncols, 2)
+    M = ctx.matrix_from_csr(A1, with_f32=True)
+    P = ctx.plan(M, xab.XCB, j_per_lane=J, xcb_slices=S)
+    assert P.describe()["xcb_slices"] == S
+    assert P.array(10).size == 0  # the slices hold the copies
+    for A in (A1, A2):
+        if A is A2:
+            M.val.copy_(dev(A2.val))
+            M.val32.copy_(dev(A2.val, torch.float32))
+            P.refresh()
+        yo, _ = oracle.spmv(A, x)
+        assert np.array_equal(ctx.spmv(P, dev(x)).cpu().numpy(), yo)
+        for ydt, acc in ((torch.float64, xab.F64), (torch.float32, xab.F64), (torch.float32, xab.F32)):
+            y = ctx.spmv(P, dev(x, torch.float32), ydtype=ydt, acc=acc).double().cpu().numpy()
+            assert np.array_equal(y, yo), (ydt, acc)
+
+
+@pytest.mark.parametrize("name", sorted(GENERAL))
+def test_xcb_sliced_general_suite(ctx, name):
+    # empty rows and matrices, a single row, 3000- and 114,910-entry rows,
+    # fewer columns than blocks per slice
+    A = _int_version(GENERAL[name])
+    x = gen.int_vec(A.ncols, 4)
+    yo, _ = oracle.spmv(A, x)
+    M = ctx.matrix_from_csr(A)
+    for S in (2, 8):
+        P = ctx.plan(M, xab.XCB, j_per_lane=8, xcb_slices=S)
+        assert np.array_equal(ctx.spmv(P, dev(x)).cpu().numpy(), yo), S
+
+
+def test_xcb_sliced_fp64_gate_and_reruns(ctx):
+    A = gen.powerlaw(60_000, seed=3)
+    x = gen.uniform_vec(A.ncols, 5)
+    yo, s = oracle.spmv(A, x)
+    M = ctx.matrix_from_csr(A)
+    P = ctx.plan(M, xab.XCB, j_per_lane=16, xcb_slices=4)
+    y0 = ctx.spmv(P, dev(x))
+    assert np.all(np.abs(y0.cpu().numpy() - yo) <= 1e-12 * s)
+    for _ in range(5):
+        assert torch.equal(ctx.spmv(P, dev(x)), y0)
+
+
+def test_xcb_slice_count_from_the_size(ctx):
+    # up to 262,144 columns per block: one slice below 2,097,153 columns
+    A = gen.powerlaw(50_000, seed=2)
+    M = ctx.matrix_from_csr(A)
+    assert ctx.plan_class(M, 12).describe()["xcb_slices"] == 1
+    with pytest.raises(xab.XabError):
+        ctx.plan(M, xab.XCB, j_per_lane=8, xcb_slices=3)
