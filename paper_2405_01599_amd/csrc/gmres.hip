@@ -16,12 +16,14 @@
 // The Hessenberg column, the Givens rotations and the residual recurrence
 // of each Arnoldi step run on the device (one small kernel at the end of
 // the step), so a cycle's steps are queued back to back: the host never
-// waits for the step the GPU is running.  It waits on the event of the
-// step before that one (to stop queueing once a step has met the
-// threshold or broken down), and on the running step too only when the
-// recurrence is about to meet the threshold.  A step queued after the
-// stopping one computes into the next basis slot and leaves the rotated
-// system alone.  The host reads the rotated system back once per cycle.
+// waits for the step the GPU is running.  It waits for the step before
+// that one (to stop queueing once a step has met the threshold or broken
+// down), and for the running step too only when the recurrence is about
+// to meet the threshold, by reading the step counter the step kernel
+// publishes in coherent host memory: no marker packet sits between two
+// steps on the stream.  A step queued after the stopping one computes
+// into the next basis slot and leaves the rotated system alone.  The host
+// reads the rotated system back once per cycle.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -69,13 +71,10 @@ struct Work {
     double *host = nullptr;  // pinned: the rotated system's read-back, then y
     Mirror *mir = nullptr;   // coherent pinned, written by the step kernel
     Mirror *mir_dev = nullptr;
-    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     ~Work() {
         if (base) xab_dfree(ctx, base);
         if (host) (void)hipHostFree(host);
         if (mir) (void)hipHostFree(mir);
-        for (auto e : ev)
-            if (e) (void)hipEventDestroy(e);
     }
 };
 
@@ -203,11 +202,6 @@ int alloc_work(xab_ctx *ctx, Work &W, int64_t n, int m, size_t tsize) {
     }
     if (hipHostGetDevicePointer((void **)&W.mir_dev, W.mir, 0) != hipSuccess)
         return xab_fail(ctx, XAB_E_DEVICE, "device address of the step mirror");
-    for (auto &e : W.ev)
-        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
-            e = nullptr;
-            return xab_fail(ctx, XAB_E_DEVICE, "step events");
-        }
     return XAB_OK;
 }
 
@@ -256,8 +250,22 @@ int cycle(xab_ctx *ctx, const xab_plan *pl, xab_matrix *A, Work &W, int m, doubl
     hipLaunchKernelGGL(k_gmres_cycle_init, dim3(1), dim3(64), 0, ctx->stream, beta, tol_abs, W.g, W.st);
     XAB_LAUNCH_CHECK(ctx, "k_gmres_cycle_init");
     out.breakdown = false;
+    // until step q's kernel has published its rotation: a spin on the
+    // counter in coherent host memory; a step that has not reported within 20 ms
+    // (a very large matrix, or a failed launch) is waited for by draining
+    // the stream, which also returns any error of the queued work
     auto wait_step = [&](int q) -> int {
-        XAB_HIP(ctx, hipEventSynchronize(W.ev[q & 3]));
+        const volatile int *done = &mir->done;
+        if (*done >= q) return XAB_OK;
+        const auto t0 = std::chrono::steady_clock::now();
+        while (*done < q) {
+            if (std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(20)) {
+                XAB_HIP(ctx, hipStreamSynchronize(ctx->stream));
+                break;
+            }
+            __builtin_ia32_pause();
+        }
+        __atomic_thread_fence(__ATOMIC_ACQUIRE);  // no read of the mirror moves above the wait
         return XAB_OK;
     };
     for (int j = 0; j < m && j < max_steps; ++j) {
@@ -325,7 +333,6 @@ int cycle(xab_ctx *ctx, const xab_plan *pl, xab_matrix *A, Work &W, int m, doubl
                            dgks ? 1 : 0, W.h1, W.h2, W.sc, W.gate, w, vn, z, d, n, nblk, W.H, W.cs, W.sn, W.g, W.st,
                            W.mir_dev);
         XAB_LAUNCH_CHECK(ctx, "k_gmres_step_end");
-        XAB_HIP(ctx, hipEventRecord(W.ev[j & 3], ctx->stream));
     }
     // one read-back of the rotated system per cycle
     XAB_HIP(ctx, hipMemcpyAsync(W.host, W.H, W.sys_bytes, hipMemcpyDeviceToHost, ctx->stream));
