@@ -263,7 +263,9 @@ int cycle(xab_ctx *ctx, const xab_plan *pl, xab_matrix *A, Work &W, int m, doubl
                 XAB_HIP(ctx, hipStreamSynchronize(ctx->stream));
                 break;
             }
+#if defined(__x86_64__)
             __builtin_ia32_pause();
+#endif
         }
         __atomic_thread_fence(__ATOMIC_ACQUIRE);  // no read of the mirror moves above the wait
         return XAB_OK;
