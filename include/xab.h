@@ -434,6 +434,10 @@ typedef struct {
  * and the relative recurrence residual after each of its steps); below
  * mm_ratio the cycle is judged stagnant and m grows by restart_step, up to
  * m_max.  In IR mode the samples are those of the inner cycle.
+ * Inside a cycle the host waits for a step by polling a counter that the
+ * step's last kernel writes to pinned host memory; after XAB_STEP_WAIT_MS
+ * milliseconds without it (environment variable, default 20; 0 drains at
+ * once) it drains the stream instead, with the same result.
  * Synchronous. */
 int xab_gmres(xab_ctx *ctx, const xab_plan *plan, const double *d_b, double *d_x, const xab_krylov_opts *opts,
               xab_krylov_info *info);

@@ -27,6 +27,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -251,15 +252,18 @@ int cycle(xab_ctx *ctx, const xab_plan *pl, xab_matrix *A, Work &W, int m, doubl
     XAB_LAUNCH_CHECK(ctx, "k_gmres_cycle_init");
     out.breakdown = false;
     // until step q's kernel has published its rotation: a spin on the
-    // counter in coherent host memory; a step that has not reported within 20 ms
-    // (a very large matrix, or a failed launch) is waited for by draining
-    // the stream, which also returns any error of the queued work
+    // counter in coherent host memory; a step that has not reported within
+    // the spin limit (20 ms, or XAB_STEP_WAIT_MS; a very large matrix, or a
+    // failed launch) is waited for by draining the stream, which also
+    // returns any error of the queued work
+    const char *wenv = getenv("XAB_STEP_WAIT_MS");
+    const long wait_ms = wenv && *wenv ? std::max(0L, strtol(wenv, nullptr, 10)) : 20L;
     auto wait_step = [&](int q) -> int {
         const volatile int *done = &mir->done;
         if (*done >= q) return XAB_OK;
         const auto t0 = std::chrono::steady_clock::now();
         while (*done < q) {
-            if (std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(20)) {
+            if (std::chrono::steady_clock::now() - t0 >= std::chrono::milliseconds(wait_ms)) {
                 XAB_HIP(ctx, hipStreamSynchronize(ctx->stream));
                 break;
             }

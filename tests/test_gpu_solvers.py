@@ -146,6 +146,26 @@ def test_gmres_resume_from_x(ctx):
     assert st2 == 0 and info2["iters"] == 0
 
 
+@pytest.mark.parametrize("mode", [xab.MODE_FP64, xab.MODE_IR])
+def test_gmres_step_wait_drain_fallback(ctx, mode, monkeypatch):
+    """The host waits for a step through the counter the step kernel writes
+    to pinned memory and drains the stream when it has not arrived within
+    XAB_STEP_WAIT_MS; at 0 every wait drains.  The queued kernels and their
+    order are the same either way (steps queued past the stop touch neither
+    the rotated system nor the basis vectors the update uses), so the solve
+    is the same bit for bit."""
+    A = gen.powerlaw(50_000, seed=2)
+    M, P = _setup(ctx, A, 12)
+    b = dev(np.ones(A.n))
+    x0, i0, s0 = ctx.gmres(P, b, m=30, tol=1e-10, mode=mode, precond=xab.PRECOND_JACOBI)
+    monkeypatch.setenv("XAB_STEP_WAIT_MS", "0")
+    x1, i1, s1 = ctx.gmres(P, b, m=30, tol=1e-10, mode=mode, precond=xab.PRECOND_JACOBI)
+    assert s0 == s1 == 0
+    assert (i0["iters"], i0["restarts"], i0["refinements"]) == (i1["iters"], i1["restarts"], i1["refinements"])
+    assert i0["true_relres"] == i1["true_relres"] <= 1e-10
+    assert torch.equal(x0, x1)
+
+
 # ----------------------------------------------------------------- batch
 def _batch(nsys=12, nmin=300, nmax=3000):
     return gen.batch(nsys, seed=4, nmin=nmin, nmax=nmax)
