@@ -387,19 +387,31 @@ def fp32_error_per_result(y, yo, s):
 
 def gmres_pair(ctx, xab, torch, plan, n, reps=3):
     """Time-to-1e-10 of GMRES(30) with Jacobi, FP64 and mixed precision
-    (FP32 inner solve, FP64 refinement): b = 1, x0 = 0, median of `reps`."""
+    (FP32 inner solve to the default inner tolerance 1e-6, FP64
+    refinement): b = 1, x0 = 0, median of `reps`.  Also the mixed-precision
+    solve with looser inner tolerances (more refinements, fewer inner
+    steps each)."""
     b = torch.ones(n, dtype=torch.float64, device="cuda")
     res = {}
-    for mode, name in ((xab.MODE_FP64, "fp64"), (xab.MODE_IR, "ir")):
+
+    def run(mode, **kw):
         runs = []
         for _ in range(reps):
-            xs, inf, st = ctx.gmres(plan, b, m=30, tol=1e-10, mode=mode, precond=xab.PRECOND_JACOBI)
+            xs, inf, st = ctx.gmres(plan, b, m=30, tol=1e-10, mode=mode, precond=xab.PRECOND_JACOBI, **kw)
             runs.append(inf)
         runs.sort(key=lambda r: r["seconds"])
         med = runs[len(runs) // 2]
-        res[name] = {"s": round(med["seconds"], 5), "iters": med["iters"], "restarts": med["restarts"],
-                     "refinements": med["refinements"], "relres": med["true_relres"], "status": med["status"]}
+        return {"s": round(med["seconds"], 5), "iters": med["iters"], "restarts": med["restarts"],
+                "refinements": med["refinements"], "relres": med["true_relres"], "status": med["status"]}
+
+    res["fp64"] = run(xab.MODE_FP64)
+    res["ir"] = run(xab.MODE_IR)
     res["ir_speedup"] = round(res["fp64"]["s"] / res["ir"]["s"], 3)
+    res["ir_inner_tol"] = {}
+    for it in (1e-3, 1e-4):
+        r = run(xab.MODE_IR, inner_tol=it)
+        r["speedup_vs_fp64"] = round(res["fp64"]["s"] / r["s"], 3)
+        res["ir_inner_tol"][f"{it:g}"] = r
     return res
 
 
