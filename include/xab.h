@@ -244,7 +244,11 @@ int xab_plan_refresh(xab_plan *plan);
  * y nrows; they must not overlap.  Asynchronous. */
 int xab_spmv_csr(xab_ctx *ctx, const xab_plan *plan, const void *d_x, xab_dtype xt, void *d_y, xab_dtype yt,
                  xab_dtype acc);
-/* y = (L + L_strict^T) x for an XAB_SYM_LOWER matrix. Same precisions. */
+/* y = (L + L_strict^T) x for an XAB_SYM_LOWER matrix. Same precisions;
+ * XAB_SYM_S3 accumulates in FP64 also when FP32 accumulation is asked for
+ * (its tile sums take one LDS atomic add per entry, and the FP32 one runs
+ * about 20x slower than the FP64 one on gfx950), so its FP32-accumulation
+ * result is its FP64-accumulation result. */
 int xab_spmv_sym(xab_ctx *ctx, const xab_plan *plan, const void *d_x, xab_dtype xt, void *d_y, xab_dtype yt,
                  xab_dtype acc);
 

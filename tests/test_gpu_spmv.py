@@ -510,6 +510,21 @@ def test_sym_fp32(ctx, k, combo):
     assert np.all(np.abs(y - y_exact) <= bound * s)
 
 
+@pytest.mark.parametrize("name", ["st27_24", "arrow", "sym_powerlaw", "sym_powerlaw_holes"])
+@pytest.mark.parametrize("k", [10, 11])
+def test_sym_s3_fp32_accumulation_is_fp64(ctx, name, k):
+    """S3 keeps its tile sums in FP64 for either accumulation type (the FP32
+    LDS atomic add is the slow one on this chip), so asking for FP32
+    accumulation gives the FP64-accumulation bits, on both walks."""
+    A = SYM[name]
+    x32 = dev(gen.uniform_vec(A.n, 17).astype(np.float32), torch.float32)
+    M = ctx.matrix_from_csr(A, with_f32=True)
+    P = ctx.plan_class(M, k)
+    y32 = ctx.spmv(P, x32, ydtype=torch.float32, acc=xab.F32)
+    y64 = ctx.spmv(P, x32, ydtype=torch.float32, acc=xab.F64)
+    assert torch.equal(y32, y64)
+
+
 @pytest.mark.parametrize("name", ["st27_24", "banded_holes", "arrow", "sym_powerlaw", "sym_powerlaw_holes"])
 @pytest.mark.parametrize("k", [10, 11])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
