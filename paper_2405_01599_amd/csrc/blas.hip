@@ -380,8 +380,9 @@ __global__ void k_copy_cast(const double *__restrict__ s, T *__restrict__ d, int
 // instance is the smallest of 4, 8, 12, ..., 32, 40, 48, 64 that covers the
 // vectors in play: past about 28 vectors (FP32 pairs) the update-and-dots
 // sweep drops to one wave per SIMD, and the unused slots of a larger
-// instance still cost their predicated work.  Steps of 4 to 32 took C3's
-// mixed-precision GMRES from 16.6 to 15.2 ms.
+// instance still cost their predicated work.  Steps of 4 to 32 took the
+// mixed-precision GMRES(30) on the lower-stored 27-point 128^3 stencil
+// from 16.6 to 15.2 ms.
 template <class T>
 int mdot(xab_ctx *ctx, const T *V, int64_t ldv, int nv, const T *w, int64_t n, double *part, int nb,
          const int *gate) {

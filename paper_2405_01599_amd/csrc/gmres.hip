@@ -260,16 +260,17 @@ int cycle(xab_ctx *ctx, const xab_plan *pl, xab_matrix *A, Work &W, int m, doubl
     const long wait_ms = wenv && *wenv ? std::max(0L, strtol(wenv, nullptr, 10)) : 20L;
     auto wait_step = [&](int q) -> int {
         const volatile int *done = &mir->done;
-        if (*done >= q) return XAB_OK;
-        const auto t0 = std::chrono::steady_clock::now();
-        while (*done < q) {
-            if (std::chrono::steady_clock::now() - t0 >= std::chrono::milliseconds(wait_ms)) {
-                XAB_HIP(ctx, hipStreamSynchronize(ctx->stream));
-                break;
-            }
+        if (*done < q) {
+            const auto t0 = std::chrono::steady_clock::now();
+            while (*done < q) {
+                if (std::chrono::steady_clock::now() - t0 >= std::chrono::milliseconds(wait_ms)) {
+                    XAB_HIP(ctx, hipStreamSynchronize(ctx->stream));
+                    break;
+                }
 #if defined(__x86_64__)
-            __builtin_ia32_pause();
+                __builtin_ia32_pause();
 #endif
+            }
         }
         __atomic_thread_fence(__ATOMIC_ACQUIRE);  // no read of the mirror moves above the wait
         return XAB_OK;

@@ -564,7 +564,8 @@ static int launch_s3_c(xab_ctx *ctx, const xab_plan *pl, const VT *val, const XT
 // slower than the FP64 one (3.2 vs 72 G wave instructions/s with distinct
 // consecutive addresses), so the symmetric product accumulates in FP64
 // whatever accumulation type is asked for: FP32 accumulation gives the
-// FP64-accumulation result, at its speed (C3 FP32 values: 201 -> 80 us).
+// FP64-accumulation result, at its speed (27-point 128^3 stencil, FP32
+// values: 201 -> 80 us).
 template <class VT, class XT, class YT, class AT>
 int launch_sym_s3(xab_ctx *ctx, const xab_plan *pl, const VT *val, const XT *x, YT *y) {
     using LT = double;
