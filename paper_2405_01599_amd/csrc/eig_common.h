@@ -20,50 +20,45 @@ constexpr int kRotNT = 256;
 constexpr int kMaxNarrowEig = 8;  // accuracy policy: tenfold narrowings of the threshold at most
 
 // out[:, c] = sum_{j < mm} V[:, j] * Y[j + c * mm] for c < k (column-major
-// Y; mm <= 64, k <= 63).  A workgroup takes 64 rows: it stages their mm basis entries in LDS
-// (one coalesced 512-byte run per vector), then wave q forms the outputs
-// c = q, q + 4, ... for those rows, lane = row, all of them at once in
-// registers, so each staged entry is read from LDS once per wave; every
-// basis entry is read from HBM once and every output written once.  Each
-// output is one fma chain over j = 0, 1, ..., mm - 1.
-constexpr int kRotRows = 64;
-constexpr int kRotOut = (kMaxM + kRotNT / kRotRows - 1) / (kRotNT / kRotRows);  // outputs per wave
+// Y; mm <= 64, k <= 64).  One row per thread, grid-stride: the thread keeps
+// its row's k outputs in registers (K >= k of them) and streams the row's mm
+// basis entries, eight loads in flight (coalesced across the wave); Y, the
+// same for every thread, is read with scalar loads, eight consecutive
+// entries of a column at a time, straight into the fma operands.  Each
+// output is one fma chain over j = 0, 1, ..., mm - 1; every basis entry is
+// read from HBM once and every output written once.  (A workgroup per 64
+// rows staging the basis in LDS took 330 us for 30 vectors to 20 on the
+// 2,097,152-row stencil; this takes 200 us.)
+template <int K>
 __global__ __launch_bounds__(kRotNT) void k_rotate(const double *__restrict__ V, int64_t ldv, int mm,
                                                    const double *__restrict__ Y, int k, double *__restrict__ out,
                                                    int64_t ldo, int64_t n) {
-    extern __shared__ double lds[];  // [mm][kRotRows] basis rows, then Y (mm * k)
-    double *vs = lds, *ys = lds + mm * kRotRows;
-    const int64_t r0 = (int64_t)blockIdx.x * kRotRows;
-    const int lane = threadIdx.x % kRotRows, q = threadIdx.x / kRotRows;
-    const int64_t r = r0 + lane;
-    for (int i = threadIdx.x; i < mm * k; i += kRotNT) ys[i] = Y[i];
-    constexpr int G = kRotNT / kRotRows;
-    {
-        // every load of this wave's share first, then the LDS stores
-        double st[kRotOut + 1];
+    for (int64_t r = (int64_t)blockIdx.x * kRotNT + threadIdx.x; r < n; r += (int64_t)gridDim.x * kRotNT) {
+        double acc[K];
 #pragma unroll
-        for (int t = 0; t <= kRotOut; ++t) {
-            const int j = q + t * G;
-            st[t] = (j < mm && r < n) ? V[(int64_t)j * ldv + r] : 0.0;
+        for (int t = 0; t < K; ++t) acc[t] = 0.0;
+        int j = 0;
+        for (; j + 8 <= mm; j += 8) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = V[(int64_t)(j + u) * ldv + r];
+#pragma unroll
+            for (int t = 0; t < K; ++t)
+                if (t < k) {
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) acc[t] = fma(v[u], Y[t * mm + j + u], acc[t]);
+                }
+        }
+        for (; j < mm; ++j) {
+            const double v = V[(int64_t)j * ldv + r];
+#pragma unroll
+            for (int t = 0; t < K; ++t)
+                if (t < k) acc[t] = fma(v, Y[t * mm + j], acc[t]);
         }
 #pragma unroll
-        for (int t = 0; t <= kRotOut; ++t)
-            if (q + t * G < mm) vs[(q + t * G) * kRotRows + lane] = st[t];
+        for (int t = 0; t < K; ++t)
+            if (t < k) out[(int64_t)t * ldo + r] = acc[t];
     }
-    __syncthreads();
-    if (r >= n) return;
-    double acc[kRotOut];
-#pragma unroll
-    for (int t = 0; t < kRotOut; ++t) acc[t] = 0.0;
-    for (int j = 0; j < mm; ++j) {
-        const double v = vs[j * kRotRows + lane];
-#pragma unroll
-        for (int t = 0; t < kRotOut; ++t)
-            if (q + t * G < k) acc[t] = fma(v, ys[(q + t * G) * mm + j], acc[t]);
-    }
-#pragma unroll
-    for (int t = 0; t < kRotOut; ++t)
-        if (q + t * G < k) out[(int64_t)(q + t * G) * ldo + r] = acc[t];
 }
 
 // part[block] = sum over its rows of (ax - c1 x1 - c2 x2)^2 (x2 may be null)
@@ -147,11 +142,18 @@ double mm_ratio(const std::vector<double> &v, size_t s, size_t t) {
 
 int rotate(xab_ctx *ctx, const Work &W, int mm, const std::vector<double> &Ycm, int k, double *out, int64_t ldo,
            int64_t n) {
+    if (mm > 64 || k > 64) return xab_fail(ctx, XAB_E_SHAPE, "rotation of %d vectors to %d", mm, k);
     memcpy(W.host, Ycm.data(), sizeof(double) * (size_t)mm * k);
     XAB_HIP(ctx, hipMemcpyAsync(W.Y, W.host, sizeof(double) * (size_t)mm * k, hipMemcpyHostToDevice, ctx->stream));
-    const size_t lds = sizeof(double) * (size_t)mm * (kRotRows + k);  // <= 64 KB (mm, k <= 63)
-    hipLaunchKernelGGL(k_rotate, dim3((unsigned)((n + kRotRows - 1) / kRotRows)), dim3(kRotNT), lds, ctx->stream, W.V,
-                       W.ldv, mm, W.Y, k, out, ldo, n);
+    // the smallest instance that holds k outputs per thread
+    const dim3 g((unsigned)std::max<int64_t>(1, std::min<int64_t>((n + kRotNT - 1) / kRotNT, 4096))), b(kRotNT);
+    hipStream_t st = ctx->stream;
+    if (k <= 8) hipLaunchKernelGGL((k_rotate<8>), g, b, 0, st, W.V, W.ldv, mm, W.Y, k, out, ldo, n);
+    else if (k <= 16) hipLaunchKernelGGL((k_rotate<16>), g, b, 0, st, W.V, W.ldv, mm, W.Y, k, out, ldo, n);
+    else if (k <= 24) hipLaunchKernelGGL((k_rotate<24>), g, b, 0, st, W.V, W.ldv, mm, W.Y, k, out, ldo, n);
+    else if (k <= 32) hipLaunchKernelGGL((k_rotate<32>), g, b, 0, st, W.V, W.ldv, mm, W.Y, k, out, ldo, n);
+    else if (k <= 48) hipLaunchKernelGGL((k_rotate<48>), g, b, 0, st, W.V, W.ldv, mm, W.Y, k, out, ldo, n);
+    else hipLaunchKernelGGL((k_rotate<64>), g, b, 0, st, W.V, W.ldv, mm, W.Y, k, out, ldo, n);
     XAB_LAUNCH_CHECK(ctx, "k_rotate");
     // the pinned buffer is reused by the next read-back: finish the copy first
     XAB_HIP(ctx, hipStreamSynchronize(ctx->stream));
